@@ -1,0 +1,205 @@
+"""Benchmark of the correlator X-engine on one MI355X.
+
+Default workload: the LOFAR-scale correlation of Section 2 -- 64 dual-polarised
+stations, 256 channels, integrations of 768 complex-float32 samples (noise plus
+three point sources).  One step = one correlation of the whole block (every
+channel, every station pair, all four polarisation pairs) with the samples
+already resident in device memory.  Throughput is counted as 8 flops per
+complex multiply-accumulate, 32 per baseline per sample.
+
+Prints one JSON line with the headline value, the roofline position of the
+kernel, a CPU baseline (the oracle on the host cores, on a bounded sample of
+the same workload) and the other kernel paths on the 256-station int8
+workload for comparison (MFMA int8 / f16 / bf16 / f32 against the FP32
+vector-ALU form on the same values).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAKS = {  # MI355X published dense peaks
+    "hbm_GBs": 8000.0,
+    "fp32_mfma_TF": 157.3,
+    "fp16_mfma_TF": 2500.0,
+    "bf16_mfma_TF": 2500.0,
+    "int8_mfma_TOPS": 5000.0,
+    "fp32_valu_TF": 157.3,
+}
+KERNEL_SOURCES = {"mfma": "paper_1702_00844_amd/csrc/mfma.hip", "valu": "paper_1702_00844_amd/csrc/valu.hip"}
+
+
+def source_sha(kind: str) -> str:
+    with open(os.path.join(ROOT, KERNEL_SOURCES[kind]), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def load_traffic(key: str, kind: str):
+    """HBM bytes per launch from committed rocprofv3 PMC summaries, or None if
+    absent or taken on a different version of the kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        table = json.load(f)
+    ent = table.get(key)
+    if not ent or ent.get("source_sha") != source_sha(kind):
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def time_launches(fn, steps: int, warmup: int, stream):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps  # ms per launch, measured on the launch stream
+
+
+def cpu_baseline(x_host_fn, n_channels_total: int, flops_per_channel: float, budget_s: float = 12.0):
+    """Time the oracle on a bounded number of channels of the workload."""
+    import oracle
+    lib = oracle.load()
+    xs = x_host_fn(1)
+    t0 = time.perf_counter()
+    oracle.correlate_f64(xs, lib)
+    t1 = time.perf_counter() - t0
+    threads = oracle.threads()
+    # channels are independent: choose enough to keep every thread busy for ~budget_s
+    n = int(max(1, min(n_channels_total, budget_s / max(t1, 1e-3) * max(1, min(threads, 8)))))
+    n = max(n, min(threads, n_channels_total))
+    xs = x_host_fn(n)
+    t0 = time.perf_counter()
+    oracle.correlate_f64(xs, lib)
+    dt = time.perf_counter() - t0
+    return {"value": flops_per_channel * n / dt / 1e12, "unit": "TFLOP/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n} of {n_channels_total} channels of the same workload (FP64 oracle, {dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--kernel", choices=["auto", "mfma", "valu"], default="auto")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-compare", action="store_true", help="skip the other kernel paths")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this correlator build runs on one GPU; channels would shard across GPUs "
+                                   "(see the design notes) but no multi-GPU path is built"}))
+        sys.exit(2)
+
+    import torch
+    import paper_1702_00844_amd as xe
+    from paper_1702_00844_amd import inputs
+
+    dev = "cuda:0"
+    stream = torch.cuda.current_stream()
+    S, C, T = 64, 256, 768
+    x, _ = inputs.point_sources(C, T, S, seed=2, device=dev)
+    out = torch.empty(xe.vis_shape(C, S, xe.XC_OUT_CF32), dtype=torch.complex64, device=dev)
+    cfg = {"auto": None, "mfma": {"kernel": xe.XC_KERNEL_MFMA}, "valu": {"kernel": xe.XC_KERNEL_VALU}}[args.kernel]
+    resolved = xe.resolve_config((xe.XC_IN_CF32, C, T, S, 2), config=cfg)
+    kind = "mfma" if resolved["kernel"] == xe.XC_KERNEL_MFMA else "valu"
+
+    def step():
+        xe.correlate_into(x, out, config=cfg, stream=stream)
+
+    # timed region: synchronise, K steps, synchronise (one GPU: no barrier partner)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t_wall0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter() - t_wall0
+    ms_launch = e0.elapsed_time(e1) / args.steps
+    flops = xe.flops(S, C, T)
+    value = flops * args.steps / t_wall / 1e12
+    achieved = flops / (ms_launch * 1e-3) / 1e12
+    peak = PEAKS["fp32_mfma_TF"] if kind == "mfma" else PEAKS["fp32_valu_TF"]
+    traffic_key = f"{kind}_cf32_S{S}_C{C}_T{T}"
+    roofline = {"bound": "mfma" if kind == "mfma" else "alu", "achieved": round(achieved, 3), "peak": peak,
+                "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": load_traffic(traffic_key, kind),
+                "kernel": kind, "ms_per_launch": round(ms_launch, 5),
+                "algorithmic_flops_per_launch": flops}
+    res = {"metric": "visibility TFLOP/s (8 flop/CMAC) + % roofline, FP32 vs MFMA; stream p99",
+           "value": round(value, 3), "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(t_wall / args.steps * 1e3, 5), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "lofar64: 64 stations x 2 pol, 256 channels, 768 samples, complex64 "
+                                  "CN(0,1) noise + 3 point sources", "n_stations": S, "n_channels": C,
+                      "n_times": T, "kernel": resolved},
+           "roofline": roofline}
+
+    if not args.no_compare:
+        res["paths"] = compare_paths(xe, inputs, torch, dev, stream)
+
+    if not args.no_cpu_baseline:
+        def host_sample(n):
+            return x[:n].cpu().numpy()
+        res["cpu_baseline"] = cpu_baseline(host_sample, C, flops / C)
+    print(json.dumps(res), flush=True)
+
+
+def compare_paths(xe, inputs, torch, dev, stream, steps=10):
+    """Every kernel path on the 256-station, 1024-channel, 1024-sample workload
+    with complex-int8 values (exact in every input type), plus the FP32 forms
+    on the 64-station workload."""
+    out = {}
+    S, C, T = 256, 1024, 1024
+    xi = inputs.ci8_gaussian(C, T, S, seed=3, device=dev)
+    flops = xe.flops(S, C, T)
+    hbm_in = {"ci8": C * T * S * 4, "cf16": C * T * S * 8, "cbf16": C * T * S * 8, "cf32": C * T * S * 16}
+    vis_bytes = C * (S * (S + 1) // 2) * 4 * 8
+    cases = [("int8_mfma", "ci8", None, "int8_mfma_TOPS"),
+             ("f16_mfma", "cf16", None, "fp16_mfma_TF"),
+             ("bf16_mfma", "cbf16", None, "bf16_mfma_TF"),
+             ("f32_mfma", "cf32", {"kernel": xe.XC_KERNEL_MFMA}, "fp32_mfma_TF"),
+             ("f32_valu", "cf32", {"kernel": xe.XC_KERNEL_VALU}, "fp32_valu_TF")]
+    for name, kind, cfg, peak_key in cases:
+        if kind == "ci8":
+            x = xi
+        elif kind == "cf16":
+            x = xi.to(torch.float16)
+        elif kind == "cbf16":
+            x = xi.to(torch.bfloat16)
+        else:
+            x = torch.view_as_complex(xi.to(torch.float32))
+        o = torch.empty(xe.vis_shape(C, S, xe.XC_OUT_CI32 if kind == "ci8" else xe.XC_OUT_CF32),
+                        dtype=torch.int32 if kind == "ci8" else torch.complex64, device=dev)
+        ms = time_launches(lambda: xe.correlate_into(x, o, config=cfg, stream=stream), steps, 2, stream)
+        tf = flops / (ms * 1e-3) / 1e12
+        byts = hbm_in[kind] + vis_bytes
+        peak = PEAKS[peak_key]
+        out[name] = {"workload": "256 stations, 1024 channels, 1024 samples (int8 values)",
+                     "ms": round(ms, 4), "TFLOP/s": round(tf, 2), "frac_of_compute_peak": round(tf / peak, 4),
+                     "algorithmic_GB/s": round(byts / (ms * 1e-3) / 1e9, 1),
+                     "frac_of_hbm": round(byts / (ms * 1e-3) / 1e9 / PEAKS["hbm_GBs"], 4)}
+        del x, o
+    torch.cuda.empty_cache()
+    return out
+
+
+if __name__ == "__main__":
+    main()

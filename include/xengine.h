@@ -1,0 +1,320 @@
+/*
+ * xengine.h -- C ABI of the MI355X (gfx950) correlator X-engine.
+ *
+ * The library computes, for every frequency channel c, the visibilities
+ *
+ *   V[c][b(i,j)][p][q] = sum_{t=0}^{T-1} x[c][t][i][p] * conj(x[c][t][j][q])
+ *
+ * for all station pairs 0 <= i <= j < S (autocorrelations included) and all
+ * four polarisation pairs p, q in {X=0, Y=1}: the correlation equation and
+ * pseudo-code (Figure 2) of Section 2 of van Nieuwpoort & Romein, "Correlating
+ * Radio Astronomy Signals with Many-Core Hardware".  Each station pair is
+ * computed once (V(j,i) = conj V(i,j), Section 2); the conjugated factor is
+ * the higher-numbered station j.
+ *
+ * Layouts (row-major, innermost last):
+ *   samples  x[C][T][S][P] complex, time-major (all stations of one time step
+ *            together, the layout of Section 4.4).  A complex sample is
+ *              XC_IN_CF32 : {float re, im}            8 bytes
+ *              XC_IN_CF16 : {_Float16 re, im}         4 bytes
+ *              XC_IN_CBF16: {bfloat16 re, im}         4 bytes
+ *              XC_IN_CI8  : {int8 re, im}             2 bytes, values in [-127, 127]
+ *   vis      V[C][B][P][P] complex, B = S(S+1)/2, b(i,j) = j(j+1)/2 + i
+ *            (Figure 2 writes correlation[b][c][p][q]; this is the same data
+ *            with the first two axes swapped, so that a channel is contiguous).
+ *              XC_OUT_CF32: {float re, im}   (any input type)
+ *              XC_OUT_CI32: {int32 re, im}   (XC_IN_CI8 only; exact)
+ *
+ * Conventions for every call:
+ *   - Data pointers are DEVICE pointers owned by the caller; the library never
+ *     frees them.  Pointers must be 16-byte aligned.
+ *   - `stream` is a hipStream_t (NULL = the legacy default stream).  Calls
+ *     enqueue work and return before it completes.
+ *   - Argument errors are reported before anything is enqueued; HIP errors
+ *     return XC_ERR_HIP.  xc_last_error() gives a thread-local message for the
+ *     last failing call.  The library never aborts and never prints.
+ *   - Only n_pol == 2 is supported (dual-polarised stations, Section 2).
+ */
+#ifndef XENGINE_H
+#define XENGINE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum xc_status {
+    XC_OK = 0,
+    XC_ERR_INVALID_ARG = 1,    /* bad pointer, size, enum or configuration        */
+    XC_ERR_UNSUPPORTED = 2,    /* valid but not implemented (e.g. n_pol != 2)     */
+    XC_ERR_OUT_OF_MEMORY = 3,  /* a library-owned allocation failed               */
+    XC_ERR_OVERFLOW_RISK = 4,  /* int32 output could overflow for this n_times    */
+    XC_ERR_ADMISSION = 5,      /* stream does not fit the server's memory budget  */
+    XC_ERR_BACKPRESSURE = 6,   /* stream ring full: block not accepted            */
+    XC_ERR_HIP = 7,            /* a HIP runtime call failed                       */
+    XC_ERR_STATE = 8           /* call not valid in the object's current state    */
+} xc_status;
+
+typedef enum xc_in_type {
+    XC_IN_CF32 = 0,
+    XC_IN_CI8 = 1,
+    XC_IN_CF16 = 2,
+    XC_IN_CBF16 = 3
+} xc_in_type;
+
+typedef enum xc_out_type {
+    XC_OUT_CF32 = 0,
+    XC_OUT_CI32 = 1
+} xc_out_type;
+
+/* Kernel families.  AUTO lets the library choose (tuned choice if a tuning
+ * cache entry exists, else a built-in default). */
+typedef enum xc_kernel {
+    XC_KERNEL_AUTO = 0,
+    XC_KERNEL_VALU = 1,   /* FP32 vector FMA, register-tiled (XC_IN_CF32 only)      */
+    XC_KERNEL_MFMA = 2    /* matrix cores: f32, f16, bf16 or i8 by input type        */
+} xc_kernel;
+
+/* Largest integration for which XC_OUT_CI32 is exact for every input:
+ * |re|,|im| <= 2 * 127^2 * T <= 2^31 - 1  <=>  T <= 66572. */
+#define XC_CI32_MAX_TIMES 66572
+
+/* ------------------------------------------------------------------------ */
+/* Index helpers (host only, no device access).                              */
+
+/* S(S+1)/2: station pairs including autocorrelations (Section 2). -1 if S < 0. */
+int64_t xc_n_baselines(int32_t n_stations);
+
+/* b(i,j) = j(j+1)/2 + i, the dense baseline number of Figure 2's
+ * computeBaseline.  -1 unless 0 <= i <= j. */
+int64_t xc_baseline_index(int32_t i, int32_t j);
+
+/* Complex elements of one visibility array: C * B * P * P.  -1 on bad args. */
+int64_t xc_vis_elems(int32_t n_stations, int32_t n_pol, int32_t n_channels);
+
+/* Bytes of a sample block / visibility array of the given type.  -1 on bad args. */
+int64_t xc_sample_bytes(xc_in_type in_type, int32_t n_stations, int32_t n_pol,
+                        int32_t n_channels, int32_t n_times);
+int64_t xc_vis_bytes(xc_out_type out_type, int32_t n_stations, int32_t n_pol,
+                     int32_t n_channels);
+
+/* ------------------------------------------------------------------------ */
+/* Correlation (Section 2, correlation equation; Figure 2).                  */
+
+/*
+ * vis  = correlation of samples          (accumulate == 0), or
+ * vis += correlation of samples          (accumulate == 1; long integrations
+ *                                         split into sub-intervals, Section 4.5)
+ *
+ * samples: device, x[C][T][S][P] of in_type.  vis: device, V[C][B][P][P] of
+ * out_type, fully overwritten when accumulate == 0.  Errors:
+ *   XC_ERR_INVALID_ARG  null/unaligned pointer, S, C or T < 1, bad enum,
+ *                       XC_OUT_CI32 with a non-int8 input;
+ *   XC_ERR_UNSUPPORTED  n_pol != 2;
+ *   XC_ERR_OVERFLOW_RISK XC_OUT_CI32 and n_times > XC_CI32_MAX_TIMES;
+ *   XC_ERR_HIP          launch failure.
+ * If the environment variable XC_CHECK=1 is set, XC_IN_CI8 input is scanned
+ * for the value -128 first (synchronously) and rejected with
+ * XC_ERR_INVALID_ARG.
+ */
+xc_status xc_correlate(const void *samples, xc_in_type in_type, int32_t n_stations,
+                       int32_t n_pol, int32_t n_channels, int32_t n_times, void *vis,
+                       xc_out_type out_type, int32_t accumulate, void *stream);
+
+/*
+ * Kernel configuration.  Zero fields mean "default for this shape".
+ *   kernel        xc_kernel
+ *   block         stations per block of the triangle's block grid (Section 4.5
+ *                 splits large triangles into blocks).  VALU: 32.  MFMA: 32 or 64.
+ *   time_chunk    time steps staged in LDS per pipeline stage.
+ *   time_split    waves of a workgroup that share one output block, each
+ *                 integrating a different part of every time chunk; their
+ *                 partial sums are added in LDS before the single store.
+ *                 VALU: 1, 2, 4 or 8.  MFMA: 1.
+ */
+typedef struct xc_config {
+    int32_t kernel;
+    int32_t block;
+    int32_t time_chunk;
+    int32_t time_split;
+} xc_config;
+
+/* Checks a configuration against a shape without touching the device.
+ * On success, writes the resolved configuration (defaults filled in) to
+ * *resolved if it is not NULL.  Same errors as xc_correlate. */
+xc_status xc_resolve_config(const xc_config *cfg, xc_in_type in_type, xc_out_type out_type,
+                            int32_t n_stations, int32_t n_pol, int32_t n_channels,
+                            int32_t n_times, xc_config *resolved);
+
+/* xc_correlate with an explicit configuration (cfg may be NULL = AUTO). */
+xc_status xc_correlate_config(const xc_config *cfg, const void *samples, xc_in_type in_type,
+                              int32_t n_stations, int32_t n_pol, int32_t n_channels,
+                              int32_t n_times, void *vis, xc_out_type out_type,
+                              int32_t accumulate, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Cost model (Section 2, Table 1; Section 3.6 bound-and-bottleneck).        */
+
+/* For a w x h tile of station pairs: flops = 32wh, bytes = 16(w+h) (complex
+ * float dual-pol samples), minimum registers = 4(1 + min(w,h)) + 8wh floats.
+ * XC_ERR_INVALID_ARG if w or h < 1 or an output pointer is NULL. */
+xc_status xc_tile_cost(int32_t w, int32_t h, int64_t *flops, int64_t *bytes,
+                       int64_t *min_registers);
+
+/* perf_max = min(perf_peak, AI * bandwidth) (Section 3.6). */
+double xc_perf_max(double perf_peak, double arithmetic_intensity, double bandwidth);
+
+/* Global arithmetic intensity of correlating S dual-pol complex-float
+ * stations: 32 flops per baseline over 16 bytes per station = S + 1. */
+double xc_ai_global(int32_t n_stations);
+
+/* Algorithmic flops of one correlation: 8 per complex multiply-accumulate,
+ * 32 per baseline per time step = 32 * C * T * S(S+1)/2. */
+double xc_flops(int32_t n_stations, int32_t n_channels, int32_t n_times);
+
+/* ------------------------------------------------------------------------ */
+/* Batches of sub-arrays in one persistent launch.                           */
+
+typedef struct xc_subarray {
+    const void *samples;   /* device, x[C][T][S][2] of the batch's in_type  */
+    void *vis;             /* device, V[C][B][2][2] of the batch's out_type */
+    int32_t n_stations;
+    int32_t n_channels;
+    int32_t n_times;
+} xc_subarray;
+
+typedef struct xc_batch_plan xc_batch_plan;
+
+/*
+ * Builds a plan for correlating every item of `items` in one persistent
+ * launch.  The plan copies the item list and builds a device work list of
+ * (item, channel, block pair) units ordered by decreasing cost; workgroups take
+ * units from an atomic counter.  If use_graph != 0 the launch (with the reset
+ * of its counter) is captured into a hipGraph on `stream` and replayed by
+ * xc_batch_plan_run.  The plan owns its device work list and counter;
+ * xc_batch_plan_destroy frees them.  Pointers in `items` are baked into the
+ * plan: they must stay valid while the plan is used.
+ * Errors: as xc_correlate for each item; XC_ERR_OUT_OF_MEMORY.
+ */
+xc_status xc_batch_plan_create(const xc_subarray *items, int32_t n_items, int32_t n_pol,
+                               xc_in_type in_type, xc_out_type out_type, int32_t accumulate,
+                               const xc_config *cfg, int32_t use_graph, void *stream,
+                               xc_batch_plan **out);
+xc_status xc_batch_plan_run(xc_batch_plan *plan, void *stream);
+void xc_batch_plan_destroy(xc_batch_plan *plan);
+/* Number of work units (item, channel, block pair) in the plan. */
+int64_t xc_batch_plan_units(const xc_batch_plan *plan);
+
+/*
+ * Host-only work-list construction, exposed for tests: fills units[k] =
+ * {item, channel, block_i, block_j} (4 int32 each) for every work unit of the
+ * batch in the order the plan would use.  Returns the unit count (or -1 on
+ * bad args); writes at most `capacity` units.
+ */
+int64_t xc_batch_worklist(const int32_t *n_stations, const int32_t *n_channels,
+                          const int32_t *n_times, int32_t n_items, int32_t block,
+                          int32_t *units, int64_t capacity);
+
+/* ------------------------------------------------------------------------ */
+/* Auto-tuning (tile sizes must be tuned per platform, Section 2).           */
+
+/*
+ * Times every valid configuration for the shape on `stream` (synchronising),
+ * using the caller's samples/vis buffers (vis is overwritten), and writes the
+ * fastest to *best and its kernel time to *best_ms.  If cache_path is not
+ * NULL the result is stored in that JSON-lines file and xc_correlate (AUTO)
+ * uses it for the same shape in this process.
+ */
+xc_status xc_autotune(const void *samples, xc_in_type in_type, int32_t n_stations,
+                      int32_t n_pol, int32_t n_channels, int32_t n_times, void *vis,
+                      xc_out_type out_type, const char *cache_path, void *stream,
+                      xc_config *best, double *best_ms);
+
+/* Loads a tuning cache written by xc_autotune (entries for other shapes are
+ * kept).  Returns the number of entries loaded, or -1 if the file is
+ * unreadable. */
+int64_t xc_tune_cache_load(const char *cache_path);
+
+/* ------------------------------------------------------------------------ */
+/* Streaming: blocks arrive, partial integrations stay resident on device.   */
+
+typedef struct xc_stream_desc {
+    int32_t n_stations;
+    int32_t n_pol;                  /* must be 2 */
+    int32_t n_channels;
+    int32_t block_times;            /* samples per arriving block                  */
+    int32_t blocks_per_integration; /* blocks folded into one published integration */
+    int32_t blocks_per_fold;        /* k: blocks correlated per fold launch         */
+    int32_t ring_blocks;            /* device ring slots (>= 2 * blocks_per_fold)   */
+    int32_t in_type;                /* xc_in_type                                    */
+    int32_t acc_type;               /* xc_out_type of the resident accumulator       */
+    double block_period_s;          /* arrival period P; deadline = k * P            */
+} xc_stream_desc;
+
+typedef struct xc_latency_stats {
+    double p50_ms, p99_ms, max_ms;  /* block arrival -> its fold completed          */
+    double deadline_ms;             /* blocks_per_fold * block_period               */
+    double tflops;                  /* algorithmic TFLOP/s over the measured span   */
+    int64_t blocks;                 /* blocks whose latency was measured            */
+    int64_t misses;                 /* blocks whose latency exceeded the deadline   */
+    int64_t integrations;           /* integrations published                       */
+} xc_latency_stats;
+
+typedef struct xc_server xc_server;
+
+/* Creates a server with a device-memory budget (0 = 90% of the free memory
+ * of the current device). */
+xc_status xc_server_create(size_t hbm_budget_bytes, xc_server **out);
+void xc_server_destroy(xc_server *srv);
+
+/* Device bytes one stream needs: two resident accumulators (one integrating,
+ * one published) plus the ring of sample blocks.  0 on bad args. */
+size_t xc_stream_footprint(const xc_stream_desc *desc);
+
+/* Admits a stream if its footprint fits the remaining budget
+ * (XC_ERR_ADMISSION otherwise), allocates its buffers and a HIP stream. */
+xc_status xc_stream_open(xc_server *srv, const xc_stream_desc *desc, int32_t *stream_id);
+
+/* Returns the device pointer of the next free ring slot (x[C][block_times][S][2]).
+ * XC_ERR_BACKPRESSURE if every slot holds a block that is not yet folded. */
+xc_status xc_stream_acquire(xc_server *srv, int32_t stream_id, void **block_dev_ptr);
+
+/* Marks the acquired slot as filled; arrival_ns is the block's arrival time
+ * on the host clock (CLOCK_MONOTONIC ns).  Every blocks_per_fold committed
+ * blocks one fold (accumulate-mode correlation over those blocks) is
+ * enqueued; after blocks_per_integration blocks the accumulators swap and the
+ * finished integration is published. */
+xc_status xc_stream_commit(xc_server *srv, int32_t stream_id, uint64_t arrival_ns);
+
+/* Device pointer to the latest published integration (V[C][B][2][2] of
+ * acc_type) and its sequence number (-1 and NULL if none yet).  Work that
+ * reads it must be ordered after the stream's folds (xc_stream_stats
+ * synchronises them).  The buffer is reused, and overwritten, by the first
+ * fold of the integration after next, so read it before the next
+ * integration has been published. */
+xc_status xc_stream_latest(xc_server *srv, int32_t stream_id, const void **vis,
+                           int64_t *sequence);
+
+/* Waits for all enqueued folds of the stream, then fills *stats. */
+xc_status xc_stream_stats(xc_server *srv, int32_t stream_id, xc_latency_stats *stats);
+
+/* Waits for the stream's work and frees its buffers. */
+xc_status xc_stream_close(xc_server *srv, int32_t stream_id);
+
+/* Host-only helpers, exposed for tests. */
+/* q-quantile (0..1) of n values by the nearest-rank method; NaN if n == 0. */
+double xc_quantile(const double *values, int64_t n, double q);
+
+/* ------------------------------------------------------------------------ */
+const char *xc_status_string(xc_status status);
+const char *xc_last_error(void);
+/* Library version string. */
+const char *xc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* XENGINE_H */

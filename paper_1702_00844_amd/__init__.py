@@ -1,0 +1,294 @@
+"""MI355X (gfx950) correlator X-engine.
+
+Computes, per frequency channel c, the visibilities of Section 2 of
+van Nieuwpoort & Romein, "Correlating Radio Astronomy Signals with Many-Core
+Hardware":
+
+    V[c][b(i,j)][p][q] = sum_t x[c][t][i][p] * conj(x[c][t][j][q]),
+    0 <= i <= j < S,  b(i,j) = j(j+1)/2 + i,  p, q in {X, Y}.
+
+Every step runs in the HIP library ``libxengine.so`` (include/xengine.h);
+this package only marshals torch tensors (device memory and streams) into the
+C ABI.  There is no CPU path: tensors must live on the GPU and the library
+must be built.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _lib
+from ._lib import (XC_CI32_MAX_TIMES, XC_IN_CBF16, XC_IN_CF16, XC_IN_CF32, XC_IN_CI8, XC_KERNEL_AUTO,
+                   XC_KERNEL_MFMA, XC_KERNEL_VALU, XC_OUT_CF32, XC_OUT_CI32, XengineError)
+
+__all__ = ["correlate", "correlate_into", "n_baselines", "baseline_index", "tile_cost", "perf_max", "ai_global",
+           "flops", "resolve_config", "BatchPlan", "batch_worklist", "autotune", "tune_cache_load", "Server",
+           "quantile", "XengineError", "in_type_of", "vis_shape"]
+
+
+def lib():
+    return _lib.load()
+
+
+def n_baselines(n_stations: int) -> int:
+    return int(lib().xc_n_baselines(n_stations))
+
+
+def baseline_index(i: int, j: int) -> int:
+    return int(lib().xc_baseline_index(i, j))
+
+
+def tile_cost(w: int, h: int):
+    """(flops, bytes, min_registers) of a w x h tile (Table 1)."""
+    f, b, r = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    _lib.check(lib().xc_tile_cost(w, h, ctypes.byref(f), ctypes.byref(b), ctypes.byref(r)))
+    return f.value, b.value, r.value
+
+
+def perf_max(perf_peak: float, arithmetic_intensity: float, bandwidth: float) -> float:
+    return float(lib().xc_perf_max(perf_peak, arithmetic_intensity, bandwidth))
+
+
+def ai_global(n_stations: int) -> float:
+    return float(lib().xc_ai_global(n_stations))
+
+
+def flops(n_stations: int, n_channels: int, n_times: int) -> float:
+    return float(lib().xc_flops(n_stations, n_channels, n_times))
+
+
+def quantile(values, q: float) -> float:
+    arr = (ctypes.c_double * len(values))(*values)
+    return float(lib().xc_quantile(arr, len(values), q))
+
+
+def in_type_of(x: torch.Tensor):
+    """(xc_in_type, C, T, S, P) of a sample tensor."""
+    if x.dtype == torch.complex64:
+        if x.dim() != 4:
+            raise ValueError("complex64 samples must have shape [C, T, S, P]")
+        C, T, S, P = x.shape
+        return XC_IN_CF32, C, T, S, P
+    kinds = {torch.int8: XC_IN_CI8, torch.float16: XC_IN_CF16, torch.bfloat16: XC_IN_CBF16}
+    if x.dtype not in kinds:
+        raise TypeError(f"unsupported sample dtype {x.dtype}")
+    if x.dim() != 5 or x.shape[-1] != 2:
+        raise ValueError(f"{x.dtype} samples must have shape [C, T, S, P, 2] (re, im)")
+    C, T, S, P, _ = x.shape
+    return kinds[x.dtype], C, T, S, P
+
+
+def vis_shape(n_channels: int, n_stations: int, out_type: int, n_pol: int = 2):
+    B = n_stations * (n_stations + 1) // 2
+    return (n_channels, B, n_pol, n_pol) if out_type == XC_OUT_CF32 else (n_channels, B, n_pol, n_pol, 2)
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _require_device(*tensors):
+    for t in tensors:
+        if not t.is_cuda:
+            raise ValueError("the correlator runs on the GPU only: pass device tensors")
+        if not t.is_contiguous():
+            raise ValueError("tensors must be contiguous")
+
+
+def _config(config):
+    if config is None:
+        return None
+    if isinstance(config, _lib.XcConfig):
+        return config
+    return _lib.XcConfig(int(config.get("kernel", 0)), int(config.get("block", 0)),
+                         int(config.get("time_chunk", 0)), int(config.get("time_split", 0)))
+
+
+def resolve_config(x_shape_type, out_type=XC_OUT_CF32, config=None) -> dict:
+    """Resolved configuration for (in_type, C, T, S, P) without touching the GPU."""
+    in_type, C, T, S, P = x_shape_type
+    cfg = _config(config)
+    res = _lib.XcConfig()
+    _lib.check(lib().xc_resolve_config(ctypes.byref(cfg) if cfg else None, in_type, out_type, S, P, C, T,
+                                       ctypes.byref(res)))
+    return {"kernel": res.kernel, "block": res.block, "time_chunk": res.time_chunk, "time_split": res.time_split}
+
+
+def correlate_into(x: torch.Tensor, out: torch.Tensor, accumulate: bool = False, stream=None,
+                   config=None) -> torch.Tensor:
+    """out (+)= correlation of x; out dtype complex64 (XC_OUT_CF32) or int32 (XC_OUT_CI32)."""
+    in_type, C, T, S, P = in_type_of(x)
+    out_type = XC_OUT_CI32 if out.dtype == torch.int32 else XC_OUT_CF32
+    if out.dtype not in (torch.int32, torch.complex64):
+        raise TypeError("out must be complex64 or int32")
+    if tuple(out.shape) != vis_shape(C, S, out_type, P):
+        raise ValueError(f"out has shape {tuple(out.shape)}, expected {vis_shape(C, S, out_type, P)}")
+    _require_device(x, out)
+    cfg = _config(config)
+    st = lib().xc_correlate_config(ctypes.byref(cfg) if cfg else None, ctypes.c_void_p(x.data_ptr()), in_type, S, P,
+                                   C, T, ctypes.c_void_p(out.data_ptr()), out_type, 1 if accumulate else 0,
+                                   _stream_ptr(stream))
+    _lib.check(st)
+    return out
+
+
+def correlate(x: torch.Tensor, out: torch.Tensor | None = None, accumulate: bool = False, stream=None,
+              config=None, out_type: int | None = None) -> torch.Tensor:
+    """Visibilities of samples x.
+
+    x: complex64 [C, T, S, 2], or int8 / float16 / bfloat16 [C, T, S, 2, 2]
+    returns complex64 [C, B, 2, 2] (int8 input: int32 [C, B, 2, 2, 2] unless
+    out_type = XC_OUT_CF32).  The paper's correlation[b][c][p][q] order is
+    ``out.permute(1, 0, 2, 3)``.
+    """
+    in_type, C, T, S, P = in_type_of(x)
+    if out is None:
+        if out_type is None:
+            out_type = XC_OUT_CI32 if in_type == XC_IN_CI8 else XC_OUT_CF32
+        dtype = torch.int32 if out_type == XC_OUT_CI32 else torch.complex64
+        alloc = torch.zeros if accumulate else torch.empty
+        out = alloc(vis_shape(C, S, out_type, P), dtype=dtype, device=x.device)
+    return correlate_into(x, out, accumulate=accumulate, stream=stream, config=config)
+
+
+def batch_worklist(shapes, block: int):
+    """Host-side work list [(item, channel, bi, bj), ...] of a batch of
+    (n_stations, n_channels, n_times) shapes."""
+    n = len(shapes)
+    S = (ctypes.c_int32 * n)(*[s[0] for s in shapes])
+    C = (ctypes.c_int32 * n)(*[s[1] for s in shapes])
+    T = (ctypes.c_int32 * n)(*[s[2] for s in shapes])
+    count = lib().xc_batch_worklist(S, C, T, n, block, None, 0)
+    if count < 0:
+        raise ValueError("invalid batch shapes")
+    buf = (ctypes.c_int32 * (4 * count))()
+    lib().xc_batch_worklist(S, C, T, n, block, buf, count)
+    return [tuple(buf[4 * k:4 * k + 4]) for k in range(count)]
+
+
+class BatchPlan:
+    """Many sub-arrays of uneven shape correlated by one persistent launch,
+    replayed from a hipGraph when use_graph is true."""
+
+    def __init__(self, samples, outs, accumulate=False, config=None, use_graph=True, stream=None):
+        if len(samples) != len(outs) or not samples:
+            raise ValueError("need one output per sample block")
+        kinds = {in_type_of(x)[0] for x in samples}
+        if len(kinds) != 1:
+            raise ValueError("all items of a batch share one sample type")
+        self.in_type = kinds.pop()
+        self.out_type = XC_OUT_CI32 if outs[0].dtype == torch.int32 else XC_OUT_CF32
+        items = (_lib.XcSubarray * len(samples))()
+        for k, (x, o) in enumerate(zip(samples, outs)):
+            _, C, T, S, P = in_type_of(x)
+            if tuple(o.shape) != vis_shape(C, S, self.out_type, P):
+                raise ValueError(f"item {k}: output shape {tuple(o.shape)} does not match")
+            _require_device(x, o)
+            items[k] = _lib.XcSubarray(x.data_ptr(), o.data_ptr(), S, C, T)
+        self._keep = (list(samples), list(outs))
+        cfg = _config(config)
+        handle = ctypes.c_void_p()
+        _lib.check(lib().xc_batch_plan_create(items, len(samples), 2, self.in_type, self.out_type,
+                                              1 if accumulate else 0, ctypes.byref(cfg) if cfg else None,
+                                              1 if use_graph else 0, _stream_ptr(stream), ctypes.byref(handle)))
+        self._h = handle
+
+    @property
+    def units(self) -> int:
+        return int(lib().xc_batch_plan_units(self._h))
+
+    def run(self, stream=None):
+        _lib.check(lib().xc_batch_plan_run(self._h, _stream_ptr(stream)))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().xc_batch_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def autotune(x: torch.Tensor, out: torch.Tensor, cache_path: str | None = None, stream=None):
+    """Time every valid configuration for x's shape; returns (config dict, ms).
+    Later AUTO calls for the same shape use the winner."""
+    in_type, C, T, S, P = in_type_of(x)
+    out_type = XC_OUT_CI32 if out.dtype == torch.int32 else XC_OUT_CF32
+    _require_device(x, out)
+    best = _lib.XcConfig()
+    ms = ctypes.c_double()
+    _lib.check(lib().xc_autotune(ctypes.c_void_p(x.data_ptr()), in_type, S, P, C, T, ctypes.c_void_p(out.data_ptr()),
+                                 out_type, cache_path.encode() if cache_path else None, _stream_ptr(stream),
+                                 ctypes.byref(best), ctypes.byref(ms)))
+    return ({"kernel": best.kernel, "block": best.block, "time_chunk": best.time_chunk,
+             "time_split": best.time_split}, ms.value)
+
+
+def tune_cache_load(path: str) -> int:
+    return int(lib().xc_tune_cache_load(path.encode()))
+
+
+class Server:
+    """Streaming correlator: blocks arrive into a device ring, partial
+    integrations stay resident, streams are admitted by device-memory footprint."""
+
+    def __init__(self, hbm_budget_bytes: int = 0):
+        h = ctypes.c_void_p()
+        _lib.check(lib().xc_server_create(hbm_budget_bytes, ctypes.byref(h)))
+        self._h = h
+
+    @staticmethod
+    def desc(n_stations, n_channels, block_times, blocks_per_integration, blocks_per_fold=1, ring_blocks=0,
+             in_type=XC_IN_CI8, acc_type=XC_OUT_CI32, block_period_s=0.0):
+        if ring_blocks == 0:
+            ring_blocks = 2 * blocks_per_fold
+        return _lib.XcStreamDesc(n_stations, 2, n_channels, block_times, blocks_per_integration, blocks_per_fold,
+                                 ring_blocks, in_type, acc_type, block_period_s)
+
+    @staticmethod
+    def footprint(desc) -> int:
+        return int(lib().xc_stream_footprint(ctypes.byref(desc)))
+
+    def open(self, desc) -> int:
+        sid = ctypes.c_int32()
+        _lib.check(lib().xc_stream_open(self._h, ctypes.byref(desc), ctypes.byref(sid)))
+        return sid.value
+
+    def acquire(self, sid: int) -> int:
+        p = ctypes.c_void_p()
+        _lib.check(lib().xc_stream_acquire(self._h, sid, ctypes.byref(p)))
+        return p.value
+
+    def commit(self, sid: int, arrival_ns: int):
+        _lib.check(lib().xc_stream_commit(self._h, sid, arrival_ns))
+
+    def latest(self, sid: int):
+        p = ctypes.c_void_p()
+        seq = ctypes.c_int64()
+        _lib.check(lib().xc_stream_latest(self._h, sid, ctypes.byref(p), ctypes.byref(seq)))
+        return p.value, seq.value
+
+    def stats(self, sid: int) -> dict:
+        s = _lib.XcLatencyStats()
+        _lib.check(lib().xc_stream_stats(self._h, sid, ctypes.byref(s)))
+        return {k: getattr(s, k) for k, _ in _lib.XcLatencyStats._fields_}
+
+    def close_stream(self, sid: int):
+        _lib.check(lib().xc_stream_close(self._h, sid))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().xc_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

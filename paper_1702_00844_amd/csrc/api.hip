@@ -1,0 +1,332 @@
+// C ABI: argument validation, configuration resolution, dispatch, cost model.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <string>
+
+#include "common.h"
+
+namespace xc {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+xc_status set_error(xc_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+xc_status hip_error(hipError_t err, const char *what) {
+    return set_error(XC_ERR_HIP, "%s: %s (%d)", what, hipGetErrorString(err), (int)err);
+}
+
+int device_cu_count() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) return 256;
+    return n;
+}
+
+static bool valid_in(int t) { return t >= XC_IN_CF32 && t <= XC_IN_CBF16; }
+static bool valid_out(int t) { return t == XC_OUT_CF32 || t == XC_OUT_CI32; }
+
+// Time steps per LDS stage of the MFMA kernels (fixed per variant).
+static int mfma_chunk(xc_in_type t, int block) {
+    switch (t) {
+    case XC_IN_CI8: return 64;
+    case XC_IN_CF16:
+    case XC_IN_CBF16: return 32;
+    default: return 16;
+    }
+}
+
+// Tuned configurations chosen by xc_autotune for a shape (process-wide).
+struct TuneEntry {
+    TuneKey key;
+    xc_config cfg;
+};
+static std::mutex g_tune_mu;
+static TuneEntry *g_tune = nullptr;
+static int g_tune_n = 0, g_tune_cap = 0;
+
+void tune_put(const TuneKey &k, const xc_config &cfg) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (int i = 0; i < g_tune_n; ++i)
+        if (g_tune[i].key == k) {
+            g_tune[i].cfg = cfg;
+            return;
+        }
+    if (g_tune_n == g_tune_cap) {
+        int cap = g_tune_cap ? 2 * g_tune_cap : 16;
+        TuneEntry *n = static_cast<TuneEntry *>(realloc(g_tune, sizeof(TuneEntry) * cap));
+        if (!n) return;
+        g_tune = n;
+        g_tune_cap = cap;
+    }
+    g_tune[g_tune_n++] = TuneEntry{k, cfg};
+}
+
+bool tune_get(const TuneKey &k, xc_config *cfg) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (int i = 0; i < g_tune_n; ++i)
+        if (g_tune[i].key == k) {
+            *cfg = g_tune[i].cfg;
+            return true;
+        }
+    return false;
+}
+
+xc_status resolve(const xc_config *cfg_in, xc_in_type in_type, xc_out_type out_type, int32_t S, int32_t P,
+                  int32_t C, int32_t T, Plan *plan) {
+    if (!valid_in(in_type)) return set_error(XC_ERR_INVALID_ARG, "invalid in_type %d", (int)in_type);
+    if (!valid_out(out_type)) return set_error(XC_ERR_INVALID_ARG, "invalid out_type %d", (int)out_type);
+    if (P != 2) return set_error(XC_ERR_UNSUPPORTED, "n_pol = %d: only dual-polarised stations (2) are supported", P);
+    if (S < 1 || C < 1 || T < 1)
+        return set_error(XC_ERR_INVALID_ARG, "sizes must be >= 1 (S=%d C=%d T=%d)", S, C, T);
+    if (S > 32768) return set_error(XC_ERR_UNSUPPORTED, "n_stations = %d exceeds 32768", S);
+    if (out_type == XC_OUT_CI32 && in_type != XC_IN_CI8)
+        return set_error(XC_ERR_INVALID_ARG, "XC_OUT_CI32 requires XC_IN_CI8 samples");
+    if (out_type == XC_OUT_CI32 && T > XC_CI32_MAX_TIMES)
+        return set_error(XC_ERR_OVERFLOW_RISK, "n_times = %d > %d: int32 visibilities could overflow", T,
+                         XC_CI32_MAX_TIMES);
+
+    xc_config cfg = {0, 0, 0, 0};
+    if (cfg_in) cfg = *cfg_in;
+    if (cfg.kernel == XC_KERNEL_AUTO && !cfg_in) {
+        xc_config tuned;
+        if (tune_get(TuneKey{(int)in_type, (int)out_type, S, C, T}, &tuned)) cfg = tuned;
+    }
+    int kernel = cfg.kernel;
+    if (kernel == XC_KERNEL_AUTO) kernel = XC_KERNEL_MFMA;
+    if (kernel != XC_KERNEL_VALU && kernel != XC_KERNEL_MFMA)
+        return set_error(XC_ERR_INVALID_ARG, "invalid kernel %d", cfg.kernel);
+    Plan p;
+    p.kernel = kernel;
+    if (kernel == XC_KERNEL_VALU) {
+        if (in_type != XC_IN_CF32)
+            return set_error(XC_ERR_UNSUPPORTED, "the vector-ALU kernel takes complex-float32 samples only");
+        p.block = cfg.block ? cfg.block : 32;
+        p.time_chunk = cfg.time_chunk ? cfg.time_chunk : 16;
+        p.time_split = cfg.time_split ? cfg.time_split : 4;
+        if (p.block != 32) return set_error(XC_ERR_INVALID_ARG, "VALU block must be 32 (got %d)", p.block);
+        const bool ok = (p.time_chunk == 16 && (p.time_split == 1 || p.time_split == 2 || p.time_split == 4)) ||
+                        (p.time_chunk == 32 && (p.time_split == 2 || p.time_split == 4 || p.time_split == 8));
+        if (!ok)
+            return set_error(XC_ERR_INVALID_ARG, "VALU (time_chunk, time_split) = (%d, %d) not available",
+                             p.time_chunk, p.time_split);
+    } else {
+        p.block = cfg.block ? cfg.block : (in_type == XC_IN_CF32 ? 32 : 64);
+        if (p.block != 32 && p.block != 64)
+            return set_error(XC_ERR_INVALID_ARG, "MFMA block must be 32 or 64 (got %d)", p.block);
+        p.time_chunk = cfg.time_chunk ? cfg.time_chunk : mfma_chunk(in_type, p.block);
+        p.time_split = cfg.time_split ? cfg.time_split : 1;
+        if (p.time_chunk != mfma_chunk(in_type, p.block))
+            return set_error(XC_ERR_INVALID_ARG, "MFMA time_chunk for this input type and block must be %d",
+                             mfma_chunk(in_type, p.block));
+        if (p.time_split != 1) return set_error(XC_ERR_INVALID_ARG, "MFMA time_split must be 1");
+    }
+    const int64_t nb = (S + p.block - 1) / p.block;
+    const int64_t nwork = (int64_t)C * (nb * (nb + 1) / 2);
+    if (nwork > (int64_t)1 << 30)
+        return set_error(XC_ERR_UNSUPPORTED, "too many work units (%lld)", (long long)nwork);
+    *plan = p;
+    return XC_OK;
+}
+
+static int in_bytes(xc_in_type t) {
+    switch (t) {
+    case XC_IN_CF32: return 8;
+    case XC_IN_CI8: return 2;
+    default: return 4;
+    }
+}
+
+static bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+
+// -- optional scan of int8 input for -128 (XC_CHECK=1) --
+__global__ void scan_m128(const int8_t *x, size_t n, int *flag) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride)
+        if (x[i] == -128) {
+            *flag = 1;
+            return;
+        }
+}
+__global__ void zero_int(int *p) { *p = 0; }
+
+static xc_status check_int8(const void *samples, size_t n, hipStream_t stream) {
+    int *flag = nullptr;
+    hipError_t e = hipMalloc(&flag, sizeof(int));
+    if (e != hipSuccess) return hip_error(e, "hipMalloc(check flag)");
+    hipLaunchKernelGGL(zero_int, dim3(1), dim3(1), 0, stream, flag);
+    hipLaunchKernelGGL(scan_m128, dim3(1024), dim3(256), 0, stream, static_cast<const int8_t *>(samples), n, flag);
+    int h = 0;
+    e = hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    hipFree(flag);
+    if (e != hipSuccess) return hip_error(e, "XC_CHECK scan");
+    if (h) return set_error(XC_ERR_INVALID_ARG, "XC_CHECK: int8 samples contain -128 (domain is [-127, 127])");
+    return XC_OK;
+}
+
+static bool check_env() {
+    const char *v = getenv("XC_CHECK");
+    return v && v[0] == '1';
+}
+
+Job make_job(const void *samples, void *vis, int S, int C, int T, int block, int accumulate) {
+    Job j;
+    j.x = samples;
+    j.vis = vis;
+    j.S = S;
+    j.C = C;
+    j.T = T;
+    j.nb = (S + block - 1) / block;
+    j.npairs = j.nb * (j.nb + 1) / 2;
+    j.accumulate = accumulate ? 1 : 0;
+    j.tblk = T;
+    j.bstride = 0;
+    return j;
+}
+
+xc_status launch_plan(const Plan &plan, xc_in_type in_type, xc_out_type out_type, const Job &job,
+                      hipStream_t stream) {
+    hipError_t e = plan.kernel == XC_KERNEL_VALU ? launch_valu(plan, job, stream)
+                                                 : launch_mfma(plan, in_type, out_type, job, stream);
+    if (e != hipSuccess) return hip_error(e, "kernel launch");
+    return XC_OK;
+}
+
+}  // namespace xc
+
+using namespace xc;
+
+extern "C" {
+
+int64_t xc_n_baselines(int32_t n_stations) {
+    if (n_stations < 0) return -1;
+    return (int64_t)n_stations * (n_stations + 1) / 2;
+}
+
+int64_t xc_baseline_index(int32_t i, int32_t j) {
+    if (i < 0 || j < 0 || i > j) return -1;
+    return (int64_t)j * (j + 1) / 2 + i;
+}
+
+int64_t xc_vis_elems(int32_t n_stations, int32_t n_pol, int32_t n_channels) {
+    if (n_stations < 0 || n_pol < 0 || n_channels < 0) return -1;
+    return (int64_t)n_channels * xc_n_baselines(n_stations) * n_pol * n_pol;
+}
+
+int64_t xc_sample_bytes(xc_in_type in_type, int32_t n_stations, int32_t n_pol, int32_t n_channels,
+                        int32_t n_times) {
+    if (!valid_in(in_type) || n_stations < 0 || n_pol < 0 || n_channels < 0 || n_times < 0) return -1;
+    return (int64_t)n_channels * n_times * n_stations * n_pol * in_bytes(in_type);
+}
+
+int64_t xc_vis_bytes(xc_out_type out_type, int32_t n_stations, int32_t n_pol, int32_t n_channels) {
+    if (!valid_out(out_type)) return -1;
+    const int64_t n = xc_vis_elems(n_stations, n_pol, n_channels);
+    return n < 0 ? -1 : n * 8;
+}
+
+xc_status xc_resolve_config(const xc_config *cfg, xc_in_type in_type, xc_out_type out_type, int32_t n_stations,
+                            int32_t n_pol, int32_t n_channels, int32_t n_times, xc_config *resolved) {
+    Plan p;
+    xc_status st = resolve(cfg, in_type, out_type, n_stations, n_pol, n_channels, n_times, &p);
+    if (st != XC_OK) return st;
+    if (resolved) {
+        resolved->kernel = p.kernel;
+        resolved->block = p.block;
+        resolved->time_chunk = p.time_chunk;
+        resolved->time_split = p.time_split;
+    }
+    return XC_OK;
+}
+
+xc_status xc_correlate_config(const xc_config *cfg, const void *samples, xc_in_type in_type, int32_t n_stations,
+                              int32_t n_pol, int32_t n_channels, int32_t n_times, void *vis,
+                              xc_out_type out_type, int32_t accumulate, void *stream) {
+    Plan plan;
+    xc_status st = resolve(cfg, in_type, out_type, n_stations, n_pol, n_channels, n_times, &plan);
+    if (st != XC_OK) return st;
+    if (!samples || !vis) return set_error(XC_ERR_INVALID_ARG, "null samples or vis pointer");
+    if (!aligned16(samples) || !aligned16(vis))
+        return set_error(XC_ERR_INVALID_ARG, "samples and vis must be 16-byte aligned");
+    if (accumulate != 0 && accumulate != 1) return set_error(XC_ERR_INVALID_ARG, "accumulate must be 0 or 1");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (in_type == XC_IN_CI8 && check_env()) {
+        st = check_int8(samples, (size_t)xc_sample_bytes(in_type, n_stations, n_pol, n_channels, n_times), s);
+        if (st != XC_OK) return st;
+    }
+    const Job job = make_job(samples, vis, n_stations, n_channels, n_times, plan.block, accumulate);
+    return launch_plan(plan, in_type, out_type, job, s);
+}
+
+xc_status xc_correlate(const void *samples, xc_in_type in_type, int32_t n_stations, int32_t n_pol,
+                       int32_t n_channels, int32_t n_times, void *vis, xc_out_type out_type, int32_t accumulate,
+                       void *stream) {
+    return xc_correlate_config(nullptr, samples, in_type, n_stations, n_pol, n_channels, n_times, vis, out_type,
+                               accumulate, stream);
+}
+
+xc_status xc_tile_cost(int32_t w, int32_t h, int64_t *flops, int64_t *bytes, int64_t *min_registers) {
+    if (w < 1 || h < 1 || !flops || !bytes || !min_registers)
+        return set_error(XC_ERR_INVALID_ARG, "tile sizes must be >= 1 and outputs non-null");
+    // Table 1: a w x h tile correlates w stations with h stations, 4 polarisation
+    // products of 8 flops each per station pair and time step, from w + h
+    // dual-polarised complex-float samples of 16 bytes.  Registers: 8 floats of
+    // accumulators per station pair, plus the samples of one side (4 floats
+    // each) and one sample of the other side.
+    *flops = 32LL * w * h;
+    *bytes = 16LL * (w + h);
+    *min_registers = 4LL * (1 + (w < h ? w : h)) + 8LL * w * h;
+    return XC_OK;
+}
+
+double xc_perf_max(double perf_peak, double arithmetic_intensity, double bandwidth) {
+    const double mem = arithmetic_intensity * bandwidth;
+    return perf_peak < mem ? perf_peak : mem;
+}
+
+double xc_ai_global(int32_t n_stations) {
+    if (n_stations < 1) return NAN;
+    // 32 flops x S(S+1)/2 baselines over 16 bytes x S stations
+    return 32.0 * ((double)n_stations * (n_stations + 1) / 2.0) / (16.0 * n_stations);
+}
+
+double xc_flops(int32_t n_stations, int32_t n_channels, int32_t n_times) {
+    return 32.0 * n_channels * (double)n_times * ((double)n_stations * (n_stations + 1) / 2.0);
+}
+
+const char *xc_status_string(xc_status status) {
+    switch (status) {
+    case XC_OK: return "XC_OK";
+    case XC_ERR_INVALID_ARG: return "XC_ERR_INVALID_ARG";
+    case XC_ERR_UNSUPPORTED: return "XC_ERR_UNSUPPORTED";
+    case XC_ERR_OUT_OF_MEMORY: return "XC_ERR_OUT_OF_MEMORY";
+    case XC_ERR_OVERFLOW_RISK: return "XC_ERR_OVERFLOW_RISK";
+    case XC_ERR_ADMISSION: return "XC_ERR_ADMISSION";
+    case XC_ERR_BACKPRESSURE: return "XC_ERR_BACKPRESSURE";
+    case XC_ERR_HIP: return "XC_ERR_HIP";
+    case XC_ERR_STATE: return "XC_ERR_STATE";
+    }
+    return "XC_ERR_UNKNOWN";
+}
+
+const char *xc_last_error(void) { return g_last_error.c_str(); }
+
+const char *xc_version(void) { return "xengine 0.1 (gfx950)"; }
+
+}  // extern "C"

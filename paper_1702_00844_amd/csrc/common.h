@@ -1,0 +1,115 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "xengine.h"
+
+namespace xc {
+
+// Number of XCDs on MI355X.  Workgroups are dispatched to XCDs round-robin by
+// workgroup id, so kernels remap ids so that each XCD walks a contiguous range
+// of work units (all block pairs of one channel share that XCD's L2).
+constexpr int kNumXcd = 8;
+
+// One sub-array to correlate, as the device sees it.
+struct Job {
+    const void *x;     // samples x[C][T][S][2], or time-blocked (see tblk)
+    void *vis;         // visibilities V[C][B][2][2]
+    int32_t S, C, T;
+    int32_t nb;        // station blocks per side: ceil(S / block)
+    int32_t npairs;    // nb (nb + 1) / 2
+    int32_t accumulate;
+    // Time-blocked input (a run of consecutive ring slots of a stream): time t
+    // lives in block t / tblk, each block being x[C][tblk][S][2], bstride
+    // station-samples apart.  Unblocked input has tblk = T and bstride = 0.
+    int32_t tblk;
+    int64_t bstride;
+};
+
+// Index (in station-samples, i.e. units of one station's dual-pol sample) of
+// the first station of time step t of channel c.
+__host__ __device__ inline size_t row_offset(const Job &job, int c, int t) {
+    if (job.bstride == 0) return ((size_t)c * job.T + t) * job.S;
+    const int blk = t / job.tblk;
+    return (size_t)blk * job.bstride + ((size_t)c * job.tblk + (t - blk * job.tblk)) * job.S;
+}
+
+// A work unit of a batch: item, channel, block pair.
+struct Unit {
+    int32_t item, channel, bi, bj;
+};
+
+// Pair index k (column-major over the upper triangle of the block grid,
+// k = bj (bj + 1) / 2 + bi with bi <= bj) -> (bi, bj).
+__host__ __device__ inline void pair_decode(int k, int &bi, int &bj) {
+    int j = (int)((__builtin_sqrtf(8.0f * (float)k + 1.0f) - 1.0f) * 0.5f);
+    // fix rounding at either side
+    while ((j + 1) * (j + 2) / 2 <= k) ++j;
+    while (j * (j + 1) / 2 > k) --j;
+    bj = j;
+    bi = k - j * (j + 1) / 2;
+}
+
+// XCD-aware remap of a physical workgroup id to a logical work index.
+// The grid has kNumXcd * per workgroups; returns -1 for the padding ids.
+__device__ inline int xcd_remap(int phys, int nwork) {
+    const int per = (nwork + kNumXcd - 1) / kNumXcd;
+    const int logical = (phys % kNumXcd) * per + phys / kNumXcd;
+    return logical < nwork ? logical : -1;
+}
+
+inline int xcd_grid(int nwork) {
+    const int per = (nwork + kNumXcd - 1) / kNumXcd;
+    return per * kNumXcd;
+}
+
+// Resolved configuration of one launch.
+struct Plan {
+    int kernel;      // XC_KERNEL_VALU or XC_KERNEL_MFMA
+    int block;       // stations per block
+    int time_chunk;  // time steps per LDS stage
+    int time_split;  // waves sharing one output block over time
+};
+
+// Launchers (return hipSuccess or the launch error).
+hipError_t launch_valu(const Plan &plan, const Job &job, hipStream_t stream);
+hipError_t launch_mfma(const Plan &plan, xc_in_type in_type, xc_out_type out_type,
+                       const Job &job, hipStream_t stream);
+
+// Persistent batch launchers: units[0..n_units) processed by a fixed grid that
+// takes units from *counter (which must be zero at launch).
+hipError_t launch_valu_batch(const Plan &plan, const Job *jobs, const Unit *units,
+                             int n_units, int *counter, int grid, hipStream_t stream);
+hipError_t launch_mfma_batch(const Plan &plan, xc_in_type in_type, xc_out_type out_type,
+                             const Job *jobs, const Unit *units, int n_units, int *counter,
+                             int grid, hipStream_t stream);
+// Workgroups of the persistent kernel that fit on one CU at once.
+int occupancy_valu_batch(const Plan &plan);
+int occupancy_mfma_batch(const Plan &plan, xc_in_type in_type, xc_out_type out_type);
+// Resets a device counter with a one-thread kernel (graph-safe, no memset node).
+hipError_t launch_reset_counter(int *counter, hipStream_t stream);
+
+// Process-wide tuning cache (shape -> configuration chosen by xc_autotune).
+struct TuneKey {
+    int in, out, S, C, T;
+    bool operator==(const TuneKey &o) const {
+        return in == o.in && out == o.out && S == o.S && C == o.C && T == o.T;
+    }
+};
+void tune_put(const TuneKey &k, const xc_config &cfg);
+bool tune_get(const TuneKey &k, xc_config *cfg);
+
+// Device capacity helpers.
+int device_cu_count();
+
+// Status plumbing.
+xc_status set_error(xc_status st, const char *fmt, ...);
+xc_status hip_error(hipError_t err, const char *what);
+
+// Validation and plan resolution shared by the entry points.
+xc_status resolve(const xc_config *cfg, xc_in_type in_type, xc_out_type out_type, int32_t S,
+                  int32_t P, int32_t C, int32_t T, Plan *plan);
+
+}  // namespace xc

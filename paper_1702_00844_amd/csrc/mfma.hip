@@ -1,0 +1,523 @@
+// Matrix-core (MFMA) correlator kernels for gfx950.
+//
+// Per channel the correlation of Section 2 is the Hermitian product
+// V = X X^H of the (station, polarisation) x time sample matrix X.  With
+// X = Xr + i Xi it is computed on real matrix cores as two real products
+// with a doubled reduction dimension (time, re/im):
+//
+//     Re V = [Xr Xi] [Xr Xi]^T            (a_r b_r + a_i b_i)
+//     Im V = [Xr Xi] [-Xi Xr]^T           (a_i b_r - a_r b_i)
+//
+// so every lane's B fragment for the imaginary part is its real-part
+// fragment with each (re, im) pair replaced by (-im, re).  Negation is exact
+// for float types and for int8 in [-127, 127].
+//
+// Inputs and instructions:
+//   complex int8    -> v_mfma_i32_32x32x32_i8   (int32 accumulation, exact)
+//   complex f16     -> v_mfma_f32_32x32x16_f16  (f32 accumulation)
+//   complex bf16    -> v_mfma_f32_32x32x16_bf16 (f32 accumulation)
+//   complex f32     -> v_mfma_f32_32x32x2_f32   (f32 products and accumulation;
+//                      the four real products are issued separately)
+//
+// Tiling: the station triangle is split into blocks of SB stations (SB = 32
+// or 64, i.e. 2 SB rows of (station, pol)); a workgroup of four waves owns one
+// (channel, block pair bi <= bj) and each wave one SB x SB quadrant of its
+// 2SB x 2SB rows (SB/32 x SB/32 MFMA tiles of 32 x 32, real and imaginary
+// accumulators).  On a diagonal block pair the quadrant and the 32 x 32 tiles
+// that lie entirely below the diagonal are skipped, and only i <= j is stored.
+//
+// Staging: each chunk of time steps of both blocks goes through LDS,
+// double-buffered through registers (the next chunk's global loads are in
+// flight during the current chunk's MFMAs).  The int8 and 16-bit paths turn
+// the time-major samples into rows of consecutive time steps while writing
+// LDS (a corner turn in registers with byte permutes), so that each lane's
+// MFMA fragment is a single 16-byte LDS read; rows are padded by 16 bytes to
+// spread a quarter-wave's reads over all banks.  The f32 path needs no corner
+// turn: its fragments hold one time step per lane.
+#include "common.h"
+
+namespace xc {
+namespace mfma {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v16i __attribute__((ext_vector_type(16)));
+typedef float v16f __attribute__((ext_vector_type(16)));
+typedef _Float16 v8h __attribute__((ext_vector_type(8)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+enum Kind { K_I8 = 0, K_F16 = 1, K_BF16 = 2, K_F32 = 3 };
+
+// Compile-time geometry of one (kind, block size) variant.
+template <int KIND, int SB>
+struct Geo {
+    static constexpr int RB = 2 * SB;                 // rows (station, pol) per block
+    static constexpr int NS = SB / 32;                // 32x32 tiles per wave side
+    static constexpr bool TRANSPOSED = KIND != K_F32;
+    // time steps per staged chunk
+    static constexpr int KT = KIND == K_I8 ? 64 : (KIND == K_F32 ? 16 : 32);
+    // bytes of one sample (re, im)
+    static constexpr int EB = KIND == K_I8 ? 2 : (KIND == K_F32 ? 8 : 4);
+    // transposed: one row per (station, pol) of KT samples, +16 bytes pad;
+    // f32: one row per time step of both blocks' stations
+    static constexpr int PITCH = TRANSPOSED ? KT * EB + 16 : 2 * RB * 8;
+    static constexpr int STAGE_BYTES = TRANSPOSED ? 2 * RB * PITCH : KT * PITCH;
+    // staging tasks per chunk (both blocks): int8 = 4 stations x 8 steps,
+    // 16-bit = 2 stations x 4 steps, f32 = one station x one step
+    static constexpr int NTASK = KIND == K_I8 ? 2 * (SB / 4) * (KT / 8)
+                               : (KIND == K_F32 ? 2 * SB * KT : 2 * (SB / 2) * (KT / 4));
+    static constexpr int NPT = (NTASK + 255) / 256;   // tasks per thread
+    static constexpr int WORDS = KIND == K_I8 ? 32 : (KIND == K_F32 ? 4 : 16);  // dwords per task
+    static constexpr int STEP_T = KIND == K_I8 ? 16 : (KIND == K_F32 ? 2 : 8);   // time steps per MFMA
+};
+
+template <int KIND>
+struct Acc {
+    typedef v16f type;
+};
+template <>
+struct Acc<K_I8> {
+    typedef v16i type;
+};
+
+// (re, im) pairs -> (-im, re) pairs.
+__device__ __forceinline__ uint32_t conj_swap_i8(uint32_t w) {
+    // byte-wise two's-complement negation without carries between bytes
+    const uint32_t nw = ~w;
+    const uint32_t neg = ((nw & 0x7f7f7f7fu) + 0x01010101u) ^ (nw & 0x80808080u);
+    // bytes: [re0 im0 re1 im1] -> [-im0 re0 -im1 re1]
+    return __builtin_amdgcn_perm(neg, w, 0x02070005u);
+}
+__device__ __forceinline__ uint32_t conj_swap_h(uint32_t w) {
+    // halves: [re im] -> [-im re]   (sign-bit flip is exact negation)
+    const uint32_t sw = __builtin_amdgcn_perm(w, w, 0x01000302u);
+    return sw ^ 0x00008000u;
+}
+
+struct Blocks {
+    int I0, J0;     // first station of block I / J
+    bool diag;      // bi == bj: J rows are I rows, only I is staged
+};
+
+// ---------------------------------------------------------------------------
+// Global -> registers -> LDS staging.  Thread tid handles tasks tid, tid + 256...
+// Within a block, the time group is the fastest task index so that the eight
+// lanes of a group write one 128-byte row segment of LDS.
+
+template <int KIND, int SB>
+struct Pre {
+    uint32_t w[Geo<KIND, SB>::NPT][Geo<KIND, SB>::WORDS];
+};
+
+template <int KIND, int SB>
+__device__ __forceinline__ void gload(Pre<KIND, SB> &p, const Job &job, const uint8_t *__restrict__ x, int c,
+                                      const Blocks &bk, int t0, int tid) {
+    typedef Geo<KIND, SB> G;
+    const int S = job.S;
+#pragma unroll
+    for (int h = 0; h < G::NPT; ++h) {
+        const int task = tid + 256 * h;
+        if (G::NTASK % 256 != 0 && task >= G::NTASK) break;
+        if constexpr (KIND == K_I8) {
+            constexpr int NB = G::NTASK / 2;
+            const int blk = task / NB;
+            const int r = task % NB;
+            const int sg = r / (G::KT / 8);
+            const int tg = r % (G::KT / 8);
+            const int s = (blk ? bk.J0 : bk.I0) + sg * 4;
+            const bool skip = blk && bk.diag;
+            const bool vec = ((S & 3) == 0) && (s + 3 < S);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int t = t0 + tg * 8 + k;
+                const bool tok = !skip && t < job.T;
+                const uint32_t *row = reinterpret_cast<const uint32_t *>(x) + (tok ? row_offset(job, c, t) : 0);
+                if (tok && vec) {
+                    const uint4 v = *reinterpret_cast<const uint4 *>(row + s);
+                    p.w[h][4 * k + 0] = v.x; p.w[h][4 * k + 1] = v.y;
+                    p.w[h][4 * k + 2] = v.z; p.w[h][4 * k + 3] = v.w;
+                } else {
+#pragma unroll
+                    for (int d = 0; d < 4; ++d) p.w[h][4 * k + d] = (tok && s + d < S) ? row[s + d] : 0u;
+                }
+            }
+        } else if constexpr (KIND == K_F32) {
+            const int t = task / (2 * SB);
+            const int s2 = task % (2 * SB);
+            const int blk = s2 / SB;
+            const int st = (blk ? bk.J0 : bk.I0) + s2 % SB;
+            const bool ok = !(blk && bk.diag) && (t0 + t < job.T) && st < S;
+            const float4 *xs = reinterpret_cast<const float4 *>(x);
+            const float4 v = ok ? xs[row_offset(job, c, t0 + t) + st] : make_float4(0.f, 0.f, 0.f, 0.f);
+            p.w[h][0] = __float_as_uint(v.x); p.w[h][1] = __float_as_uint(v.y);
+            p.w[h][2] = __float_as_uint(v.z); p.w[h][3] = __float_as_uint(v.w);
+        } else {
+            constexpr int NB = G::NTASK / 2;
+            const int blk = task / NB;
+            const int r = task % NB;
+            const int sg = r / (G::KT / 4);
+            const int tg = r % (G::KT / 4);
+            const int s = (blk ? bk.J0 : bk.I0) + sg * 2;
+            const bool skip = blk && bk.diag;
+            const bool vec = ((S & 1) == 0) && (s + 1 < S);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int t = t0 + tg * 4 + k;
+                const bool tok = !skip && t < job.T;
+                const uint32_t *row = reinterpret_cast<const uint32_t *>(x) + (tok ? 2 * row_offset(job, c, t) : 0);
+                if (tok && vec) {
+                    const uint4 v = *reinterpret_cast<const uint4 *>(row + 2 * s);
+                    p.w[h][4 * k + 0] = v.x; p.w[h][4 * k + 1] = v.y;
+                    p.w[h][4 * k + 2] = v.z; p.w[h][4 * k + 3] = v.w;
+                } else {
+#pragma unroll
+                    for (int d = 0; d < 4; ++d)
+                        p.w[h][4 * k + d] = (tok && s + (d >> 1) < S) ? row[2 * s + d] : 0u;
+                }
+            }
+        }
+    }
+}
+
+template <int KIND, int SB>
+__device__ __forceinline__ void lstore(const Pre<KIND, SB> &p, uint8_t *lds, const Blocks &bk, int tid) {
+    typedef Geo<KIND, SB> G;
+#pragma unroll
+    for (int h = 0; h < G::NPT; ++h) {
+        const int task = tid + 256 * h;
+        if (G::NTASK % 256 != 0 && task >= G::NTASK) break;
+        if constexpr (KIND == K_I8) {
+            constexpr int NB = G::NTASK / 2;
+            const int blk = task / NB;
+            if (blk && bk.diag) continue;
+            const int r = task % NB;
+            const int sg = r / (G::KT / 8);
+            const int tg = r % (G::KT / 8);
+#pragma unroll
+            for (int d = 0; d < 4; ++d) {
+#pragma unroll
+                for (int pol = 0; pol < 2; ++pol) {
+                    // bytes of (station d, pol) at 8 consecutive steps
+                    const uint32_t sel = pol ? 0x07060302u : 0x05040100u;
+                    uint4 o;
+                    o.x = __builtin_amdgcn_perm(p.w[h][4 * 1 + d], p.w[h][4 * 0 + d], sel);
+                    o.y = __builtin_amdgcn_perm(p.w[h][4 * 3 + d], p.w[h][4 * 2 + d], sel);
+                    o.z = __builtin_amdgcn_perm(p.w[h][4 * 5 + d], p.w[h][4 * 4 + d], sel);
+                    o.w = __builtin_amdgcn_perm(p.w[h][4 * 7 + d], p.w[h][4 * 6 + d], sel);
+                    const int row = blk * G::RB + (sg * 4 + d) * 2 + pol;
+                    *reinterpret_cast<uint4 *>(lds + row * G::PITCH + tg * 16) = o;
+                }
+            }
+        } else if constexpr (KIND == K_F32) {
+            const int t = task / (2 * SB);
+            const int s2 = task % (2 * SB);
+            if (s2 >= SB && bk.diag) continue;
+            uint4 o;
+            o.x = p.w[h][0]; o.y = p.w[h][1]; o.z = p.w[h][2]; o.w = p.w[h][3];
+            *reinterpret_cast<uint4 *>(lds + t * G::PITCH + s2 * 16) = o;
+        } else {
+            constexpr int NB = G::NTASK / 2;
+            const int blk = task / NB;
+            if (blk && bk.diag) continue;
+            const int r = task % NB;
+            const int sg = r / (G::KT / 4);
+            const int tg = r % (G::KT / 4);
+#pragma unroll
+            for (int d = 0; d < 4; ++d) {   // d = 2 * station_in_pair + pol == row offset
+                uint4 o;
+                o.x = p.w[h][0 + d]; o.y = p.w[h][4 + d]; o.z = p.w[h][8 + d]; o.w = p.w[h][12 + d];
+                const int row = blk * G::RB + sg * 4 + d;
+                *reinterpret_cast<uint4 *>(lds + row * G::PITCH + tg * 16) = o;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// One chunk of MFMAs for one wave's quadrant.
+template <int KIND, int SB>
+__device__ __forceinline__ void compute_chunk(const uint8_t *lds, typename Acc<KIND>::type (&are)[SB / 32][SB / 32],
+                                              typename Acc<KIND>::type (&aim)[SB / 32][SB / 32], int arow0,
+                                              int brow0, const bool (&run)[SB / 32][SB / 32], int lane) {
+    typedef Geo<KIND, SB> G;
+    constexpr int NS = G::NS;
+    const int r32 = lane & 31;
+    const int half = lane >> 5;
+    if constexpr (KIND == K_F32) {
+#pragma unroll 2
+        for (int ks = 0; ks < G::KT / 2; ++ks) {
+            const int t = ks * 2 + half;
+            float2 a[NS], b[NS];
+#pragma unroll
+            for (int rs = 0; rs < NS; ++rs)
+                a[rs] = *reinterpret_cast<const float2 *>(lds + t * G::PITCH + (arow0 + rs * 32 + r32) * 8);
+#pragma unroll
+            for (int cs = 0; cs < NS; ++cs)
+                b[cs] = *reinterpret_cast<const float2 *>(lds + t * G::PITCH + (brow0 + cs * 32 + r32) * 8);
+#pragma unroll
+            for (int rs = 0; rs < NS; ++rs) {
+#pragma unroll
+                for (int cs = 0; cs < NS; ++cs) {
+                    if (!run[rs][cs]) continue;
+                    are[rs][cs] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[rs].x, b[cs].x, are[rs][cs], 0, 0, 0);
+                    are[rs][cs] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[rs].y, b[cs].y, are[rs][cs], 0, 0, 0);
+                    aim[rs][cs] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[rs].y, b[cs].x, aim[rs][cs], 0, 0, 0);
+                    aim[rs][cs] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[rs].x, -b[cs].y, aim[rs][cs], 0, 0, 0);
+                }
+            }
+        }
+    } else {
+        constexpr int NSTEP = G::KT / G::STEP_T;  // 4
+#pragma unroll 2
+        for (int ks = 0; ks < NSTEP; ++ks) {
+            const int koff = ks * 32 + half * 16;
+            v4i a[NS], b[NS], bi[NS];
+#pragma unroll
+            for (int rs = 0; rs < NS; ++rs)
+                a[rs] = *reinterpret_cast<const v4i *>(lds + (arow0 + rs * 32 + r32) * G::PITCH + koff);
+#pragma unroll
+            for (int cs = 0; cs < NS; ++cs) {
+                b[cs] = *reinterpret_cast<const v4i *>(lds + (brow0 + cs * 32 + r32) * G::PITCH + koff);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const uint32_t w = (uint32_t)b[cs][e];
+                    bi[cs][e] = (int)(KIND == K_I8 ? conj_swap_i8(w) : conj_swap_h(w));
+                }
+            }
+#pragma unroll
+            for (int rs = 0; rs < NS; ++rs) {
+#pragma unroll
+                for (int cs = 0; cs < NS; ++cs) {
+                    if (!run[rs][cs]) continue;
+                    if constexpr (KIND == K_I8) {
+                        are[rs][cs] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[rs], b[cs], are[rs][cs], 0, 0, 0);
+                        aim[rs][cs] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[rs], bi[cs], aim[rs][cs], 0, 0, 0);
+                    } else if constexpr (KIND == K_F16) {
+                        are[rs][cs] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
+                            __builtin_bit_cast(v8h, a[rs]), __builtin_bit_cast(v8h, b[cs]), are[rs][cs], 0, 0, 0);
+                        aim[rs][cs] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
+                            __builtin_bit_cast(v8h, a[rs]), __builtin_bit_cast(v8h, bi[cs]), aim[rs][cs], 0, 0, 0);
+                    } else {
+                        are[rs][cs] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                            __builtin_bit_cast(v8bf, a[rs]), __builtin_bit_cast(v8bf, b[cs]), are[rs][cs], 0, 0, 0);
+                        aim[rs][cs] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                            __builtin_bit_cast(v8bf, a[rs]), __builtin_bit_cast(v8bf, bi[cs]), aim[rs][cs], 0, 0, 0);
+                    }
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Output: accumulator element (lane, r) of a 32 x 32 tile is row
+// 8 (r / 4) + 4 (lane / 32) + r % 4, column lane % 32.
+template <typename OUT>
+struct Out;
+template <>
+struct Out<float2> {
+    __device__ static float2 make(float re, float im) { return make_float2(re, im); }
+    __device__ static float2 add(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+};
+template <>
+struct Out<int2> {
+    __device__ static int2 make(int re, int im) { return make_int2(re, im); }
+    __device__ static int2 add(int2 a, int2 b) { return make_int2(a.x + b.x, a.y + b.y); }
+};
+
+template <typename ACC, typename OUT>
+__device__ __forceinline__ void store_tile(const Job &job, int c, const ACC &re, const ACC &im, int row0, int col0,
+                                           int lane) {
+    // row0/col0: global (station, pol) row of the tile's first row/column
+    const int S = job.S;
+    const int col = col0 + (lane & 31);
+    const int j = col >> 1;
+    const int q = col & 1;
+    if (j >= S) return;
+    OUT *__restrict__ V = static_cast<OUT *>(job.vis) + (size_t)c * ((size_t)S * (S + 1) / 2) * 4;
+    const size_t jbase = (size_t)j * (j + 1) / 2;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int row = row0 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        const int i = row >> 1;
+        const int p = row & 1;
+        if (i > j) continue;
+        auto vr = re[r];
+        auto vi = im[r];
+        if (i == j) {
+            if (p == 1 && q == 0) continue;      // written as conj(XY) by the q = 1 lane
+            if (p == q) vi = 0;
+        }
+        OUT v = Out<OUT>::make(vr, vi);
+        const size_t e = (jbase + i) * 4 + p * 2 + q;
+        if (job.accumulate) v = Out<OUT>::add(v, V[e]);
+        V[e] = v;
+        if (i == j && p == 0 && q == 1) {       // YX = conj(XY) for autocorrelations
+            OUT w = Out<OUT>::make(vr, -vi);
+            const size_t e2 = (jbase + i) * 4 + 2;
+            if (job.accumulate) w = Out<OUT>::add(w, V[e2]);
+            V[e2] = w;
+        }
+    }
+}
+
+template <int KIND, int SB, typename OUT>
+__device__ __forceinline__ void unit(const Job &job, int c, int bi, int bj, uint8_t *lds) {
+    typedef Geo<KIND, SB> G;
+    typedef typename Acc<KIND>::type acc_t;
+    constexpr int NS = G::NS;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int wr = wave >> 1;
+    const int wc = wave & 1;
+
+    Blocks bk;
+    bk.I0 = bi * SB;
+    bk.J0 = bj * SB;
+    bk.diag = (bi == bj);
+
+    // rows of this wave's quadrant inside the staged blocks
+    const int arow0 = wr * SB;
+    const int brow0 = (bk.diag ? 0 : G::RB) + wc * SB;
+    const int S = job.S;
+    // tiles to run: skip tiles fully below the diagonal and tiles past the last station
+    bool run[NS][NS];
+    bool any = false;
+#pragma unroll
+    for (int rs = 0; rs < NS; ++rs) {
+#pragma unroll
+        for (int cs = 0; cs < NS; ++cs) {
+            const int r0 = bk.I0 * 2 + wr * SB + rs * 32;    // first global row
+            const int c0 = bk.J0 * 2 + wc * SB + cs * 32;    // first global column
+            const bool below = (r0 >> 1) > ((c0 + 31) >> 1);
+            run[rs][cs] = !below && (r0 < 2 * S) && (c0 < 2 * S);
+            any |= run[rs][cs];
+        }
+    }
+
+    acc_t are[NS][NS], aim[NS][NS];
+#pragma unroll
+    for (int rs = 0; rs < NS; ++rs)
+#pragma unroll
+        for (int cs = 0; cs < NS; ++cs) {
+            are[rs][cs] = acc_t{};
+            aim[rs][cs] = acc_t{};
+        }
+
+    const uint8_t *x = static_cast<const uint8_t *>(job.x);
+    Pre<KIND, SB> pre;
+    const int nchunk = (job.T + G::KT - 1) / G::KT;
+    gload<KIND, SB>(pre, job, x, c, bk, 0, tid);
+    lstore<KIND, SB>(pre, lds, bk, tid);
+    __syncthreads();
+    for (int ch = 0; ch < nchunk; ++ch) {
+        const int buf = ch & 1;
+        if (ch + 1 < nchunk) gload<KIND, SB>(pre, job, x, c, bk, (ch + 1) * G::KT, tid);
+        if (any) compute_chunk<KIND, SB>(lds + buf * G::STAGE_BYTES, are, aim, arow0, brow0, run, lane);
+        if (ch + 1 < nchunk) lstore<KIND, SB>(pre, lds + (buf ^ 1) * G::STAGE_BYTES, bk, tid);
+        __syncthreads();
+    }
+
+    if (!any) return;
+#pragma unroll
+    for (int rs = 0; rs < NS; ++rs)
+#pragma unroll
+        for (int cs = 0; cs < NS; ++cs)
+            if (run[rs][cs])
+                store_tile<acc_t, OUT>(job, c, are[rs][cs], aim[rs][cs], bk.I0 * 2 + wr * SB + rs * 32,
+                                       bk.J0 * 2 + wc * SB + cs * 32, lane);
+}
+
+// Two workgroups of four waves per CU: both the staging LDS (<= 72 KiB each)
+// and the registers (<= 256 per lane) are sized for it.
+template <int KIND, int SB, typename OUT>
+__global__ __launch_bounds__(256, 2) void kernel(Job job, int nwork) {
+    __shared__ __attribute__((aligned(16))) uint8_t lds[2 * Geo<KIND, SB>::STAGE_BYTES];
+    const int w = xcd_remap(blockIdx.x, nwork);
+    if (w < 0) return;
+    const int c = w / job.npairs;
+    int bi, bj;
+    pair_decode(w - c * job.npairs, bi, bj);
+    unit<KIND, SB, OUT>(job, c, bi, bj, lds);
+}
+
+template <int KIND, int SB, typename OUT>
+__global__ __launch_bounds__(256, 2) void kernel_batch(const Job *__restrict__ jobs, const Unit *__restrict__ units,
+                                                       int n_units, int *counter) {
+    __shared__ __attribute__((aligned(16))) uint8_t lds[2 * Geo<KIND, SB>::STAGE_BYTES];
+    __shared__ int next;
+    for (;;) {
+        if (threadIdx.x == 0) next = atomicAdd(counter, 1);
+        __syncthreads();
+        const int u = next;
+        __syncthreads();
+        if (u >= n_units) return;
+        const Unit un = units[u];
+        const Job job = jobs[un.item];
+        unit<KIND, SB, OUT>(job, un.channel, un.bi, un.bj, lds);
+        __syncthreads();
+    }
+}
+
+template <int KIND, int SB, typename OUT>
+hipError_t launch_t(const Job &job, hipStream_t stream) {
+    const int nwork = job.C * job.npairs;
+    hipLaunchKernelGGL((kernel<KIND, SB, OUT>), dim3(xcd_grid(nwork)), dim3(256), 0, stream, job, nwork);
+    return hipGetLastError();
+}
+template <int KIND, int SB, typename OUT>
+hipError_t launch_batch_t(const Job *jobs, const Unit *units, int n_units, int *counter, int grid,
+                          hipStream_t stream) {
+    hipLaunchKernelGGL((kernel_batch<KIND, SB, OUT>), dim3(grid), dim3(256), 0, stream, jobs, units, n_units,
+                       counter);
+    return hipGetLastError();
+}
+template <int KIND, int SB, typename OUT>
+int occupancy_t() {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel_batch<KIND, SB, OUT>, 256, 0) != hipSuccess || n < 1)
+        n = 1;
+    return n;
+}
+
+// Dispatch over (input type, output type, block size).
+#define XC_MFMA_DISPATCH(FN, ...)                                                                     \
+    switch (in_type) {                                                                                \
+    case XC_IN_CI8:                                                                                   \
+        if (out_type == XC_OUT_CI32)                                                                  \
+            return sb == 32 ? FN<K_I8, 32, int2>(__VA_ARGS__) : FN<K_I8, 64, int2>(__VA_ARGS__);      \
+        return sb == 32 ? FN<K_I8, 32, float2>(__VA_ARGS__) : FN<K_I8, 64, float2>(__VA_ARGS__);      \
+    case XC_IN_CF16:                                                                                  \
+        return sb == 32 ? FN<K_F16, 32, float2>(__VA_ARGS__) : FN<K_F16, 64, float2>(__VA_ARGS__);    \
+    case XC_IN_CBF16:                                                                                 \
+        return sb == 32 ? FN<K_BF16, 32, float2>(__VA_ARGS__) : FN<K_BF16, 64, float2>(__VA_ARGS__);  \
+    case XC_IN_CF32:                                                                                  \
+        return sb == 32 ? FN<K_F32, 32, float2>(__VA_ARGS__) : FN<K_F32, 64, float2>(__VA_ARGS__);    \
+    }
+
+}  // namespace mfma
+
+hipError_t launch_mfma(const Plan &plan, xc_in_type in_type, xc_out_type out_type, const Job &job,
+                       hipStream_t stream) {
+    using namespace mfma;
+    const int sb = plan.block;
+    XC_MFMA_DISPATCH(launch_t, job, stream)
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_mfma_batch(const Plan &plan, xc_in_type in_type, xc_out_type out_type, const Job *jobs,
+                             const Unit *units, int n_units, int *counter, int grid, hipStream_t stream) {
+    using namespace mfma;
+    const int sb = plan.block;
+    XC_MFMA_DISPATCH(launch_batch_t, jobs, units, n_units, counter, grid, stream)
+    return hipErrorInvalidValue;
+}
+
+int occupancy_mfma_batch(const Plan &plan, xc_in_type in_type, xc_out_type out_type) {
+    using namespace mfma;
+    const int sb = plan.block;
+    XC_MFMA_DISPATCH(occupancy_t)
+    return 1;
+}
+
+}  // namespace xc

@@ -1,0 +1,175 @@
+"""The C ABI on the CPU: every declared symbol is exported, host-only helpers
+match the paper's printed values, and invalid arguments are rejected before
+anything touches a device.  No GPU is needed."""
+import ctypes
+import math
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_1702_00844_amd import _lib
+import paper_1702_00844_amd as xe
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "xengine.h")
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(xc_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib.load()
+    names = declared_functions()
+    assert len(names) >= 30
+    out = subprocess.run(["nm", "-D", "--defined-only", _lib.LIBRARY], capture_output=True, text=True).stdout
+    exported = set(re.findall(r" T (xc_[a-z_0-9]+)$", out, flags=re.M))
+    missing = [n for n in names if n not in exported]
+    assert not missing, f"declared but not exported: {missing}"
+    # and the binding knows every one of them
+    assert set(names) == set(_lib.SIGNATURES), set(names) ^ set(_lib.SIGNATURES)
+    for n in names:
+        getattr(lib, n)
+
+
+def test_index_helpers():
+    assert xe.n_baselines(64) == 2080 and xe.n_baselines(256) == 32896 and xe.n_baselines(1) == 1
+    order = [(i, j) for j in range(12) for i in range(j + 1)]
+    assert [xe.baseline_index(i, j) for i, j in order] == list(range(len(order)))
+    assert xe.baseline_index(3, 2) == -1
+    lib = _lib.load()
+    assert lib.xc_vis_elems(64, 2, 256) == 256 * 2080 * 4
+    assert lib.xc_sample_bytes(_lib.XC_IN_CI8, 256, 2, 1024, 1024) == 1 << 30
+    assert lib.xc_sample_bytes(_lib.XC_IN_CF32, 64, 2, 256, 768) == 201326592
+    assert lib.xc_vis_bytes(_lib.XC_OUT_CF32, 64, 2, 256) == 17039360
+
+
+def test_table1_tile_costs():
+    """Table 1: the tile cost model reproduces every printed row."""
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "table1_tile_sizes.txt")) if l.strip() and l[0] != "#"]
+    assert len(rows) == 8
+    for tile, fl, by, ai, regs in rows:
+        w, h = map(int, tile.split("x"))
+        f, b, r = xe.tile_cost(w, h)
+        assert (f, b, r) == (int(fl), int(by), int(regs)), tile
+        assert round(f / b, 2) == float(ai), tile
+    # a 2x2 tile does the work of a 1x4 tile with fewer loads (Section 6)
+    assert xe.tile_cost(2, 2)[0] == xe.tile_cost(1, 4)[0] and xe.tile_cost(2, 2)[1] < xe.tile_cost(1, 4)[1]
+    with pytest.raises(xe.XengineError):
+        xe.tile_cost(0, 3)
+
+
+def test_perf_max_examples():
+    rows = [l.split(None, 6) for l in open(os.path.join(GOLDEN, "perf_max.txt")) if l.strip() and l[0] != "#"]
+    assert len(rows) == 5
+    for kind, peak, ai, bw, expect, tol, _ in rows:
+        got = xe.perf_max(float(peak), float(ai), float(bw))
+        assert abs(got - float(expect)) <= float(tol) + 0.01 * float(expect) * 0, (kind, peak, ai, bw, got)
+    assert xe.ai_global(64) == 65.0
+    assert xe.flops(64, 256, 768) == 32 * 256 * 768 * 2080
+
+
+VP = ctypes.c_void_p
+
+
+def call_correlate(**kw):
+    args = dict(samples=VP(16), in_type=0, S=8, P=2, C=4, T=16, vis=VP(32), out_type=0, acc=0)
+    args.update(kw)
+    lib = _lib.load()
+    return lib.xc_correlate(args["samples"], args["in_type"], args["S"], args["P"], args["C"], args["T"],
+                            args["vis"], args["out_type"], args["acc"], None)
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(P=1), 2), (dict(P=3), 2),
+    (dict(S=0), 1), (dict(C=0), 1), (dict(T=0), 1), (dict(S=-4), 1),
+    (dict(in_type=7), 1), (dict(out_type=5), 1),
+    (dict(out_type=1), 1),                         # CI32 output needs int8 input
+    (dict(in_type=1, out_type=1, T=66573), 4),     # int32 overflow risk
+    (dict(samples=VP(0)), 1), (dict(vis=VP(0)), 1),
+    (dict(samples=VP(8)), 1), (dict(vis=VP(4)), 1),  # not 16-byte aligned
+    (dict(acc=2), 1),
+])
+def test_invalid_arguments_rejected_before_launch(kw, status):
+    assert call_correlate(**kw) == status
+    assert _lib.load().xc_last_error()
+
+
+def test_int32_bound_is_exact():
+    lib = _lib.load()
+    res = _lib.XcConfig()
+    assert lib.xc_resolve_config(None, 1, 1, 16, 2, 4, 66572, ctypes.byref(res)) == 0
+    assert lib.xc_resolve_config(None, 1, 1, 16, 2, 4, 66573, ctypes.byref(res)) == 4
+    # 2 * 127^2 * 66572 fits in int32; one more sample does not
+    assert 2 * 127 * 127 * 66572 <= 2 ** 31 - 1 < 2 * 127 * 127 * 66573
+
+
+def test_config_resolution():
+    shp = (_lib.XC_IN_CF32, 256, 768, 64, 2)
+    r = xe.resolve_config(shp, config={"kernel": _lib.XC_KERNEL_VALU})
+    assert r == {"kernel": 1, "block": 32, "time_chunk": 16, "time_split": 4}
+    r = xe.resolve_config(shp, config={"kernel": _lib.XC_KERNEL_MFMA})
+    assert r["kernel"] == 2 and r["block"] == 64
+    with pytest.raises(xe.XengineError):
+        xe.resolve_config((_lib.XC_IN_CI8, 4, 16, 8, 2), config={"kernel": _lib.XC_KERNEL_VALU})
+    with pytest.raises(xe.XengineError):
+        xe.resolve_config(shp, config={"kernel": _lib.XC_KERNEL_VALU, "time_split": 3})
+
+
+def test_status_strings():
+    lib = _lib.load()
+    for code, name in _lib.STATUS_NAMES.items():
+        assert lib.xc_status_string(code).decode() == name
+    assert b"gfx950" in lib.xc_version()
+
+
+def test_quantile_nearest_rank():
+    vals = [5.0, 1.0, 3.0, 2.0, 4.0]
+    assert xe.quantile(vals, 0.5) == 3.0
+    assert xe.quantile(vals, 0.99) == 5.0
+    assert xe.quantile(vals, 0.0) == 1.0
+    assert xe.quantile(list(range(1, 101)), 0.99) == 99
+    assert math.isnan(_lib.load().xc_quantile(None, 0, 0.5))
+
+
+def test_batch_worklist_covers_every_unit_once():
+    shapes = [(24, 3, 768), (130, 2, 1024), (64, 5, 512), (1, 2, 10)]
+    for block in (32, 64):
+        units = xe.batch_worklist(shapes, block)
+        expect = set()
+        for it, (S, C, T) in enumerate(shapes):
+            nb = -(-S // block)
+            for c in range(C):
+                for bj in range(nb):
+                    for bi in range(bj + 1):
+                        expect.add((it, c, bi, bj))
+        assert len(units) == len(expect) and set(units) == expect
+        # longest integrations first
+        Ts = [shapes[u[0]][2] for u in units]
+        assert Ts == sorted(Ts, reverse=True)
+
+
+def test_stream_footprint_and_validation():
+    lib = _lib.load()
+    d = xe.Server.desc(512, 4096, 256, 192, blocks_per_fold=5, ring_blocks=10)
+    B = 512 * 513 // 2
+    acc = 4096 * B * 4 * 8
+    block = 4096 * 256 * 512 * 2 * 2
+    assert xe.Server.footprint(d) == 2 * acc + 10 * block
+    # budget-limited admission, checked with a server whose budget is given
+    h = ctypes.c_void_p()
+    assert lib.xc_server_create(1000, ctypes.byref(h)) == 0
+    sid = ctypes.c_int32()
+    small = xe.Server.desc(4, 2, 16, 4, blocks_per_fold=2, ring_blocks=4)
+    assert xe.Server.footprint(small) > 1000
+    assert lib.xc_stream_open(h, ctypes.byref(small), ctypes.byref(sid)) == 5      # XC_ERR_ADMISSION
+    bad = xe.Server.desc(4, 2, 16, 5, blocks_per_fold=2, ring_blocks=4)          # 5 % 2 != 0
+    assert lib.xc_stream_open(h, ctypes.byref(bad), ctypes.byref(sid)) == 1
+    over = xe.Server.desc(4, 2, 256, 261, blocks_per_fold=1, ring_blocks=2)      # 66816 samples > int32 bound
+    assert lib.xc_stream_open(h, ctypes.byref(over), ctypes.byref(sid)) == 4
+    lib.xc_server_destroy(h)

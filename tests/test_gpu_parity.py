@@ -1,0 +1,214 @@
+"""GPU parity: the HIP kernels against the oracle, element by element.
+
+Bars: complex-int8 -> int32 bit-exact; complex-float32 inputs within 1e-5
+normwise; 16-bit float inputs: accumulation error against the oracle on the
+same (rounded) samples within 1e-5 normwise, total error against the oracle on
+the unrounded samples within the per-element rounding bound (and 2e-3
+normwise on a workload-sized block), and exact on integer-valued samples whose
+partial sums stay below 2^24."""
+import numpy as np
+import pytest
+import torch
+
+import paper_1702_00844_amd as xe
+from paper_1702_00844_amd import inputs
+from tests.helpers import assert_hermitian_autos, gpu_vis_numpy, oracle_vis, rel_err
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+FP32_TOL = 1e-5
+
+VALU = [dict(kernel=xe.XC_KERNEL_VALU, time_chunk=tc, time_split=ts)
+        for tc, ts in [(16, 1), (16, 2), (16, 4), (32, 2), (32, 4)]]
+MFMA = dict(kernel=xe.XC_KERNEL_MFMA)
+
+# (S, C, T): tiny, ragged station counts across block edges, ragged time tails
+SHAPES = [(1, 2, 1), (3, 1, 5), (8, 3, 17), (33, 2, 100), (64, 2, 64), (70, 1, 300), (130, 1, 77)]
+
+
+def _cf32(S, C, T, seed):
+    return inputs.cn_gaussian(C, T, S, seed=seed, device=DEV)
+
+
+@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "S%d_C%d_T%d" % s)
+@pytest.mark.parametrize("cfg", VALU + [MFMA], ids=lambda c: "valu_tc%d_ts%d" % (c["time_chunk"], c["time_split"])
+                         if c["kernel"] == xe.XC_KERNEL_VALU else "mfma")
+def test_cf32_parity(shape, cfg):
+    S, C, T = shape
+    x = _cf32(S, C, T, seed=S * 1000 + T)
+    v = xe.correlate(x, config=cfg)
+    torch.cuda.synchronize()
+    got, ref = gpu_vis_numpy(v), oracle_vis(x)
+    assert rel_err(got, ref) <= FP32_TOL, rel_err(got, ref)
+    assert_hermitian_autos(got, S)
+
+
+@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "S%d_C%d_T%d" % s)
+@pytest.mark.parametrize("out_type", [xe.XC_OUT_CI32, xe.XC_OUT_CF32], ids=["ci32", "cf32"])
+def test_ci8_bit_exact(shape, out_type):
+    S, C, T = shape
+    x = inputs.ci8_gaussian(C, T, S, seed=S + 7 * T, device=DEV)
+    v = xe.correlate(x, out_type=out_type)
+    torch.cuda.synchronize()
+    ref = oracle_vis(x)
+    got = gpu_vis_numpy(v)
+    if out_type == xe.XC_OUT_CI32:
+        assert np.array_equal(got, ref)
+    else:  # int32 sums converted to float: exact below 2^24
+        assert np.array_equal(got, ref[..., 0] + 1j * ref[..., 1])
+
+
+# unit roundoff and half the smallest subnormal spacing of the 16-bit formats
+HALF_U = {torch.float16: 2.0 ** -11, torch.bfloat16: 2.0 ** -8}
+HALF_ETA = {torch.float16: 2.0 ** -25, torch.bfloat16: 2.0 ** -134}
+
+
+def _half_bound(xf, dtype):
+    """Per-element bound on |V(rounded samples) - V(exact samples)|: rounding
+    each complex component to a 16-bit format moves a sample a by at most
+    u |a| + eta, so each product a conj(b) moves by at most
+    (2u + u^2) |a||b| + eta (|a| + |b|) (1 + u), summed over time; plus the
+    FP32 accumulation, at most T 2^-24 of the magnitude sum."""
+    x = xf.detach().cpu().numpy().astype(np.complex128)
+    mag = np.abs(x)
+    T = x.shape[1]
+    vabs = oracle_vis(torch.from_numpy(mag.astype(np.complex128)).to(torch.complex64)).real
+    u, eta = HALF_U[dtype], HALF_ETA[dtype]
+    s = mag.sum(axis=1)                                  # [C, S, P]
+    C, S, P = s.shape
+    lin = np.zeros_like(vabs)
+    for j in range(S):
+        for i in range(j + 1):
+            b = j * (j + 1) // 2 + i
+            lin[:, b] = s[:, i, :, None] + s[:, j, None, :]
+    return (2 * u + u * u + T * 2.0 ** -24) * vabs * 1.001 + eta * (1 + u) * lin * 1.001
+
+
+@pytest.mark.parametrize("dtype", [torch.float16, torch.bfloat16], ids=["f16", "bf16"])
+@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "S%d_C%d_T%d" % s)
+def test_half_parity(shape, dtype):
+    S, C, T = shape
+    xf = _cf32(S, C, T, seed=S * 31 + T)
+    xh = torch.view_as_real(xf).to(dtype).contiguous()
+    v = xe.correlate(xh)
+    torch.cuda.synchronize()
+    got = gpu_vis_numpy(v)
+    acc_err = rel_err(got, oracle_vis(xh))          # same rounded samples: accumulation only
+    assert acc_err <= FP32_TOL, acc_err
+    err = np.abs(got - oracle_vis(xf))              # unrounded samples: quantisation + accumulation
+    assert np.all(err <= _half_bound(xf, dtype)), float((err / _half_bound(xf, dtype)).max())
+    assert_hermitian_autos(got, S)
+
+
+@pytest.mark.parametrize("dtype", [torch.float16, torch.bfloat16], ids=["f16", "bf16"])
+def test_half_normwise_on_workload_shape(dtype):
+    """64 stations, 768 samples of CN(0,1) noise (16 of the 256 channels):
+    total error against the FP64 oracle on the unrounded samples <= 2e-3."""
+    xf = _cf32(64, 16, 768, seed=2)
+    xh = torch.view_as_real(xf).to(dtype).contiguous()
+    got = gpu_vis_numpy(xe.correlate(xh))
+    tot = rel_err(got, oracle_vis(xf))
+    assert tot <= 2e-3, tot
+
+
+@pytest.mark.parametrize("dtype", [torch.float16, torch.bfloat16], ids=["f16", "bf16"])
+def test_half_exact_on_integer_samples(dtype):
+    S, C, T = 70, 2, 200
+    xi = inputs.ci8_gaussian(C, T, S, seed=5, device=DEV)
+    xh = xi.to(dtype)                                # |v| <= 127: exact in f16 and bf16
+    v = xe.correlate(xh)
+    torch.cuda.synchronize()
+    ref = oracle_vis(xi)
+    assert np.abs(ref).max() < 2 ** 24
+    assert np.array_equal(gpu_vis_numpy(v), ref[..., 0] + 1j * ref[..., 1])
+
+
+@pytest.mark.parametrize("cfg", [VALU[2], MFMA], ids=["valu", "mfma"])
+def test_accumulate_mode(cfg):
+    S, C, T = 40, 3, 96
+    x1 = _cf32(S, C, T, seed=11)
+    x2 = _cf32(S, C, T, seed=12)
+    v = xe.correlate(x1, config=cfg)
+    xe.correlate(x2, out=v, accumulate=True, config=cfg)
+    torch.cuda.synchronize()
+    ref = oracle_vis(torch.cat([x1, x2], dim=1))     # additivity over time
+    assert rel_err(gpu_vis_numpy(v), ref) <= FP32_TOL
+
+
+def test_accumulate_int_exact():
+    S, C, T = 66, 2, 128
+    x1 = inputs.ci8_gaussian(C, T, S, seed=21, device=DEV)
+    x2 = inputs.ci8_gaussian(C, T, S, seed=22, device=DEV)
+    v = xe.correlate(x1)
+    xe.correlate(x2, out=v, accumulate=True)
+    torch.cuda.synchronize()
+    assert np.array_equal(gpu_vis_numpy(v), oracle_vis(torch.cat([x1, x2], dim=1)))
+
+
+def test_int32_worst_case():
+    """All samples (127, -127): V = 2 * 127^2 * T exactly, at a ragged T."""
+    S, C, T = 9, 1, 1000
+    x = torch.empty((C, T, S, 2, 2), dtype=torch.int8, device=DEV)
+    x[..., 0] = 127
+    x[..., 1] = -127
+    v = xe.correlate(x)
+    torch.cuda.synchronize()
+    got = gpu_vis_numpy(v)
+    assert np.all(got[..., 0] == 2 * 127 * 127 * T) and np.all(got[..., 1] == 0)
+
+
+def test_delta_conjugation_and_numbering():
+    S, C, T = 70, 2, 40
+    i, j, p, q, t0, c = 5, 66, 0, 1, 33, 1
+    x = torch.zeros((C, T, S, 2), dtype=torch.complex64, device=DEV)
+    x[c, t0, i, p] = 1
+    x[c, t0, j, q] = 1j
+    for cfg in VALU[2:3] + [MFMA]:
+        v = gpu_vis_numpy(xe.correlate(x, config=cfg))
+        expect = np.zeros_like(v)
+        expect[c, xe.baseline_index(i, j), p, q] = -1j
+        expect[c, xe.baseline_index(i, i), p, p] = 1
+        expect[c, xe.baseline_index(j, j), q, q] = 1
+        assert np.array_equal(v, expect)
+
+
+def test_config1_full():
+    """8 stations, 16 channels, 256 samples, CN(0,1): every output."""
+    x = inputs.cn_gaussian(16, 256, 8, seed=1, device=DEV)
+    ref = oracle_vis(x)
+    for cfg in VALU + [MFMA]:
+        assert rel_err(gpu_vis_numpy(xe.correlate(x, config=cfg)), ref) <= FP32_TOL
+
+
+def test_config2_full():
+    """64 stations, 256 channels, 768 samples, noise plus three point sources:
+    every output, both FP32 kernels, in the configurations the benchmark times."""
+    x, _ = inputs.point_sources(256, 768, 64, seed=2, device=DEV)
+    ref = oracle_vis(x)
+    for cfg in [VALU[2], MFMA, None]:
+        got = gpu_vis_numpy(xe.correlate(x, config=cfg))
+        assert rel_err(got, ref) <= FP32_TOL
+        assert_hermitian_autos(got, 64)
+
+
+def test_config3_sampled_channels():
+    """256 stations, 1024 channels, 1024 samples of complex int8: int8 MFMA is
+    bit-exact, the same values as f16/bf16 are exact, and the FP32 twin is
+    within 1e-5, on sampled channels (first, last, and two inside)."""
+    C, T, S = 1024, 1024, 256
+    x = inputs.ci8_gaussian(C, T, S, seed=3, device=DEV)
+    chans = [0, 1, 517, C - 1]
+    ref = oracle_vis(x, chans)
+    v = xe.correlate(x)
+    assert np.array_equal(gpu_vis_numpy(v, chans), ref)
+    del v
+    refc = ref[..., 0] + 1j * ref[..., 1]
+    for dtype in (torch.float16, torch.bfloat16):
+        vh = xe.correlate(x.to(dtype))
+        assert np.array_equal(gpu_vis_numpy(vh, chans), refc)
+        del vh
+    xf = torch.view_as_complex(x.to(torch.float32))
+    for cfg in [VALU[2], MFMA]:
+        vf = xe.correlate(xf, config=cfg)
+        assert rel_err(gpu_vis_numpy(vf, chans), refc) <= FP32_TOL
+        del vf
