@@ -234,6 +234,22 @@ def tune_cache_load(path: str) -> int:
     return int(lib().xc_tune_cache_load(path.encode()))
 
 
+class _DevicePointer:
+    """Exposes a raw device allocation of the library to torch (no copy)."""
+
+    def __init__(self, ptr: int, shape, typestr: str):
+        self.__cuda_array_interface__ = {"shape": tuple(shape), "typestr": typestr, "data": (ptr, False),
+                                         "version": 2, "strides": None}
+
+
+def device_tensor(ptr: int, shape, dtype: torch.dtype, device="cuda") -> torch.Tensor:
+    """A torch view of library-owned device memory (stream ring slots, resident
+    integrations); the memory stays owned by the library."""
+    typestr = {torch.int8: "|i1", torch.int32: "<i4", torch.float32: "<f4", torch.float16: "<f2",
+               torch.complex64: "<c8"}[dtype]
+    return torch.as_tensor(_DevicePointer(ptr, shape, typestr), device=device)
+
+
 class Server:
     """Streaming correlator: blocks arrive into a device ring, partial
     integrations stay resident, streams are admitted by device-memory footprint."""

@@ -1,0 +1,182 @@
+"""GPU tests of the batch plans (one persistent launch, hipGraph replay), the
+auto-tuner and the streaming server, against the oracle."""
+import ctypes
+import os
+import time
+
+import numpy as np
+import pytest
+import torch
+
+import paper_1702_00844_amd as xe
+from paper_1702_00844_amd import _lib, inputs
+from tests.helpers import gpu_vis_numpy, oracle_vis, rel_err
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+SHAPES = [(24, 5, 768), (70, 3, 300), (130, 2, 128), (8, 16, 256), (1, 4, 33), (65, 1, 1000)]
+
+
+def _make(kind, shapes, seed=40):
+    xs = []
+    for k, (S, C, T) in enumerate(shapes):
+        if kind == "ci8":
+            xs.append(inputs.ci8_gaussian(C, T, S, seed=seed + k, device=DEV))
+        elif kind == "cf32":
+            xs.append(inputs.cn_gaussian(C, T, S, seed=seed + k, device=DEV))
+        else:
+            dt = torch.float16 if kind == "cf16" else torch.bfloat16
+            xs.append(inputs.ci8_gaussian(C, T, S, seed=seed + k, device=DEV).to(dt))
+    return xs
+
+
+def _check(kind, xs, outs, base=None):
+    for k, (x, o) in enumerate(zip(xs, outs)):
+        src = x.to(torch.int8) if kind in ("cf16", "cbf16") else x
+        ref = oracle_vis(src)
+        if base is not None:
+            ref = ref + base[k]
+        got = gpu_vis_numpy(o)
+        if kind == "ci8":
+            assert np.array_equal(got, ref), k
+        elif kind in ("cf16", "cbf16"):
+            assert np.array_equal(got, ref[..., 0] + 1j * ref[..., 1]), k
+        else:
+            assert rel_err(got, ref) <= 1e-5, k
+
+
+@pytest.mark.parametrize("kind,config", [
+    ("ci8", None), ("cf16", None), ("cbf16", None),
+    ("cf32", {"kernel": xe.XC_KERNEL_MFMA}), ("cf32", {"kernel": xe.XC_KERNEL_MFMA, "block": 64}),
+    ("cf32", {"kernel": xe.XC_KERNEL_VALU, "time_chunk": 32, "time_split": 8}),
+    ("cf32", {"kernel": xe.XC_KERNEL_VALU, "time_chunk": 16, "time_split": 1}),
+], ids=["ci8", "cf16", "cbf16", "f32mfma32", "f32mfma64", "valu_ts8", "valu_ts1"])
+@pytest.mark.parametrize("use_graph", [True, False], ids=["graph", "direct"])
+def test_batch_matches_oracle(kind, config, use_graph):
+    xs = _make(kind, SHAPES)
+    out_dtype = torch.int32 if kind == "ci8" else torch.complex64
+    ot = xe.XC_OUT_CI32 if kind == "ci8" else xe.XC_OUT_CF32
+    outs = [torch.full(xe.vis_shape(s[1], s[0], ot), 7, dtype=out_dtype, device=DEV) for s in SHAPES]
+    plan = xe.BatchPlan(xs, outs, config=config, use_graph=use_graph)
+    assert plan.units == len(xe.batch_worklist(SHAPES, xe.resolve_config(
+        (xe.in_type_of(xs[0])[0], 1, 1, 1, 2), ot, config)["block"]))
+    for rep in range(3):
+        for o in outs:
+            o.fill_(3)                       # eager work between replays
+        torch.cuda.synchronize()
+        plan.run()
+        torch.cuda.synchronize()
+        _check(kind, xs, outs)
+    plan.close()
+
+
+def test_batch_accumulate():
+    xs = _make("ci8", SHAPES, seed=90)
+    base = [torch.randint(-1000, 1000, xe.vis_shape(s[1], s[0], xe.XC_OUT_CI32), dtype=torch.int32, device=DEV)
+            for s in SHAPES]
+    outs = [b.clone() for b in base]
+    plan = xe.BatchPlan(xs, outs, accumulate=True, use_graph=True)
+    plan.run()
+    torch.cuda.synchronize()
+    _check("ci8", xs, outs, base=[b.cpu().numpy().astype(np.int64) for b in base])
+
+
+def test_batch_rejects_mixed_types():
+    xs = [inputs.ci8_gaussian(2, 16, 8, seed=1, device=DEV), inputs.cn_gaussian(2, 16, 8, seed=1, device=DEV)]
+    outs = [torch.empty(xe.vis_shape(2, 8, 1), dtype=torch.int32, device=DEV),
+            torch.empty(xe.vis_shape(2, 8, 0), dtype=torch.complex64, device=DEV)]
+    with pytest.raises(ValueError):
+        xe.BatchPlan(xs, outs)
+
+
+def test_autotune_and_cache(tmp_path):
+    S, C, T = 48, 8, 256
+    x = inputs.cn_gaussian(C, T, S, seed=77, device=DEV)
+    out = torch.empty(xe.vis_shape(C, S, 0), dtype=torch.complex64, device=DEV)
+    path = str(tmp_path / "tune.jsonl")
+    best, ms = xe.autotune(x, out, cache_path=path)
+    assert ms > 0 and best["kernel"] in (xe.XC_KERNEL_VALU, xe.XC_KERNEL_MFMA)
+    assert os.path.exists(path) and xe.tune_cache_load(path) == 1
+    v = xe.correlate(x)                      # AUTO now uses the tuned choice
+    torch.cuda.synchronize()
+    assert rel_err(gpu_vis_numpy(v), oracle_vis(x)) <= 1e-5
+
+
+@pytest.mark.parametrize("kind", ["ci8", "cf32"])
+def test_stream_integrations_match_oracle(kind):
+    S, C, bt, bpi, k = 20, 3, 32, 6, 2
+    n_int = 2
+    srv = xe.Server()
+    in_type = xe.XC_IN_CI8 if kind == "ci8" else xe.XC_IN_CF32
+    acc = xe.XC_OUT_CI32 if kind == "ci8" else xe.XC_OUT_CF32
+    d = xe.Server.desc(S, C, bt, bpi, blocks_per_fold=k, ring_blocks=4, in_type=in_type, acc_type=acc,
+                       block_period_s=0.001)
+    sid = srv.open(d)
+    blocks = []
+    for b in range(bpi * n_int):
+        blk = (inputs.ci8_gaussian(C, bt, S, seed=500 + b, device=DEV) if kind == "ci8"
+               else inputs.cn_gaussian(C, bt, S, seed=500 + b, device=DEV))
+        blocks.append(blk)
+        while True:
+            try:
+                ptr = srv.acquire(sid)
+                break
+            except xe.XengineError as e:
+                assert e.status_name == "XC_ERR_BACKPRESSURE"
+                time.sleep(0.001)
+        if kind == "ci8":
+            slot = xe.device_tensor(ptr, (C, bt, S, 2, 2), torch.int8)
+            slot.copy_(blk)
+        else:
+            slot = xe.device_tensor(ptr, (C, bt, S, 2 * 2), torch.float32)
+            slot.copy_(torch.view_as_real(blk).reshape(C, bt, S, 4))
+        torch.cuda.synchronize()
+        srv.commit(sid, time.monotonic_ns())
+        if (b + 1) % bpi == 0:
+            st = srv.stats(sid)                 # waits for the folds
+            vptr, seq = srv.latest(sid)
+            assert seq == (b + 1) // bpi - 1
+            shape = xe.vis_shape(C, S, acc)
+            got = xe.device_tensor(vptr, shape, torch.int32 if kind == "ci8" else torch.complex64)
+            ref = oracle_vis(torch.cat(blocks[b + 1 - bpi:b + 1], dim=1))
+            if kind == "ci8":
+                assert np.array_equal(gpu_vis_numpy(got), ref)
+            else:
+                assert rel_err(gpu_vis_numpy(got), ref) <= 1e-5
+    st = srv.stats(sid)
+    assert st["blocks"] == bpi * n_int and st["integrations"] == n_int
+    assert 0 <= st["p50_ms"] <= st["p99_ms"] <= st["max_ms"]
+    assert st["deadline_ms"] == pytest.approx(2.0)
+    srv.close_stream(sid)
+    srv.close()
+
+
+def test_stream_state_errors_and_admission():
+    srv = xe.Server()
+    d = xe.Server.desc(8, 2, 16, 4, blocks_per_fold=2, ring_blocks=4)
+    sid = srv.open(d)
+    with pytest.raises(xe.XengineError) as e:
+        srv.commit(sid, 0)
+    assert e.value.status_name == "XC_ERR_STATE"
+    srv.acquire(sid)
+    with pytest.raises(xe.XengineError) as e:
+        srv.acquire(sid)
+    assert e.value.status_name == "XC_ERR_STATE"
+    srv.commit(sid, time.monotonic_ns())
+    srv.close_stream(sid)
+    with pytest.raises(xe.XengineError):
+        srv.acquire(sid)
+    srv.close()
+    # admission against a budget that fits exactly two such streams
+    fp = xe.Server.footprint(d)
+    srv = xe.Server(hbm_budget_bytes=2 * fp + fp // 2)
+    a, b = srv.open(d), srv.open(d)
+    with pytest.raises(xe.XengineError) as e:
+        srv.open(d)
+    assert e.value.status_name == "XC_ERR_ADMISSION"
+    srv.close_stream(a)
+    c = srv.open(d)                     # the freed budget admits a new stream
+    srv.close_stream(b)
+    srv.close_stream(c)
+    srv.close()
