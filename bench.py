@@ -162,6 +162,13 @@ def main():
     ap.add_argument("--no-compare", action="store_true", help="skip the other kernel paths")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (for scaling HBM counters)")
+    ap.add_argument("--batch", choices=["none", "ci8", "cf32", "both"], default="ci8",
+                    help="also time the 32-sub-array persistent batch")
+    ap.add_argument("--stream-streams", type=int, default=1, help="streams for the streaming run (0: skip)")
+    ap.add_argument("--stream-fold", type=int, default=8, help="blocks per fold (deadline = fold x period)")
+    ap.add_argument("--stream-blocks", type=int, default=384, help="blocks per stream after one warm-up integration")
+    ap.add_argument("--stream-only", action="store_true", help="run only the streaming measurement")
+    ap.add_argument("--batch-only", action="store_true", help="run only the batch measurement")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this correlator build runs on one GPU; channels would shard across GPUs "
@@ -177,6 +184,14 @@ def main():
 
     dev = "cuda:0"
     stream = torch.cuda.current_stream()
+    if args.stream_only:
+        print(json.dumps(stream_bench(xe, inputs, torch, args.stream_streams, args.stream_fold, args.stream_blocks)),
+              flush=True)
+        return
+    if args.batch_only:
+        print(json.dumps({k: batch_bench(xe, inputs, torch, dev, stream, k)
+                          for k in (["ci8", "cf32"] if args.batch == "both" else [args.batch])}), flush=True)
+        return
     S, C, T, kind_in, cfg = WORKLOADS[args.workload]
     if args.workload == "lofar64" and args.kernel != "auto":
         cfg = {"mfma": {"kernel": xe.XC_KERNEL_MFMA}, "valu": {"kernel": xe.XC_KERNEL_VALU}}[args.kernel]
@@ -227,6 +242,14 @@ def main():
         torch.cuda.empty_cache()
         res["paths"] = compare_paths(xe, inputs, torch, dev, stream)
 
+    if not args.no_compare and args.workload == "lofar64":
+        if args.batch != "none":
+            res["batch"] = {k: batch_bench(xe, inputs, torch, dev, stream, k)
+                            for k in (["ci8", "cf32"] if args.batch == "both" else [args.batch])}
+        if args.stream_streams > 0:
+            res["stream"] = stream_bench(xe, inputs, torch, args.stream_streams, args.stream_fold,
+                                         args.stream_blocks)
+
     if not args.no_cpu_baseline:
         xh = None
 
@@ -276,6 +299,110 @@ def compare_paths(xe, inputs, torch, dev, stream, steps=10):
         del x, o
     torch.cuda.empty_cache()
     return out
+
+
+def batch_bench(xe, inputs, torch, dev, stream, kind, steps=5):
+    """32 sub-arrays of uneven shape (stations uniform in [24, 576], channels
+    uniform in [16, 1024], 768 samples) in one persistent, graph-replayed
+    launch, against one xc_correlate launch per sub-array."""
+    shapes = inputs.subarray_shapes(32, seed=4)
+    xs, outs = [], []
+    for k, (S, C, T) in enumerate(shapes):
+        if kind == "ci8":
+            xs.append(inputs.ci8_gaussian(C, T, S, seed=1000 + k, device=dev))
+            outs.append(torch.empty(xe.vis_shape(C, S, xe.XC_OUT_CI32), dtype=torch.int32, device=dev))
+        else:
+            xs.append(inputs.cn_gaussian(C, T, S, seed=1000 + k, device=dev))
+            outs.append(torch.empty(xe.vis_shape(C, S, xe.XC_OUT_CF32), dtype=torch.complex64, device=dev))
+    flops = sum(xe.flops(S, C, T) for S, C, T in shapes)
+    plan = xe.BatchPlan(xs, outs, use_graph=True, stream=stream)
+    ms_plan = time_launches(lambda: plan.run(stream), steps, 1, stream)
+
+    def each():
+        for x, o in zip(xs, outs):
+            xe.correlate_into(x, o, stream=stream)
+    ms_each = time_launches(each, steps, 1, stream)
+    plan.close()
+    in_bytes = sum(x.numel() * x.element_size() for x in xs)
+    out_bytes = sum(o.numel() * o.element_size() for o in outs)
+    del xs, outs
+    torch.cuda.empty_cache()
+    return {"workload": "32 sub-arrays, stations U[24,576], channels U[16,1024], 768 samples, "
+                        + ("complex int8" if kind == "ci8" else "complex64 CN(0,1)"),
+            "units": plan.units, "algorithmic_flops": flops, "in_GB": round(in_bytes / 1e9, 2),
+            "out_GB": round(out_bytes / 1e9, 2),
+            "persistent_graph_ms": round(ms_plan, 3), "persistent_TFLOP/s": round(flops / ms_plan / 1e9, 1),
+            "per_item_launches_ms": round(ms_each, 3), "per_item_TFLOP/s": round(flops / ms_each / 1e9, 1)}
+
+
+def stream_bench(xe, inputs, torch, n_streams, k, n_blocks, S=512, C=4096, bt=256, bpi=192):
+    """Streaming: 512 stations, 4096 channels, complex int8 blocks of 256
+    samples arriving every P = 256 / 49152 s (192 blocks = one second per
+    integration), folded k blocks at a time into resident int32 accumulators.
+    Arrivals are simulated: every ring slot is filled once with distinct
+    random blocks and a block 'arrives' at its scheduled host time t0 + n P.
+    Latency = fold completion - arrival; deadline = k P."""
+    P = bt / 49152.0
+    srv = xe.Server()
+    desc = xe.Server.desc(S, C, bt, bpi, blocks_per_fold=k, ring_blocks=2 * k, in_type=xe.XC_IN_CI8,
+                          acc_type=xe.XC_OUT_CI32, block_period_s=P)
+    fp = xe.Server.footprint(desc)
+    sids, admitted, refused = [], 0, 0
+    for _ in range(n_streams):
+        try:
+            sids.append(srv.open(desc))
+            admitted += 1
+        except xe.XengineError as e:
+            if e.status_name != "XC_ERR_ADMISSION":
+                raise
+            refused += 1
+    # fill every ring slot with distinct samples
+    for sid in sids:
+        for slot in range(2 * k):
+            ptr = srv.acquire(sid)
+            t = xe.device_tensor(ptr, (C, bt, S, 2, 2), torch.int8)
+            t.copy_(inputs.ci8_gaussian(C, bt, S, seed=7000 + 31 * sid + slot, device="cuda:0", chunk_channels=512))
+            srv.commit(sid, time.monotonic_ns())
+    torch.cuda.synchronize()
+    for sid in sids:
+        srv.stats(sid)
+    def feed(n_feed):
+        stalls = 0
+        t0 = time.monotonic_ns()
+        for n in range(n_feed):
+            due = t0 + int(n * P * 1e9)
+            while time.monotonic_ns() < due:
+                pass
+            for sid in sids:
+                while True:
+                    try:
+                        srv.acquire(sid)
+                        break
+                    except xe.XengineError as e:
+                        if e.status_name != "XC_ERR_BACKPRESSURE":
+                            raise
+                        stalls += 1
+                srv.commit(sid, due)
+        return stalls
+
+    # warm-up: the rest of the first integration at the real-time rate
+    feed(bpi - 2 * k)
+    for sid in sids:
+        srv.reset_stats(sid)
+    stalls = feed(n_blocks)
+    per = [srv.stats(sid) for sid in sids]
+    for sid in sids:
+        srv.close_stream(sid)
+    srv.close()
+    return {"workload": f"{S} stations, {C} channels, complex int8 blocks of {bt} samples every "
+                        f"{P * 1e3:.3f} ms, {bpi} blocks per integration, fold every {k} blocks",
+            "streams_requested": n_streams, "streams_admitted": admitted, "streams_refused": refused,
+            "footprint_GB": round(fp / 1e9, 1), "deadline_ms": round(k * P * 1e3, 3),
+            "p50_ms": [round(p["p50_ms"], 3) for p in per], "p99_ms": [round(p["p99_ms"], 3) for p in per],
+            "max_ms": [round(p["max_ms"], 3) for p in per], "blocks": [p["blocks"] for p in per],
+            "misses": [p["misses"] for p in per], "integrations": [p["integrations"] for p in per],
+            "sustained_TFLOP/s": [round(p["tflops"], 1) for p in per], "producer_stalls": stalls,
+            "realtime_TFLOP/s_needed_per_stream": round(xe.flops(S, C, bt) / P / 1e12, 1)}
 
 
 if __name__ == "__main__":

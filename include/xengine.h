@@ -300,6 +300,11 @@ xc_status xc_stream_latest(xc_server *srv, int32_t stream_id, const void **vis,
 /* Waits for all enqueued folds of the stream, then fills *stats. */
 xc_status xc_stream_stats(xc_server *srv, int32_t stream_id, xc_latency_stats *stats);
 
+/* Waits for all enqueued folds of the stream, then forgets their latency
+ * records (the next xc_stream_stats covers only blocks committed after this
+ * call).  Integration state is unchanged. */
+xc_status xc_stream_reset_stats(xc_server *srv, int32_t stream_id);
+
 /* Waits for the stream's work and frees its buffers. */
 xc_status xc_stream_close(xc_server *srv, int32_t stream_id);
 

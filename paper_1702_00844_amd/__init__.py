@@ -295,6 +295,9 @@ class Server:
         _lib.check(lib().xc_stream_stats(self._h, sid, ctypes.byref(s)))
         return {k: getattr(s, k) for k, _ in _lib.XcLatencyStats._fields_}
 
+    def reset_stats(self, sid: int):
+        _lib.check(lib().xc_stream_reset_stats(self._h, sid))
+
     def close_stream(self, sid: int):
         _lib.check(lib().xc_stream_close(self._h, sid))
 

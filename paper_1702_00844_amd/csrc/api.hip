@@ -125,15 +125,21 @@ xc_status resolve(const xc_config *cfg_in, xc_in_type in_type, xc_out_type out_t
             return set_error(XC_ERR_INVALID_ARG, "VALU (time_chunk, time_split) = (%d, %d) not available",
                              p.time_chunk, p.time_split);
     } else {
-        p.block = cfg.block ? cfg.block : (in_type == XC_IN_CF32 ? 32 : 64);
+        p.block = cfg.block ? cfg.block : 64;
         if (p.block != 32 && p.block != 64)
             return set_error(XC_ERR_INVALID_ARG, "MFMA block must be 32 or 64 (got %d)", p.block);
-        p.time_chunk = cfg.time_chunk ? cfg.time_chunk : mfma_chunk(in_type, p.block);
-        p.time_split = cfg.time_split ? cfg.time_split : 1;
-        if (p.time_chunk != mfma_chunk(in_type, p.block))
-            return set_error(XC_ERR_INVALID_ARG, "MFMA time_chunk for this input type and block must be %d",
-                             mfma_chunk(in_type, p.block));
-        if (p.time_split != 1) return set_error(XC_ERR_INVALID_ARG, "MFMA time_split must be 1");
+        // complex-float32 on 64-station blocks uses the 16x16 tile kernel, which
+        // can split time over two wave groups (with 32-step chunks); every
+        // other variant uses one
+        const bool f16tile = in_type == XC_IN_CF32 && p.block == 64;
+        p.time_split = cfg.time_split ? cfg.time_split : (f16tile && S <= 64 ? 2 : 1);
+        const int chunk = (f16tile && p.time_split == 2) ? 32 : mfma_chunk(in_type, p.block);
+        p.time_chunk = cfg.time_chunk ? cfg.time_chunk : chunk;
+        if (p.time_chunk != chunk)
+            return set_error(XC_ERR_INVALID_ARG, "MFMA time_chunk for this configuration must be %d", chunk);
+        if (!(p.time_split == 1 || (f16tile && p.time_split == 2)))
+            return set_error(XC_ERR_INVALID_ARG,
+                             "MFMA time_split must be 1 (or 2 for complex-float32 on 64-station blocks)");
     }
     const int64_t nb = (S + p.block - 1) / p.block;
     const int64_t nwork = (int64_t)C * (nb * (nb + 1) / 2);
@@ -174,7 +180,7 @@ static xc_status check_int8(const void *samples, size_t n, hipStream_t stream) {
     int h = 0;
     e = hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
-    hipFree(flag);
+    (void)hipFree(flag);
     if (e != hipSuccess) return hip_error(e, "XC_CHECK scan");
     if (h) return set_error(XC_ERR_INVALID_ARG, "XC_CHECK: int8 samples contain -128 (domain is [-127, 127])");
     return XC_OK;
@@ -202,8 +208,10 @@ Job make_job(const void *samples, void *vis, int S, int C, int T, int block, int
 
 xc_status launch_plan(const Plan &plan, xc_in_type in_type, xc_out_type out_type, const Job &job,
                       hipStream_t stream) {
-    hipError_t e = plan.kernel == XC_KERNEL_VALU ? launch_valu(plan, job, stream)
-                                                 : launch_mfma(plan, in_type, out_type, job, stream);
+    hipError_t e;
+    if (plan.kernel == XC_KERNEL_VALU) e = launch_valu(plan, job, stream);
+    else if (in_type == XC_IN_CF32 && plan.block == 64) e = launch_mfma16(plan, job, stream);
+    else e = launch_mfma(plan, in_type, out_type, job, stream);
     if (e != hipSuccess) return hip_error(e, "kernel launch");
     return XC_OK;
 }

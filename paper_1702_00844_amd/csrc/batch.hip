@@ -81,6 +81,8 @@ static hipError_t plan_enqueue(xc_batch_plan *p, hipStream_t s) {
     if (e != hipSuccess) return e;
     if (p->plan.kernel == XC_KERNEL_VALU)
         return launch_valu_batch(p->plan, p->d_jobs, p->d_units, (int)p->n_units, p->d_counter, p->grid, s);
+    if (p->in_type == XC_IN_CF32 && p->plan.block == 64)
+        return launch_mfma16_batch(p->plan, p->d_jobs, p->d_units, (int)p->n_units, p->d_counter, p->grid, s);
     return launch_mfma_batch(p->plan, p->in_type, p->out_type, p->d_jobs, p->d_units, (int)p->n_units,
                              p->d_counter, p->grid, s);
 }
@@ -114,6 +116,10 @@ xc_status xc_batch_plan_create(const xc_subarray *items, int32_t n_items, int32_
     if (!items || n_items < 1) return set_error(XC_ERR_INVALID_ARG, "a batch needs at least one item");
     if (accumulate != 0 && accumulate != 1) return set_error(XC_ERR_INVALID_ARG, "accumulate must be 0 or 1");
     Plan plan{};
+    // Without an explicit configuration every item runs one time group per
+    // workgroup, so that all items share one persistent kernel.
+    const xc_config one_group = {XC_KERNEL_AUTO, 0, 0, 1};
+    if (!cfg) cfg = &one_group;
     std::vector<int32_t> S(n_items), C(n_items), T(n_items);
     for (int i = 0; i < n_items; ++i) {
         Plan pi;
@@ -157,8 +163,9 @@ xc_status xc_batch_plan_create(const xc_subarray *items, int32_t n_items, int32_
     }
     // persistent grid: every CU filled to the kernel's occupancy
     const int cus = device_cu_count();
-    const int per_cu = plan.kernel == XC_KERNEL_VALU ? occupancy_valu_batch(plan)
-                                                     : occupancy_mfma_batch(plan, in_type, out_type);
+    const int per_cu = plan.kernel == XC_KERNEL_VALU                    ? occupancy_valu_batch(plan)
+                       : (in_type == XC_IN_CF32 && plan.block == 64) ? occupancy_mfma16_batch(plan)
+                                                                     : occupancy_mfma_batch(plan, in_type, out_type);
     p->grid = (int)std::min<int64_t>((int64_t)cus * per_cu, n_units);
     if (use_graph) {
         e = hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking);

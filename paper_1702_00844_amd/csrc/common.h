@@ -78,6 +78,12 @@ hipError_t launch_valu(const Plan &plan, const Job &job, hipStream_t stream);
 hipError_t launch_mfma(const Plan &plan, xc_in_type in_type, xc_out_type out_type,
                        const Job &job, hipStream_t stream);
 
+// FP32 samples on 16x16x4 matrix-core tiles (64-station blocks).
+hipError_t launch_mfma16(const Plan &plan, const Job &job, hipStream_t stream);
+hipError_t launch_mfma16_batch(const Plan &plan, const Job *jobs, const Unit *units, int n_units, int *counter,
+                               int grid, hipStream_t stream);
+int occupancy_mfma16_batch(const Plan &plan);
+
 // Persistent batch launchers: units[0..n_units) processed by a fixed grid that
 // takes units from *counter (which must be zero at launch).
 hipError_t launch_valu_batch(const Plan &plan, const Job *jobs, const Unit *units,

@@ -17,7 +17,9 @@
 //   complex f16     -> v_mfma_f32_32x32x16_f16  (f32 accumulation)
 //   complex bf16    -> v_mfma_f32_32x32x16_bf16 (f32 accumulation)
 //   complex f32     -> v_mfma_f32_32x32x2_f32   (f32 products and accumulation;
-//                      the four real products are issued separately)
+//                      the four real products are issued separately; this
+//                      variant serves 32-station blocks, while 64-station
+//                      blocks of complex f32 use the 16 x 16 tile kernel)
 //
 // Tiling: the station triangle is split into blocks of SB stations (SB = 32
 // or 64, i.e. 2 SB rows of (station, pol)); a workgroup of four waves owns one
@@ -492,7 +494,7 @@ int occupancy_t() {
     case XC_IN_CBF16:                                                                                 \
         return sb == 32 ? FN<K_BF16, 32, float2>(__VA_ARGS__) : FN<K_BF16, 64, float2>(__VA_ARGS__);  \
     case XC_IN_CF32:                                                                                  \
-        return sb == 32 ? FN<K_F32, 32, float2>(__VA_ARGS__) : FN<K_F32, 64, float2>(__VA_ARGS__);    \
+        return FN<K_F32, 32, float2>(__VA_ARGS__);                                                    \
     }
 
 }  // namespace mfma

@@ -328,6 +328,24 @@ xc_status xc_stream_stats(xc_server *srv, int32_t id, xc_latency_stats *stats) {
     return XC_OK;
 }
 
+xc_status xc_stream_reset_stats(xc_server *srv, int32_t id) {
+    if (!srv) return set_error(XC_ERR_INVALID_ARG, "null server");
+    std::lock_guard<std::mutex> lk(srv->mu);
+    Stream *s = get_stream(srv, id);
+    if (!s) return set_error(XC_ERR_INVALID_ARG, "no open stream %d", id);
+    hipError_t e = hipStreamSynchronize(s->hs);
+    if (e != hipSuccess) return hip_error(e, "hipStreamSynchronize");
+    for (auto &f : s->folds) {
+        while (!__atomic_load_n(&f.rec->done, __ATOMIC_ACQUIRE)) {
+        }
+    }
+    // ring slots still point at completed records: release them first
+    for (auto &b : s->slot_busy) b = nullptr;
+    for (auto &f : s->folds) delete f.rec;
+    s->folds.clear();
+    return XC_OK;
+}
+
 xc_status xc_stream_close(xc_server *srv, int32_t id) {
     if (!srv) return set_error(XC_ERR_INVALID_ARG, "null server");
     std::lock_guard<std::mutex> lk(srv->mu);

@@ -12,7 +12,8 @@ using namespace xc;
 static std::vector<xc_config> candidates(xc_in_type in_type) {
     std::vector<xc_config> v;
     v.push_back(xc_config{XC_KERNEL_MFMA, 32, 0, 0});
-    v.push_back(xc_config{XC_KERNEL_MFMA, 64, 0, 0});
+    v.push_back(xc_config{XC_KERNEL_MFMA, 64, 0, 1});
+    if (in_type == XC_IN_CF32) v.push_back(xc_config{XC_KERNEL_MFMA, 64, 0, 2});
     if (in_type == XC_IN_CF32) {
         const int opts[][2] = {{16, 1}, {16, 2}, {16, 4}, {32, 2}, {32, 4}, {32, 8}};
         for (auto &o : opts) v.push_back(xc_config{XC_KERNEL_VALU, 32, o[0], o[1]});
@@ -50,13 +51,13 @@ xc_status xc_autotune(const void *samples, xc_in_type in_type, int32_t n_station
         }
         double t_min = 1e300;
         for (int rep = 0; rep < 3 && st == XC_OK; ++rep) {
-            hipEventRecord(e0, s);
+            (void)hipEventRecord(e0, s);
             st = xc_correlate_config(&r, samples, in_type, n_stations, n_pol, n_channels, n_times, vis, out_type,
                                      0, stream);
-            hipEventRecord(e1, s);
+            (void)hipEventRecord(e1, s);
             if (hipEventSynchronize(e1) != hipSuccess) st = set_error(XC_ERR_HIP, "event sync failed");
             float ms = 0.f;
-            hipEventElapsedTime(&ms, e0, e1);
+            (void)hipEventElapsedTime(&ms, e0, e1);
             if (st == XC_OK && ms < t_min) t_min = ms;
         }
         if (st != XC_OK) {
@@ -69,8 +70,8 @@ xc_status xc_autotune(const void *samples, xc_in_type in_type, int32_t n_station
             found = true;
         }
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     if (!found) return last != XC_OK ? last : set_error(XC_ERR_UNSUPPORTED, "no configuration ran");
     *best = best_c;
     *best_ms = best_t;

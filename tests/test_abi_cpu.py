@@ -114,7 +114,13 @@ def test_config_resolution():
     r = xe.resolve_config(shp, config={"kernel": _lib.XC_KERNEL_VALU})
     assert r == {"kernel": 1, "block": 32, "time_chunk": 16, "time_split": 4}
     r = xe.resolve_config(shp, config={"kernel": _lib.XC_KERNEL_MFMA})
+    assert r == {"kernel": 2, "block": 64, "time_chunk": 32, "time_split": 2}
+    r = xe.resolve_config((_lib.XC_IN_CF32, 1024, 1024, 256, 2), config={"kernel": _lib.XC_KERNEL_MFMA})
+    assert r == {"kernel": 2, "block": 64, "time_chunk": 16, "time_split": 1}
+    r = xe.resolve_config(shp, config={"kernel": _lib.XC_KERNEL_MFMA, "block": 32})
     assert r == {"kernel": 2, "block": 32, "time_chunk": 16, "time_split": 1}
+    with pytest.raises(xe.XengineError):
+        xe.resolve_config((_lib.XC_IN_CI8, 4, 16, 8, 2), _lib.XC_OUT_CI32, config={"kernel": 2, "time_split": 2})
     r = xe.resolve_config((_lib.XC_IN_CI8, 1024, 1024, 256, 2), _lib.XC_OUT_CI32)
     assert r == {"kernel": 2, "block": 64, "time_chunk": 64, "time_split": 1}
     r = xe.resolve_config((_lib.XC_IN_CF16, 1024, 1024, 256, 2))

@@ -48,10 +48,12 @@ def _check(kind, xs, outs, base=None):
 
 @pytest.mark.parametrize("kind,config", [
     ("ci8", None), ("cf16", None), ("cbf16", None),
-    ("cf32", {"kernel": xe.XC_KERNEL_MFMA}), ("cf32", {"kernel": xe.XC_KERNEL_MFMA, "block": 64}),
+    ("cf32", {"kernel": xe.XC_KERNEL_MFMA, "block": 32}),
+    ("cf32", {"kernel": xe.XC_KERNEL_MFMA, "block": 64, "time_split": 1}),
+    ("cf32", {"kernel": xe.XC_KERNEL_MFMA, "block": 64, "time_split": 2}),
     ("cf32", {"kernel": xe.XC_KERNEL_VALU, "time_chunk": 32, "time_split": 8}),
     ("cf32", {"kernel": xe.XC_KERNEL_VALU, "time_chunk": 16, "time_split": 1}),
-], ids=["ci8", "cf16", "cbf16", "f32mfma32", "f32mfma64", "valu_ts8", "valu_ts1"])
+], ids=["ci8", "cf16", "cbf16", "f32mfma32", "f32mfma64ts1", "f32mfma64ts2", "valu_ts8", "valu_ts1"])
 @pytest.mark.parametrize("use_graph", [True, False], ids=["graph", "direct"])
 def test_batch_matches_oracle(kind, config, use_graph):
     xs = _make(kind, SHAPES)

@@ -19,8 +19,12 @@ DEV = "cuda:0"
 FP32_TOL = 1e-5
 
 VALU = [dict(kernel=xe.XC_KERNEL_VALU, time_chunk=tc, time_split=ts)
-        for tc, ts in [(16, 1), (16, 2), (16, 4), (32, 2), (32, 4)]]
+        for tc, ts in [(16, 1), (16, 2), (16, 4), (32, 2), (32, 4), (32, 8)]]
 MFMA = dict(kernel=xe.XC_KERNEL_MFMA)
+# complex-float32 matrix-core variants: 32x32 tiles on 32-station blocks, and
+# 16x16 tiles on 64-station blocks with one or two time groups
+MFMA_F32 = [dict(kernel=xe.XC_KERNEL_MFMA, block=32), dict(kernel=xe.XC_KERNEL_MFMA, block=64, time_split=1),
+            dict(kernel=xe.XC_KERNEL_MFMA, block=64, time_split=2)]
 
 # (S, C, T): tiny, ragged station counts across block edges, ragged time tails
 SHAPES = [(1, 2, 1), (3, 1, 5), (8, 3, 17), (33, 2, 100), (64, 2, 64), (70, 1, 300), (130, 1, 77)]
@@ -30,9 +34,14 @@ def _cf32(S, C, T, seed):
     return inputs.cn_gaussian(C, T, S, seed=seed, device=DEV)
 
 
+def _cfg_id(c):
+    if c["kernel"] == xe.XC_KERNEL_VALU:
+        return "valu_tc%d_ts%d" % (c["time_chunk"], c["time_split"])
+    return "mfma_b%d_ts%d" % (c.get("block", 0), c.get("time_split", 0))
+
+
 @pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "S%d_C%d_T%d" % s)
-@pytest.mark.parametrize("cfg", VALU + [MFMA], ids=lambda c: "valu_tc%d_ts%d" % (c["time_chunk"], c["time_split"])
-                         if c["kernel"] == xe.XC_KERNEL_VALU else "mfma")
+@pytest.mark.parametrize("cfg", VALU + MFMA_F32, ids=_cfg_id)
 def test_cf32_parity(shape, cfg):
     S, C, T = shape
     x = _cf32(S, C, T, seed=S * 1000 + T)
@@ -123,7 +132,7 @@ def test_half_exact_on_integer_samples(dtype):
     assert np.array_equal(gpu_vis_numpy(v), ref[..., 0] + 1j * ref[..., 1])
 
 
-@pytest.mark.parametrize("cfg", [VALU[2], MFMA], ids=["valu", "mfma"])
+@pytest.mark.parametrize("cfg", [VALU[2]] + MFMA_F32, ids=["valu", "mfma_b32", "mfma_b64_ts1", "mfma_b64_ts2"])
 def test_accumulate_mode(cfg):
     S, C, T = 40, 3, 96
     x1 = _cf32(S, C, T, seed=11)
@@ -163,7 +172,7 @@ def test_delta_conjugation_and_numbering():
     x = torch.zeros((C, T, S, 2), dtype=torch.complex64, device=DEV)
     x[c, t0, i, p] = 1
     x[c, t0, j, q] = 1j
-    for cfg in VALU[2:3] + [MFMA]:
+    for cfg in VALU[2:3] + MFMA_F32:
         v = gpu_vis_numpy(xe.correlate(x, config=cfg))
         expect = np.zeros_like(v)
         expect[c, xe.baseline_index(i, j), p, q] = -1j
@@ -176,7 +185,7 @@ def test_config1_full():
     """8 stations, 16 channels, 256 samples, CN(0,1): every output."""
     x = inputs.cn_gaussian(16, 256, 8, seed=1, device=DEV)
     ref = oracle_vis(x)
-    for cfg in VALU + [MFMA]:
+    for cfg in VALU + MFMA_F32:
         assert rel_err(gpu_vis_numpy(xe.correlate(x, config=cfg)), ref) <= FP32_TOL
 
 
@@ -185,7 +194,7 @@ def test_config2_full():
     every output, both FP32 kernels, in the configurations the benchmark times."""
     x, _ = inputs.point_sources(256, 768, 64, seed=2, device=DEV)
     ref = oracle_vis(x)
-    for cfg in [VALU[2], MFMA, None]:
+    for cfg in [VALU[2], VALU[5]] + MFMA_F32 + [None]:
         got = gpu_vis_numpy(xe.correlate(x, config=cfg))
         assert rel_err(got, ref) <= FP32_TOL
         assert_hermitian_autos(got, 64)
@@ -208,7 +217,7 @@ def test_config3_sampled_channels():
         assert np.array_equal(gpu_vis_numpy(vh, chans), refc)
         del vh
     xf = torch.view_as_complex(x.to(torch.float32))
-    for cfg in [VALU[2], MFMA]:
+    for cfg in [VALU[2]] + MFMA_F32:
         vf = xe.correlate(xf, config=cfg)
         assert rel_err(gpu_vis_numpy(vf, chans), refc) <= FP32_TOL
         del vf
