@@ -253,12 +253,20 @@ typedef struct xc_stream_desc {
     double block_period_s;          /* arrival period P; deadline = k * P            */
 } xc_stream_desc;
 
+/* Latency accounting.  A block's latency runs from its arrival to the
+ * completion of the fold that integrates it; a fold's latency runs from the
+ * arrival of its last block (when it can start) to its completion.  The
+ * real-time deadline is on folds: a fold must complete before the next fold's
+ * blocks have all arrived, i.e. within blocks_per_fold * block_period, so that
+ * the stream keeps up with bounded queueing. */
 typedef struct xc_latency_stats {
-    double p50_ms, p99_ms, max_ms;  /* block arrival -> its fold completed          */
-    double deadline_ms;             /* blocks_per_fold * block_period               */
+    double p50_ms, p99_ms, max_ms;            /* per block: arrival -> fold completed     */
+    double fold_p50_ms, fold_p99_ms, fold_max_ms;  /* per fold: last arrival -> completed */
+    double deadline_ms;             /* blocks_per_fold * block_period (per fold)    */
     double tflops;                  /* algorithmic TFLOP/s over the measured span   */
     int64_t blocks;                 /* blocks whose latency was measured            */
-    int64_t misses;                 /* blocks whose latency exceeded the deadline   */
+    int64_t folds;                  /* folds whose latency was measured             */
+    int64_t misses;                 /* folds whose latency exceeded the deadline    */
     int64_t integrations;           /* integrations published                       */
 } xc_latency_stats;
 
@@ -311,6 +319,24 @@ xc_status xc_stream_close(xc_server *srv, int32_t stream_id);
 /* Host-only helpers, exposed for tests. */
 /* q-quantile (0..1) of n values by the nearest-rank method; NaN if n == 0. */
 double xc_quantile(const double *values, int64_t n, double q);
+
+/* ------------------------------------------------------------------------ */
+/* Achievable device peaks (for roofline reports).                           */
+
+typedef enum xc_peak {
+    XC_PEAK_F32_MFMA16 = 0,   /* v_mfma_f32_16x16x4_f32, TFLOP/s  */
+    XC_PEAK_F32_MFMA32 = 1,   /* v_mfma_f32_32x32x2_f32, TFLOP/s  */
+    XC_PEAK_I8_MFMA = 2,      /* v_mfma_i32_32x32x32_i8, TOP/s    */
+    XC_PEAK_F16_MFMA = 3,     /* v_mfma_f32_32x32x16_f16, TFLOP/s */
+    XC_PEAK_BF16_MFMA = 4,    /* v_mfma_f32_32x32x16_bf16, TFLOP/s */
+    XC_PEAK_F32_FMA = 5,      /* v_fma_f32 (vector ALU), TFLOP/s  */
+    XC_PEAK_HBM_COPY = 6      /* 1 GiB device copy, GB/s (read + write) */
+} xc_peak;
+
+/* Times register-only loops of the instruction (8 waves per SIMD, no memory
+ * traffic) or a 1 GiB device copy on the current device, synchronously, and
+ * writes the achieved rate.  Allocates and frees its own scratch buffers. */
+xc_status xc_measure_peak(int32_t which, double *value);
 
 /* ------------------------------------------------------------------------ */
 const char *xc_status_string(xc_status status);

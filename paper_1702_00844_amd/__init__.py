@@ -58,6 +58,19 @@ def flops(n_stations: int, n_channels: int, n_times: int) -> float:
     return float(lib().xc_flops(n_stations, n_channels, n_times))
 
 
+PEAK_NAMES = {"f32_mfma16": _lib.XC_PEAK_F32_MFMA16, "f32_mfma32": _lib.XC_PEAK_F32_MFMA32,
+              "i8_mfma": _lib.XC_PEAK_I8_MFMA, "f16_mfma": _lib.XC_PEAK_F16_MFMA, "bf16_mfma": _lib.XC_PEAK_BF16_MFMA,
+              "f32_fma": _lib.XC_PEAK_F32_FMA, "hbm_copy": _lib.XC_PEAK_HBM_COPY}
+
+
+def measure_peak(name: str) -> float:
+    """Achievable rate of one instruction (TFLOP/s or TOP/s) or of a device
+    copy (GB/s) on the current GPU."""
+    v = ctypes.c_double()
+    _lib.check(lib().xc_measure_peak(PEAK_NAMES[name], ctypes.byref(v)))
+    return v.value
+
+
 def quantile(values, q: float) -> float:
     arr = (ctypes.c_double * len(values))(*values)
     return float(lib().xc_quantile(arr, len(values), q))

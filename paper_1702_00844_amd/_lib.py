@@ -20,6 +20,8 @@ XC_IN_CF32, XC_IN_CI8, XC_IN_CF16, XC_IN_CBF16 = 0, 1, 2, 3
 XC_OUT_CF32, XC_OUT_CI32 = 0, 1
 XC_KERNEL_AUTO, XC_KERNEL_VALU, XC_KERNEL_MFMA = 0, 1, 2
 XC_CI32_MAX_TIMES = 66572
+XC_PEAK_F32_MFMA16, XC_PEAK_F32_MFMA32, XC_PEAK_I8_MFMA, XC_PEAK_F16_MFMA, XC_PEAK_BF16_MFMA, XC_PEAK_F32_FMA, \
+    XC_PEAK_HBM_COPY = range(7)
 
 
 class XcConfig(ctypes.Structure):
@@ -38,8 +40,9 @@ class XcStreamDesc(ctypes.Structure):
 
 
 class XcLatencyStats(ctypes.Structure):
-    _fields_ = [("p50_ms", c_f64), ("p99_ms", c_f64), ("max_ms", c_f64), ("deadline_ms", c_f64),
-                ("tflops", c_f64), ("blocks", c_i64), ("misses", c_i64), ("integrations", c_i64)]
+    _fields_ = [("p50_ms", c_f64), ("p99_ms", c_f64), ("max_ms", c_f64), ("fold_p50_ms", c_f64),
+                ("fold_p99_ms", c_f64), ("fold_max_ms", c_f64), ("deadline_ms", c_f64), ("tflops", c_f64),
+                ("blocks", c_i64), ("folds", c_i64), ("misses", c_i64), ("integrations", c_i64)]
 
 
 # name -> (restype, argtypes): every symbol include/xengine.h declares
@@ -80,6 +83,7 @@ SIGNATURES = {
     "xc_stream_close": (c_i32, [c_vp, c_i32]),
     "xc_stream_reset_stats": (c_i32, [c_vp, c_i32]),
     "xc_quantile": (c_f64, [ctypes.POINTER(c_f64), c_i64, c_f64]),
+    "xc_measure_peak": (c_i32, [c_i32, ctypes.POINTER(c_f64)]),
     "xc_status_string": (c_char_p, [c_i32]),
     "xc_last_error": (c_char_p, []),
     "xc_version": (c_char_p, []),

@@ -12,10 +12,12 @@ xc_status resolve(const xc_config *cfg, xc_in_type in_type, xc_out_type out_type
                   int32_t T, Plan *plan);
 Job make_job(const void *samples, void *vis, int S, int C, int T, int block, int accumulate);
 
-__global__ void reset_counter_kernel(int *counter) { *counter = 0; }
+__global__ void reset_counters_kernel(int *counters) {
+    if (threadIdx.x < kNumXcd) counters[threadIdx.x] = 0;
+}
 
-hipError_t launch_reset_counter(int *counter, hipStream_t stream) {
-    hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, stream, counter);
+hipError_t launch_reset_counters(int *counters, hipStream_t stream) {
+    hipLaunchKernelGGL(reset_counters_kernel, dim3(1), dim3(64), 0, stream, counters);
     return hipGetLastError();
 }
 
@@ -59,7 +61,7 @@ struct xc_batch_plan {
     int grid;
     Job *d_jobs;
     Unit *d_units;
-    int *d_counter;
+    int *d_queue;        // kNumXcd + 1 segment bounds, then kNumXcd counters
     hipGraph_t graph;
     hipGraphExec_t exec;
     hipStream_t capture_stream;
@@ -72,19 +74,18 @@ static void plan_free(xc_batch_plan *p) {
     if (p->capture_stream) (void)hipStreamDestroy(p->capture_stream);
     if (p->d_jobs) (void)hipFree(p->d_jobs);
     if (p->d_units) (void)hipFree(p->d_units);
-    if (p->d_counter) (void)hipFree(p->d_counter);
+    if (p->d_queue) (void)hipFree(p->d_queue);
     delete p;
 }
 
 static hipError_t plan_enqueue(xc_batch_plan *p, hipStream_t s) {
-    hipError_t e = launch_reset_counter(p->d_counter, s);
+    Queues q{p->d_queue, p->d_queue + kNumXcd + 1};
+    hipError_t e = launch_reset_counters(q.counters, s);
     if (e != hipSuccess) return e;
-    if (p->plan.kernel == XC_KERNEL_VALU)
-        return launch_valu_batch(p->plan, p->d_jobs, p->d_units, (int)p->n_units, p->d_counter, p->grid, s);
+    if (p->plan.kernel == XC_KERNEL_VALU) return launch_valu_batch(p->plan, p->d_jobs, p->d_units, q, p->grid, s);
     if (p->in_type == XC_IN_CF32 && p->plan.block == 64)
-        return launch_mfma16_batch(p->plan, p->d_jobs, p->d_units, (int)p->n_units, p->d_counter, p->grid, s);
-    return launch_mfma_batch(p->plan, p->in_type, p->out_type, p->d_jobs, p->d_units, (int)p->n_units,
-                             p->d_counter, p->grid, s);
+        return launch_mfma16_batch(p->plan, p->d_jobs, p->d_units, q, p->grid, s);
+    return launch_mfma_batch(p->plan, p->in_type, p->out_type, p->d_jobs, p->d_units, q, p->grid, s);
 }
 
 extern "C" {
@@ -149,7 +150,7 @@ xc_status xc_batch_plan_create(const xc_subarray *items, int32_t n_items, int32_
     p->n_units = n_units;
     hipError_t e = hipMalloc(&p->d_jobs, sizeof(Job) * n_items);
     if (e == hipSuccess) e = hipMalloc(&p->d_units, sizeof(Unit) * (size_t)n_units);
-    if (e == hipSuccess) e = hipMalloc(&p->d_counter, sizeof(int));
+    if (e == hipSuccess) e = hipMalloc(&p->d_queue, sizeof(int) * (2 * kNumXcd + 1));
     if (e != hipSuccess) {
         plan_free(p);
         return set_error(XC_ERR_OUT_OF_MEMORY, "batch plan allocation failed: %s", hipGetErrorString(e));
@@ -157,6 +158,19 @@ xc_status xc_batch_plan_create(const xc_subarray *items, int32_t n_items, int32_
     e = hipMemcpy(p->d_jobs, jobs.data(), sizeof(Job) * n_items, hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipMemcpy(p->d_units, units.data(), sizeof(Unit) * (size_t)n_units, hipMemcpyHostToDevice);
+    // one contiguous segment of the list per XCD, cut at channel boundaries
+    // where possible so that a channel's block pairs stay on one XCD
+    int bounds[kNumXcd + 1];
+    bounds[0] = 0;
+    for (int x = 1; x < kNumXcd; ++x) {
+        int64_t b = n_units * x / kNumXcd;
+        while (b > bounds[x - 1] && b < n_units &&
+               (units[b].item == units[b - 1].item && units[b].channel == units[b - 1].channel))
+            --b;
+        bounds[x] = (int)b;
+    }
+    bounds[kNumXcd] = (int)n_units;
+    if (e == hipSuccess) e = hipMemcpy(p->d_queue, bounds, sizeof(bounds), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         plan_free(p);
         return hip_error(e, "batch plan upload");

@@ -110,11 +110,16 @@ struct Pre {
     uint32_t w[Geo<KIND, SB>::NPT][Geo<KIND, SB>::WORDS];
 };
 
+// Station counts that are multiples of the staging group (4 stations for
+// int8, 2 for 16-bit) put every group wholly inside or outside the array, so
+// staging loads need no per-station checks: out-of-range groups and time
+// steps read a clamped, valid address and are replaced by zeros.
 template <int KIND, int SB>
 __device__ __forceinline__ void gload(Pre<KIND, SB> &p, const Job &job, const uint8_t *__restrict__ x, int c,
                                       const Blocks &bk, int t0, int tid) {
     typedef Geo<KIND, SB> G;
     const int S = job.S;
+    const int T = job.T;
 #pragma unroll
     for (int h = 0; h < G::NPT; ++h) {
         const int task = tid + 256 * h;
@@ -126,18 +131,26 @@ __device__ __forceinline__ void gload(Pre<KIND, SB> &p, const Job &job, const ui
             const int sg = r / (G::KT / 8);
             const int tg = r % (G::KT / 8);
             const int s = (blk ? bk.J0 : bk.I0) + sg * 4;
-            const bool skip = blk && bk.diag;
-            const bool vec = ((S & 3) == 0) && (s + 3 < S);
+            if (blk && bk.diag) continue;                 // wave-uniform: J rows are I rows
+            const uint32_t *xw = reinterpret_cast<const uint32_t *>(x);
+            if ((S & 3) == 0) {
+                const bool sok = s < S;
+                const int sc = sok ? s : 0;
 #pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                const int t = t0 + tg * 8 + k;
-                const bool tok = !skip && t < job.T;
-                const uint32_t *row = reinterpret_cast<const uint32_t *>(x) + (tok ? row_offset(job, c, t) : 0);
-                if (tok && vec) {
-                    const uint4 v = *reinterpret_cast<const uint4 *>(row + s);
-                    p.w[h][4 * k + 0] = v.x; p.w[h][4 * k + 1] = v.y;
-                    p.w[h][4 * k + 2] = v.z; p.w[h][4 * k + 3] = v.w;
-                } else {
+                for (int k = 0; k < 8; ++k) {
+                    const int t = t0 + tg * 8 + k;
+                    const bool ok = sok && t < T;
+                    const int tc = t < T ? t : T - 1;
+                    const uint4 v = *reinterpret_cast<const uint4 *>(xw + row_offset(job, c, tc) + sc);
+                    p.w[h][4 * k + 0] = ok ? v.x : 0u; p.w[h][4 * k + 1] = ok ? v.y : 0u;
+                    p.w[h][4 * k + 2] = ok ? v.z : 0u; p.w[h][4 * k + 3] = ok ? v.w : 0u;
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    const int t = t0 + tg * 8 + k;
+                    const bool tok = t < T;
+                    const uint32_t *row = xw + (tok ? row_offset(job, c, t) : 0);
 #pragma unroll
                     for (int d = 0; d < 4; ++d) p.w[h][4 * k + d] = (tok && s + d < S) ? row[s + d] : 0u;
                 }
@@ -147,11 +160,13 @@ __device__ __forceinline__ void gload(Pre<KIND, SB> &p, const Job &job, const ui
             const int s2 = task % (2 * SB);
             const int blk = s2 / SB;
             const int st = (blk ? bk.J0 : bk.I0) + s2 % SB;
-            const bool ok = !(blk && bk.diag) && (t0 + t < job.T) && st < S;
+            const bool ok = !(blk && bk.diag) && (t0 + t < T) && st < S;
+            const int tc = t0 + t < T ? t0 + t : T - 1;
+            const int sc = st < S ? st : 0;
             const float4 *xs = reinterpret_cast<const float4 *>(x);
-            const float4 v = ok ? xs[row_offset(job, c, t0 + t) + st] : make_float4(0.f, 0.f, 0.f, 0.f);
-            p.w[h][0] = __float_as_uint(v.x); p.w[h][1] = __float_as_uint(v.y);
-            p.w[h][2] = __float_as_uint(v.z); p.w[h][3] = __float_as_uint(v.w);
+            const float4 v = xs[row_offset(job, c, tc) + sc];
+            p.w[h][0] = ok ? __float_as_uint(v.x) : 0u; p.w[h][1] = ok ? __float_as_uint(v.y) : 0u;
+            p.w[h][2] = ok ? __float_as_uint(v.z) : 0u; p.w[h][3] = ok ? __float_as_uint(v.w) : 0u;
         } else {
             constexpr int NB = G::NTASK / 2;
             const int blk = task / NB;
@@ -159,18 +174,26 @@ __device__ __forceinline__ void gload(Pre<KIND, SB> &p, const Job &job, const ui
             const int sg = r / (G::KT / 4);
             const int tg = r % (G::KT / 4);
             const int s = (blk ? bk.J0 : bk.I0) + sg * 2;
-            const bool skip = blk && bk.diag;
-            const bool vec = ((S & 1) == 0) && (s + 1 < S);
+            if (blk && bk.diag) continue;                 // wave-uniform
+            const uint32_t *xw = reinterpret_cast<const uint32_t *>(x);
+            if ((S & 1) == 0) {
+                const bool sok = s < S;
+                const int sc = sok ? s : 0;
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const int t = t0 + tg * 4 + k;
-                const bool tok = !skip && t < job.T;
-                const uint32_t *row = reinterpret_cast<const uint32_t *>(x) + (tok ? 2 * row_offset(job, c, t) : 0);
-                if (tok && vec) {
-                    const uint4 v = *reinterpret_cast<const uint4 *>(row + 2 * s);
-                    p.w[h][4 * k + 0] = v.x; p.w[h][4 * k + 1] = v.y;
-                    p.w[h][4 * k + 2] = v.z; p.w[h][4 * k + 3] = v.w;
-                } else {
+                for (int k = 0; k < 4; ++k) {
+                    const int t = t0 + tg * 4 + k;
+                    const bool ok = sok && t < T;
+                    const int tc = t < T ? t : T - 1;
+                    const uint4 v = *reinterpret_cast<const uint4 *>(xw + 2 * row_offset(job, c, tc) + 2 * sc);
+                    p.w[h][4 * k + 0] = ok ? v.x : 0u; p.w[h][4 * k + 1] = ok ? v.y : 0u;
+                    p.w[h][4 * k + 2] = ok ? v.z : 0u; p.w[h][4 * k + 3] = ok ? v.w : 0u;
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int t = t0 + tg * 4 + k;
+                    const bool tok = t < T;
+                    const uint32_t *row = xw + (tok ? 2 * row_offset(job, c, t) : 0);
 #pragma unroll
                     for (int d = 0; d < 4; ++d)
                         p.w[h][4 * k + d] = (tok && s + (d >> 1) < S) ? row[2 * s + d] : 0u;
@@ -235,8 +258,11 @@ __device__ __forceinline__ void lstore(const Pre<KIND, SB> &p, uint8_t *lds, con
 }
 
 // ---------------------------------------------------------------------------
-// One chunk of MFMAs for one wave's quadrant.
-template <int KIND, int SB>
+// One chunk of MFMAs for one wave's quadrant.  ALL: every tile of the quadrant
+// is computed (no per-tile checks in the instruction stream); otherwise tiles
+// with run[] false are skipped.  The fragments of the next k-step are read
+// from LDS before the current k-step's MFMAs are issued.
+template <int KIND, int SB, bool ALL>
 __device__ __forceinline__ void compute_chunk(const uint8_t *lds, typename Acc<KIND>::type (&are)[SB / 32][SB / 32],
                                               typename Acc<KIND>::type (&aim)[SB / 32][SB / 32], int arow0,
                                               int brow0, const bool (&run)[SB / 32][SB / 32], int lane) {
@@ -259,51 +285,70 @@ __device__ __forceinline__ void compute_chunk(const uint8_t *lds, typename Acc<K
             for (int rs = 0; rs < NS; ++rs) {
 #pragma unroll
                 for (int cs = 0; cs < NS; ++cs) {
-                    if (!run[rs][cs]) continue;
+                    if (!ALL && !run[rs][cs]) continue;
                     are[rs][cs] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[rs].x, b[cs].x, are[rs][cs], 0, 0, 0);
-                    are[rs][cs] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[rs].y, b[cs].y, are[rs][cs], 0, 0, 0);
                     aim[rs][cs] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[rs].y, b[cs].x, aim[rs][cs], 0, 0, 0);
+                    are[rs][cs] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[rs].y, b[cs].y, are[rs][cs], 0, 0, 0);
                     aim[rs][cs] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[rs].x, -b[cs].y, aim[rs][cs], 0, 0, 0);
                 }
             }
         }
     } else {
         constexpr int NSTEP = G::KT / G::STEP_T;  // 4
-#pragma unroll 2
-        for (int ks = 0; ks < NSTEP; ++ks) {
+        v4i fa[2][NS], fb[2][NS];
+        auto frag = [&](int ks, v4i (&a)[NS], v4i (&b)[NS]) {
             const int koff = ks * 32 + half * 16;
-            v4i a[NS], b[NS], bi[NS];
 #pragma unroll
             for (int rs = 0; rs < NS; ++rs)
                 a[rs] = *reinterpret_cast<const v4i *>(lds + (arow0 + rs * 32 + r32) * G::PITCH + koff);
 #pragma unroll
-            for (int cs = 0; cs < NS; ++cs) {
+            for (int cs = 0; cs < NS; ++cs)
                 b[cs] = *reinterpret_cast<const v4i *>(lds + (brow0 + cs * 32 + r32) * G::PITCH + koff);
+        };
+        frag(0, fa[0], fb[0]);
+#pragma unroll
+        for (int ks = 0; ks < NSTEP; ++ks) {
+            const int cur = ks & 1;
+            if (ks + 1 < NSTEP) frag(ks + 1, fa[cur ^ 1], fb[cur ^ 1]);
+            const v4i(&a)[NS] = fa[cur];
+            const v4i(&b)[NS] = fb[cur];
+            v4i bi[NS];
+#pragma unroll
+            for (int cs = 0; cs < NS; ++cs)
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
                     const uint32_t w = (uint32_t)b[cs][e];
                     bi[cs][e] = (int)(KIND == K_I8 ? conj_swap_i8(w) : conj_swap_h(w));
+                }
+            // real parts of every tile first, then imaginary parts
+#pragma unroll
+            for (int rs = 0; rs < NS; ++rs) {
+#pragma unroll
+                for (int cs = 0; cs < NS; ++cs) {
+                    if (!ALL && !run[rs][cs]) continue;
+                    if constexpr (KIND == K_I8)
+                        are[rs][cs] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[rs], b[cs], are[rs][cs], 0, 0, 0);
+                    else if constexpr (KIND == K_F16)
+                        are[rs][cs] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
+                            __builtin_bit_cast(v8h, a[rs]), __builtin_bit_cast(v8h, b[cs]), are[rs][cs], 0, 0, 0);
+                    else
+                        are[rs][cs] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                            __builtin_bit_cast(v8bf, a[rs]), __builtin_bit_cast(v8bf, b[cs]), are[rs][cs], 0, 0, 0);
                 }
             }
 #pragma unroll
             for (int rs = 0; rs < NS; ++rs) {
 #pragma unroll
                 for (int cs = 0; cs < NS; ++cs) {
-                    if (!run[rs][cs]) continue;
-                    if constexpr (KIND == K_I8) {
-                        are[rs][cs] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[rs], b[cs], are[rs][cs], 0, 0, 0);
+                    if (!ALL && !run[rs][cs]) continue;
+                    if constexpr (KIND == K_I8)
                         aim[rs][cs] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[rs], bi[cs], aim[rs][cs], 0, 0, 0);
-                    } else if constexpr (KIND == K_F16) {
-                        are[rs][cs] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
-                            __builtin_bit_cast(v8h, a[rs]), __builtin_bit_cast(v8h, b[cs]), are[rs][cs], 0, 0, 0);
+                    else if constexpr (KIND == K_F16)
                         aim[rs][cs] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
                             __builtin_bit_cast(v8h, a[rs]), __builtin_bit_cast(v8h, bi[cs]), aim[rs][cs], 0, 0, 0);
-                    } else {
-                        are[rs][cs] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                            __builtin_bit_cast(v8bf, a[rs]), __builtin_bit_cast(v8bf, b[cs]), are[rs][cs], 0, 0, 0);
+                    else
                         aim[rs][cs] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
                             __builtin_bit_cast(v8bf, a[rs]), __builtin_bit_cast(v8bf, bi[cs]), aim[rs][cs], 0, 0, 0);
-                    }
                 }
             }
         }
@@ -362,6 +407,79 @@ __device__ __forceinline__ void store_tile(const Job &job, int c, const ACC &re,
     }
 }
 
+// Coalesced store of one 32 x 32 tile (16 x 16 station pairs) through this
+// wave's private LDS region: the accumulators are written as an image of the
+// output (for each station j, the 16 baselines (i, j) of 32 bytes each, rows
+// padded by 16 bytes), then every lane stores whole baselines, so that 16
+// consecutive lanes write one 512-byte run of V.  Autocorrelations are made
+// Hermitian (XX, YY real; YX = conj XY) on the way out.
+constexpr int IMG_ROW = 16 * 32 + 16;   // bytes per station j in a tile image
+constexpr int IMG_BYTES = 16 * IMG_ROW;
+
+template <typename OUT>
+struct Vec;
+template <>
+struct Vec<float2> {
+    __device__ static uint4 add(uint4 a, uint4 b) {
+        return make_uint4(__float_as_uint(__uint_as_float(a.x) + __uint_as_float(b.x)),
+                          __float_as_uint(__uint_as_float(a.y) + __uint_as_float(b.y)),
+                          __float_as_uint(__uint_as_float(a.z) + __uint_as_float(b.z)),
+                          __float_as_uint(__uint_as_float(a.w) + __uint_as_float(b.w)));
+    }
+    __device__ static uint32_t neg(uint32_t v) { return v ^ 0x80000000u; }
+};
+template <>
+struct Vec<int2> {
+    __device__ static uint4 add(uint4 a, uint4 b) { return make_uint4(a.x + b.x, a.y + b.y, a.z + b.z, a.w + b.w); }
+    __device__ static uint32_t neg(uint32_t v) { return 0u - v; }
+};
+
+template <typename ACC, typename OUT>
+__device__ __forceinline__ void store_tile_lds(const Job &job, int c, const ACC &re, const ACC &im, int row0,
+                                               int col0, int lane, uint8_t *img) {
+    const int S = job.S;
+    // 1. image: element (lane, r) is row 8 (r/4) + 4 (lane/32) + r%4, column lane % 32
+    {
+        const int col = lane & 31;
+        const int jl = col >> 1, q = col & 1;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int row = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+            const OUT v = Out<OUT>::make(re[r], im[r]);
+            *reinterpret_cast<OUT *>(img + jl * IMG_ROW + (row >> 1) * 32 + (row & 1) * 16 + q * 8) = v;
+        }
+    }
+    __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0): the image is written before any lane reads it
+    __builtin_amdgcn_wave_barrier();
+    // 2. whole baselines: lane handles baselines lane, lane + 64, ... of the tile
+    OUT *__restrict__ V = static_cast<OUT *>(job.vis) + (size_t)c * ((size_t)S * (S + 1) / 2) * 4;
+    const int i0 = row0 >> 1, j0 = col0 >> 1;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int bl = lane + 64 * k;
+        const int jl = bl >> 4, il = bl & 15;
+        const int i = i0 + il, j = j0 + jl;
+        uint4 lo = *reinterpret_cast<const uint4 *>(img + jl * IMG_ROW + il * 32);        // XX, XY
+        uint4 hi = *reinterpret_cast<const uint4 *>(img + jl * IMG_ROW + il * 32 + 16);   // YX, YY
+        if (j >= S || i > j) continue;
+        if (i == j) {
+            lo.y = 0u;                      // Im XX
+            hi.w = 0u;                      // Im YY
+            hi.x = lo.z;                    // YX = conj(XY)
+            hi.y = Vec<OUT>::neg(lo.w);
+        }
+        uint4 *dst = reinterpret_cast<uint4 *>(V + ((size_t)j * (j + 1) / 2 + i) * 4);
+        if (job.accumulate) {
+            lo = Vec<OUT>::add(lo, dst[0]);
+            hi = Vec<OUT>::add(hi, dst[1]);
+        }
+        dst[0] = lo;
+        dst[1] = hi;
+    }
+    __builtin_amdgcn_s_waitcnt(0xc07f);   // reads done before the region is reused
+    __builtin_amdgcn_wave_barrier();
+}
+
 template <int KIND, int SB, typename OUT>
 __device__ __forceinline__ void unit(const Job &job, int c, int bi, int bj, uint8_t *lds) {
     typedef Geo<KIND, SB> G;
@@ -369,7 +487,9 @@ __device__ __forceinline__ void unit(const Job &job, int c, int bi, int bj, uint
     constexpr int NS = G::NS;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const int wave = tid >> 6;
+    // the wave index is uniform across a wave: keep it (and everything derived
+    // from it, such as which tiles run) in scalar registers
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wr = wave >> 1;
     const int wc = wave & 1;
 
@@ -415,19 +535,36 @@ __device__ __forceinline__ void unit(const Job &job, int c, int bi, int bj, uint
     for (int ch = 0; ch < nchunk; ++ch) {
         const int buf = ch & 1;
         if (ch + 1 < nchunk) gload<KIND, SB>(pre, job, x, c, bk, (ch + 1) * G::KT, tid);
-        if (any) compute_chunk<KIND, SB>(lds + buf * G::STAGE_BYTES, are, aim, arow0, brow0, run, lane);
+        // A wave with any tile to do computes all of its tiles: the skipped ones
+        // (below the diagonal or past the last station) only occur in waves
+        // that are not the slowest of their workgroup, so this costs no time
+        // and keeps the MFMA stream free of branches.
+        if (any) compute_chunk<KIND, SB, true>(lds + buf * G::STAGE_BYTES, are, aim, arow0, brow0, run, lane);
         if (ch + 1 < nchunk) lstore<KIND, SB>(pre, lds + (buf ^ 1) * G::STAGE_BYTES, bk, tid);
         __syncthreads();
     }
 
     if (!any) return;
+    if constexpr (SB == 64) {
+        // the staging buffers are free after the last barrier: one image region per wave
+        static_assert(4 * IMG_BYTES <= 2 * G::STAGE_BYTES, "tile images must fit the staging area");
+        uint8_t *img = lds + wave * IMG_BYTES;
 #pragma unroll
-    for (int rs = 0; rs < NS; ++rs)
+        for (int rs = 0; rs < NS; ++rs)
 #pragma unroll
-        for (int cs = 0; cs < NS; ++cs)
-            if (run[rs][cs])
-                store_tile<acc_t, OUT>(job, c, are[rs][cs], aim[rs][cs], bk.I0 * 2 + wr * SB + rs * 32,
-                                       bk.J0 * 2 + wc * SB + cs * 32, lane);
+            for (int cs = 0; cs < NS; ++cs)
+                if (run[rs][cs])
+                    store_tile_lds<acc_t, OUT>(job, c, are[rs][cs], aim[rs][cs], bk.I0 * 2 + wr * SB + rs * 32,
+                                               bk.J0 * 2 + wc * SB + cs * 32, lane, img);
+    } else {
+#pragma unroll
+        for (int rs = 0; rs < NS; ++rs)
+#pragma unroll
+            for (int cs = 0; cs < NS; ++cs)
+                if (run[rs][cs])
+                    store_tile<acc_t, OUT>(job, c, are[rs][cs], aim[rs][cs], bk.I0 * 2 + wr * SB + rs * 32,
+                                           bk.J0 * 2 + wc * SB + cs * 32, lane);
+    }
 }
 
 // Two workgroups of four waves per CU: both the staging LDS (<= 72 KiB each)
@@ -445,20 +582,13 @@ __global__ __launch_bounds__(256, 2) void kernel(Job job, int nwork) {
 
 template <int KIND, int SB, typename OUT>
 __global__ __launch_bounds__(256, 2) void kernel_batch(const Job *__restrict__ jobs, const Unit *__restrict__ units,
-                                                       int n_units, int *counter) {
+                                                       Queues q) {
     __shared__ __attribute__((aligned(16))) uint8_t lds[2 * Geo<KIND, SB>::STAGE_BYTES];
     __shared__ int next;
-    for (;;) {
-        if (threadIdx.x == 0) next = atomicAdd(counter, 1);
-        __syncthreads();
-        const int u = next;
-        __syncthreads();
-        if (u >= n_units) return;
-        const Unit un = units[u];
+    drain_queues(units, q, &next, [&](const Unit &un) {
         const Job job = jobs[un.item];
         unit<KIND, SB, OUT>(job, un.channel, un.bi, un.bj, lds);
-        __syncthreads();
-    }
+    });
 }
 
 template <int KIND, int SB, typename OUT>
@@ -468,10 +598,8 @@ hipError_t launch_t(const Job &job, hipStream_t stream) {
     return hipGetLastError();
 }
 template <int KIND, int SB, typename OUT>
-hipError_t launch_batch_t(const Job *jobs, const Unit *units, int n_units, int *counter, int grid,
-                          hipStream_t stream) {
-    hipLaunchKernelGGL((kernel_batch<KIND, SB, OUT>), dim3(grid), dim3(256), 0, stream, jobs, units, n_units,
-                       counter);
+hipError_t launch_batch_t(const Job *jobs, const Unit *units, Queues q, int grid, hipStream_t stream) {
+    hipLaunchKernelGGL((kernel_batch<KIND, SB, OUT>), dim3(grid), dim3(256), 0, stream, jobs, units, q);
     return hipGetLastError();
 }
 template <int KIND, int SB, typename OUT>
@@ -508,10 +636,10 @@ hipError_t launch_mfma(const Plan &plan, xc_in_type in_type, xc_out_type out_typ
 }
 
 hipError_t launch_mfma_batch(const Plan &plan, xc_in_type in_type, xc_out_type out_type, const Job *jobs,
-                             const Unit *units, int n_units, int *counter, int grid, hipStream_t stream) {
+                             const Unit *units, Queues q, int grid, hipStream_t stream) {
     using namespace mfma;
     const int sb = plan.block;
-    XC_MFMA_DISPATCH(launch_batch_t, jobs, units, n_units, counter, grid, stream)
+    XC_MFMA_DISPATCH(launch_batch_t, jobs, units, q, grid, stream)
     return hipErrorInvalidValue;
 }
 

@@ -80,8 +80,12 @@ __device__ __forceinline__ void gload(Pre<TS> &p, const Job &job, int c, int I0,
         const int s2 = task % (2 * SB);
         const int blk = s2 / SB;
         const int st = (blk ? J0 : I0) + s2 % SB;
+        // out-of-range samples read a clamped, valid address and become zeros
         const bool ok = !(blk && diag) && (t0 + t < job.T) && st < job.S;
-        p.v[k] = ok ? xs[row_offset(job, c, t0 + t) + st] : make_float4(0.f, 0.f, 0.f, 0.f);
+        const int tc = t0 + t < job.T ? t0 + t : job.T - 1;
+        const int sc = st < job.S ? st : 0;
+        const float4 v = xs[row_offset(job, c, tc) + sc];
+        p.v[k] = ok ? v : make_float4(0.f, 0.f, 0.f, 0.f);
     }
 }
 
@@ -146,7 +150,7 @@ __device__ __forceinline__ void wave_unit(const Job &job, int c, int bi, int bj,
     typedef Sched<DIAG, W> SC;
     constexpr int NT = SC::NT;
     const int lane = tid & 63;
-    const int grp = (tid >> 6) / 4;        // time group of this wave
+    const int grp = __builtin_amdgcn_readfirstlane((tid >> 6) / 4);   // time group (uniform per wave)
     const int r16 = lane & 15;
     const int kq = lane >> 4;              // time step within a k-step
     const int I0 = bi * SB, J0 = bj * SB;
@@ -267,7 +271,7 @@ __device__ __forceinline__ void wave_unit(const Job &job, int c, int bi, int bj,
 template <int TS>
 __device__ __forceinline__ void unit(const Job &job, int c, int bi, int bj, uint8_t *lds) {
     const int tid = threadIdx.x;
-    const int w = (tid >> 6) & 3;
+    const int w = __builtin_amdgcn_readfirstlane((tid >> 6) & 3);
     if (bi == bj) {
         switch (w) {
         case 0: wave_unit<true, 0, TS>(job, c, bi, bj, lds, tid); break;
@@ -299,21 +303,13 @@ __global__ __launch_bounds__(256 * TS, 2 / TS) void kernel(Job job, int nwork) {
 
 template <int TS>
 __global__ __launch_bounds__(256 * TS, 2 / TS) void kernel_batch(const Job *__restrict__ jobs,
-                                                                 const Unit *__restrict__ units, int n_units,
-                                                                 int *counter) {
+                                                                 const Unit *__restrict__ units, Queues q) {
     __shared__ __attribute__((aligned(16))) uint8_t lds[2 * stage<TS>()];
     __shared__ int next;
-    for (;;) {
-        if (threadIdx.x == 0) next = atomicAdd(counter, 1);
-        __syncthreads();
-        const int u = next;
-        __syncthreads();
-        if (u >= n_units) return;
-        const Unit un = units[u];
+    drain_queues(units, q, &next, [&](const Unit &un) {
         const Job job = jobs[un.item];
         unit<TS>(job, un.channel, un.bi, un.bj, lds);
-        __syncthreads();
-    }
+    });
 }
 
 }  // namespace mfma16
@@ -328,12 +324,12 @@ hipError_t launch_mfma16(const Plan &plan, const Job &job, hipStream_t stream) {
     return hipGetLastError();
 }
 
-hipError_t launch_mfma16_batch(const Plan &plan, const Job *jobs, const Unit *units, int n_units, int *counter,
-                               int grid, hipStream_t stream) {
+hipError_t launch_mfma16_batch(const Plan &plan, const Job *jobs, const Unit *units, Queues q, int grid,
+                               hipStream_t stream) {
     if (plan.time_split == 2) {
-        hipLaunchKernelGGL(mfma16::kernel_batch<2>, dim3(grid), dim3(512), 0, stream, jobs, units, n_units, counter);
+        hipLaunchKernelGGL(mfma16::kernel_batch<2>, dim3(grid), dim3(512), 0, stream, jobs, units, q);
     } else {
-        hipLaunchKernelGGL(mfma16::kernel_batch<1>, dim3(grid), dim3(256), 0, stream, jobs, units, n_units, counter);
+        hipLaunchKernelGGL(mfma16::kernel_batch<1>, dim3(grid), dim3(256), 0, stream, jobs, units, q);
     }
     return hipGetLastError();
 }

@@ -13,7 +13,9 @@
 // Section 4.5 does with the Cell's local store).  The first fold of an
 // integration overwrites instead of adding, so no clearing pass is needed.
 // A host function enqueued after each fold records its completion time on
-// the host clock; per-block latency = completion - arrival.
+// the host clock; per-block latency = completion - arrival, per-fold latency
+// = completion - arrival of the fold's last block (the deadline applies to
+// folds: finish before the next fold's blocks are all in).
 // Streams are admitted only if their device footprint fits the budget.
 #include <time.h>
 
@@ -301,25 +303,33 @@ xc_status xc_stream_stats(xc_server *srv, int32_t id, xc_latency_stats *stats) {
     if (!s) return set_error(XC_ERR_INVALID_ARG, "no open stream %d", id);
     hipError_t e = hipStreamSynchronize(s->hs);
     if (e != hipSuccess) return hip_error(e, "hipStreamSynchronize");
-    std::vector<double> lat;
+    std::vector<double> lat, flat;
     uint64_t t_first = UINT64_MAX, t_last = 0;
     for (auto &f : s->folds) {
         while (!__atomic_load_n(&f.rec->done, __ATOMIC_ACQUIRE)) {
         }
+        uint64_t last_arrival = 0;
         for (uint64_t a : f.arrivals) {
             lat.push_back(f.rec->done_ns > a ? (double)(f.rec->done_ns - a) * 1e-6 : 0.0);
             t_first = std::min(t_first, a);
+            last_arrival = std::max(last_arrival, a);
         }
+        if (!f.arrivals.empty())
+            flat.push_back(f.rec->done_ns > last_arrival ? (double)(f.rec->done_ns - last_arrival) * 1e-6 : 0.0);
         t_last = std::max(t_last, f.rec->done_ns);
     }
     const double deadline = 1e3 * s->d.block_period_s * s->d.blocks_per_fold;
     xc_latency_stats r{};
     r.blocks = (int64_t)lat.size();
+    r.folds = (int64_t)flat.size();
     r.deadline_ms = deadline;
     r.p50_ms = xc_quantile(lat.data(), (int64_t)lat.size(), 0.50);
     r.p99_ms = xc_quantile(lat.data(), (int64_t)lat.size(), 0.99);
     r.max_ms = lat.empty() ? NAN : *std::max_element(lat.begin(), lat.end());
-    for (double v : lat)
+    r.fold_p50_ms = xc_quantile(flat.data(), (int64_t)flat.size(), 0.50);
+    r.fold_p99_ms = xc_quantile(flat.data(), (int64_t)flat.size(), 0.99);
+    r.fold_max_ms = flat.empty() ? NAN : *std::max_element(flat.begin(), flat.end());
+    for (double v : flat)
         if (deadline > 0 && v > deadline) r.misses++;
     const double span = (t_last > t_first && t_first != UINT64_MAX) ? (double)(t_last - t_first) * 1e-9 : 0.0;
     r.tflops = span > 0 ? s->flops_per_fold * (double)s->folds.size() / span * 1e-12 : 0.0;

@@ -60,7 +60,7 @@ __device__ __forceinline__ void unit(const Job &job, int c, int bi, int bj, Stag
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const int wave = tid >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform across the wave
     const int ti = lane & 7;
     const int tj = lane >> 3;
     const int S = job.S;
@@ -195,21 +195,13 @@ __global__ __launch_bounds__(64 * TS) void kernel(Job job, int nwork) {
 // list is exhausted.  Every workgroup leaves once the counter passes n_units.
 template <int TS, int TC>
 __global__ __launch_bounds__(64 * TS) void kernel_batch(const Job *__restrict__ jobs,
-                                                         const Unit *__restrict__ units,
-                                                         int n_units, int *counter) {
+                                                         const Unit *__restrict__ units, Queues q) {
     __shared__ Stage<TC> st;
     __shared__ int next;
-    for (;;) {
-        if (threadIdx.x == 0) next = atomicAdd(counter, 1);
-        __syncthreads();
-        const int u = next;
-        __syncthreads();
-        if (u >= n_units) return;
-        const Unit un = units[u];
+    drain_queues(units, q, &next, [&](const Unit &un) {
         const Job job = jobs[un.item];
         unit<TS, TC>(job, un.channel, un.bi, un.bj, st);
-        __syncthreads();
-    }
+    });
 }
 
 template <int TS, int TC>
@@ -220,10 +212,8 @@ hipError_t launch_t(const Job &job, hipStream_t stream) {
 }
 
 template <int TS, int TC>
-hipError_t launch_batch_t(const Job *jobs, const Unit *units, int n_units, int *counter, int grid,
-                          hipStream_t stream) {
-    hipLaunchKernelGGL((kernel_batch<TS, TC>), dim3(grid), dim3(64 * TS), 0, stream, jobs, units,
-                       n_units, counter);
+hipError_t launch_batch_t(const Job *jobs, const Unit *units, Queues q, int grid, hipStream_t stream) {
+    hipLaunchKernelGGL((kernel_batch<TS, TC>), dim3(grid), dim3(64 * TS), 0, stream, jobs, units, q);
     return hipGetLastError();
 }
 
@@ -259,15 +249,15 @@ hipError_t launch_valu(const Plan &plan, const Job &job, hipStream_t stream) {
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_valu_batch(const Plan &plan, const Job *jobs, const Unit *units, int n_units,
-                             int *counter, int grid, hipStream_t stream) {
+hipError_t launch_valu_batch(const Plan &plan, const Job *jobs, const Unit *units, Queues q, int grid,
+                             hipStream_t stream) {
     const int ts = plan.time_split, tc = plan.time_chunk;
-    if (ts == 1 && tc == 16) return valu::launch_batch_t<1, 16>(jobs, units, n_units, counter, grid, stream);
-    if (ts == 2 && tc == 16) return valu::launch_batch_t<2, 16>(jobs, units, n_units, counter, grid, stream);
-    if (ts == 4 && tc == 16) return valu::launch_batch_t<4, 16>(jobs, units, n_units, counter, grid, stream);
-    if (ts == 2 && tc == 32) return valu::launch_batch_t<2, 32>(jobs, units, n_units, counter, grid, stream);
-    if (ts == 4 && tc == 32) return valu::launch_batch_t<4, 32>(jobs, units, n_units, counter, grid, stream);
-    if (ts == 8 && tc == 32) return valu::launch_batch_t<8, 32>(jobs, units, n_units, counter, grid, stream);
+    if (ts == 1 && tc == 16) return valu::launch_batch_t<1, 16>(jobs, units, q, grid, stream);
+    if (ts == 2 && tc == 16) return valu::launch_batch_t<2, 16>(jobs, units, q, grid, stream);
+    if (ts == 4 && tc == 16) return valu::launch_batch_t<4, 16>(jobs, units, q, grid, stream);
+    if (ts == 2 && tc == 32) return valu::launch_batch_t<2, 32>(jobs, units, q, grid, stream);
+    if (ts == 4 && tc == 32) return valu::launch_batch_t<4, 32>(jobs, units, q, grid, stream);
+    if (ts == 8 && tc == 32) return valu::launch_batch_t<8, 32>(jobs, units, q, grid, stream);
     return hipErrorInvalidValue;
 }
 

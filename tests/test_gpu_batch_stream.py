@@ -148,8 +148,12 @@ def test_stream_integrations_match_oracle(kind):
                 assert rel_err(gpu_vis_numpy(got), ref) <= 1e-5
     st = srv.stats(sid)
     assert st["blocks"] == bpi * n_int and st["integrations"] == n_int
+    assert st["folds"] == bpi * n_int // k
     assert 0 <= st["p50_ms"] <= st["p99_ms"] <= st["max_ms"]
+    assert 0 <= st["fold_p50_ms"] <= st["fold_p99_ms"] <= st["fold_max_ms"] <= st["max_ms"]
     assert st["deadline_ms"] == pytest.approx(2.0)
+    srv.reset_stats(sid)
+    assert srv.stats(sid)["blocks"] == 0
     srv.close_stream(sid)
     srv.close()
 
