@@ -36,6 +36,13 @@ __host__ __device__ inline size_t row_offset(const Job &job, int c, int t) {
     return (size_t)blk * job.bstride + ((size_t)c * job.tblk + (t - blk * job.tblk)) * job.S;
 }
 
+// True when time steps t0 .. t0 + n - 1 of a channel are consecutive rows in
+// memory (S station-samples apart): always for unblocked input, and for
+// time-blocked input when the steps lie in one block.
+__host__ __device__ inline bool rows_contiguous(const Job &job, int t0, int n) {
+    return job.bstride == 0 || t0 / job.tblk == (t0 + n - 1) / job.tblk;
+}
+
 // A work unit of a batch: item, channel, block pair.
 struct Unit {
     int32_t item, channel, bi, bj;

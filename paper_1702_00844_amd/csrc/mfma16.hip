@@ -89,6 +89,22 @@ __device__ __forceinline__ void gload(Pre<TS> &p, const Job &job, int c, int I0,
     }
 }
 
+// Loads of a full chunk whose time steps are consecutive rows in memory: one
+// uniform base address per chunk plus a per-thread byte offset fixed for the
+// whole unit, so a load needs no address arithmetic.  A thread's k-th sample
+// is 2 TS rows after its (k-1)-th.  Stations past the last one read the last
+// station's sample instead of zeros: they only feed output rows and columns
+// that are never stored.  skip (uniform per wave): the thread's samples are
+// block J's of a diagonal pair, which are block I's.
+template <int TS>
+__device__ __forceinline__ void gload_full(Pre<TS> &p, const uint8_t *base, uint32_t voff, uint32_t kstride,
+                                           bool skip) {
+    if (skip) return;
+#pragma unroll
+    for (int k = 0; k < Pre<TS>::N; ++k)
+        p.v[k] = *reinterpret_cast<const float4 *>(base + (size_t)k * kstride + voff);
+}
+
 template <int TS>
 __device__ __forceinline__ void lstore(const Pre<TS> &p, uint8_t *lds, bool diag, int tid) {
 #pragma unroll
@@ -157,12 +173,15 @@ __device__ __forceinline__ void wave_unit(const Job &job, int c, int bi, int bj,
     const int S = job.S;
     const int brow_base = DIAG ? 0 : RB;
 
-    // tiles past the last station are skipped (uniform per wave)
-    bool run[NT];
+    // Tiles past the last station are not stored.  A wave with any tile to
+    // store computes all of its tiles (on zero samples for the others): the
+    // MFMA stream then has no branches, and such waves only occur in the
+    // blocks at the end of the station range.
+    bool any = false;
 #pragma unroll
     for (int s = 0; s < NT; ++s) {
         const int tr = SC::arow(SC::a_of(s)), tc = SC::bcol(SC::b_of(s));
-        run[s] = (I0 * 2 + tr * 16 < 2 * S) && (J0 * 2 + tc * 16 < 2 * S);
+        any |= (I0 * 2 + tr * 16 < 2 * S) && (J0 * 2 + tc * 16 < 2 * S);
     }
 
     v4f are[NT], aim[NT];
@@ -174,14 +193,27 @@ __device__ __forceinline__ void wave_unit(const Job &job, int c, int bi, int bj,
 
     constexpr int KT = kt<TS>();
     constexpr int STAGE = stage<TS>();
+    // this thread's sample in every chunk: row tid / 2 SB, station s2 of the pair
+    const int s2 = tid % (2 * SB);
+    const int st = (s2 < SB ? I0 : J0) + s2 % SB;
+    const uint32_t voff = (uint32_t)(((tid / (2 * SB)) * S + (st < S ? st : S - 1)) * 16);
+    const uint32_t kstride = (uint32_t)(2 * TS * S * 16);
+    const bool skip = DIAG && __builtin_amdgcn_readfirstlane(s2 >= SB);
+    const uint8_t *x8 = static_cast<const uint8_t *>(job.x);
+    auto load_chunk = [&](Pre<TS> &p, int t0) {
+        if (t0 + KT <= job.T && rows_contiguous(job, t0, KT))
+            gload_full<TS>(p, x8 + row_offset(job, c, t0) * 16, voff, kstride, skip);
+        else
+            gload<TS>(p, job, c, I0, J0, DIAG, t0, tid);
+    };
     Pre<TS> pre;
     const int nchunk = (job.T + KT - 1) / KT;
-    gload<TS>(pre, job, c, I0, J0, DIAG, 0, tid);
+    load_chunk(pre, 0);
     lstore<TS>(pre, lds, DIAG, tid);
     __syncthreads();
     for (int ch = 0; ch < nchunk; ++ch) {
         const uint8_t *buf = lds + (ch & 1) * STAGE;
-        if (ch + 1 < nchunk) gload<TS>(pre, job, c, I0, J0, DIAG, (ch + 1) * KT, tid);
+        if (ch + 1 < nchunk) load_chunk(pre, (ch + 1) * KT);
         // This group's k-steps of the chunk: ks = grp, grp + TS, ...  The next
         // k-step's fragments are read from LDS before the current k-step's
         // MFMAs are issued, and the MFMAs are ordered by product kind so that
@@ -197,32 +229,30 @@ __device__ __forceinline__ void wave_unit(const Job &job, int c, int bi, int bj,
             for (int k = 0; k < SC::NB; ++k)
                 b[k] = *reinterpret_cast<const float2 *>(buf + t * PITCH + (brow_base + SC::bcol(k) * 16 + r16) * 8);
         };
-        frag(grp, fa[0], fb[0]);
+        if (any) {
+            frag(grp, fa[0], fb[0]);
 #pragma unroll
-        for (int i = 0; i < NK; ++i) {
-            const int cur = i & 1;
-            if (i + 1 < NK) frag(grp + (i + 1) * TS, fa[cur ^ 1], fb[cur ^ 1]);
-            const float2(&a)[SC::NA] = fa[cur];
-            const float2(&b)[SC::NB] = fb[cur];
+            for (int i = 0; i < NK; ++i) {
+                const int cur = i & 1;
+                if (i + 1 < NK) frag(grp + (i + 1) * TS, fa[cur ^ 1], fb[cur ^ 1]);
+                const float2(&a)[SC::NA] = fa[cur];
+                const float2(&b)[SC::NB] = fb[cur];
 #pragma unroll
-            for (int s = 0; s < NT; ++s)
-                if (run[s])
+                for (int s = 0; s < NT; ++s)
                     are[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[SC::a_of(s)].x, b[SC::b_of(s)].x, are[s], 0, 0, 0);
 #pragma unroll
-            for (int s = 0; s < NT; ++s)
-                if (run[s])
+                for (int s = 0; s < NT; ++s)
                     aim[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[SC::a_of(s)].y, b[SC::b_of(s)].x, aim[s], 0, 0, 0);
 #pragma unroll
-            for (int s = 0; s < NT; ++s)
-                if (run[s])
+                for (int s = 0; s < NT; ++s)
                     are[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[SC::a_of(s)].y, b[SC::b_of(s)].y, are[s], 0, 0, 0);
-            float nby[SC::NB];
+                float nby[SC::NB];
 #pragma unroll
-            for (int k = 0; k < SC::NB; ++k) nby[k] = -b[k].y;
+                for (int k = 0; k < SC::NB; ++k) nby[k] = -b[k].y;
 #pragma unroll
-            for (int s = 0; s < NT; ++s)
-                if (run[s])
+                for (int s = 0; s < NT; ++s)
                     aim[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[SC::a_of(s)].x, nby[SC::b_of(s)], aim[s], 0, 0, 0);
+            }
         }
         if (ch + 1 < nchunk) lstore<TS>(pre, lds + ((ch & 1) ^ 1) * STAGE, DIAG, tid);
         __syncthreads();
@@ -263,7 +293,7 @@ __device__ __forceinline__ void wave_unit(const Job &job, int c, int bi, int bj,
     if (grp != 0) return;
 #pragma unroll
     for (int s = 0; s < NT; ++s)
-        if (run[s])
+        if (I0 * 2 + SC::arow(SC::a_of(s)) * 16 < 2 * S && J0 * 2 + SC::bcol(SC::b_of(s)) * 16 < 2 * S)
             store_tile(job, c, are[s], aim[s], I0 * 2 + SC::arow(SC::a_of(s)) * 16,
                        J0 * 2 + SC::bcol(SC::b_of(s)) * 16, lane);
 }
