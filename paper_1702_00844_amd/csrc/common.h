@@ -95,6 +95,17 @@ hipError_t launch_valu(const Plan &plan, const Job &job, hipStream_t stream);
 hipError_t launch_mfma(const Plan &plan, xc_in_type in_type, xc_out_type out_type,
                        const Job &job, hipStream_t stream);
 
+// int8 samples on 64-station blocks staged straight from HBM to LDS
+// (n_stations % 4 == 0; selected by time_chunk 32).
+hipError_t launch_mfma_dma(xc_out_type out_type, const Job &job, hipStream_t stream);
+hipError_t launch_mfma_dma_batch(xc_out_type out_type, const Job *jobs, const Unit *units, Queues q, int grid,
+                                 hipStream_t stream);
+int occupancy_mfma_dma_batch(xc_out_type out_type);
+// True when the plan runs the direct-to-LDS int8 kernel.
+inline bool plan_is_dma(const Plan &p, xc_in_type in_type) {
+    return p.kernel == XC_KERNEL_MFMA && in_type == XC_IN_CI8 && p.block == 64 && p.time_chunk == 32;
+}
+
 // FP32 samples on 16x16x4 matrix-core tiles (64-station blocks).
 hipError_t launch_mfma16(const Plan &plan, const Job &job, hipStream_t stream);
 hipError_t launch_mfma16_batch(const Plan &plan, const Job *jobs, const Unit *units, Queues q, int grid,

@@ -106,17 +106,31 @@ __device__ __forceinline__ void unit(const Job &job, int c, int bi, int bj, uint
     __syncthreads();
     for (int ch = 0; ch < nchunk; ++ch) {
         const int buf = ch & 1;
-        if (ch + 1 < nchunk) load_chunk(pre, (ch + 1) * G::KT);
+        const bool more = ch + 1 < nchunk;
+        uint8_t *next = lds + (buf ^ 1) * G::STAGE_BYTES;
+        if (more) load_chunk(pre, (ch + 1) * G::KT);
         // A wave with any tile to do computes all of its tiles: the skipped ones
         // (below the diagonal or past the last station) only occur in waves
         // that are not the slowest of their workgroup, so this costs no time
-        // and keeps the MFMA stream free of branches.
-        if (any) compute_chunk<KIND, SB, true>(lds + buf * G::STAGE_BYTES, are, aim, arow0, brow0, run, lane);
-        if (ch + 1 < nchunk) lstore<KIND, SB>(pre, lds + (buf ^ 1) * G::STAGE_BYTES, bk, tid);
+        // and keeps the MFMA stream free of branches.  The next chunk goes to
+        // the other buffer (free since the last barrier) half-way through.
+        if (any)
+            compute_chunk<KIND, SB, true>(lds + buf * G::STAGE_BYTES, are, aim, arow0, brow0, run, lane, [&] {
+                if (more) lstore<KIND, SB>(pre, next, bk, tid);
+            });
+        else if (more)
+            lstore<KIND, SB>(pre, next, bk, tid);
         __syncthreads();
     }
 
     if (!any) return;
+    if constexpr (KIND == K_I8) {
+        // the int8 imaginary accumulators hold minus the imaginary part
+#pragma unroll
+        for (int rs = 0; rs < NS; ++rs)
+#pragma unroll
+            for (int cs = 0; cs < NS; ++cs) aim[rs][cs] = -aim[rs][cs];
+    }
     if constexpr (SB == 64) {
         // the staging buffers are free after the last barrier: one image region per wave
         static_assert(4 * IMG_BYTES <= 2 * G::STAGE_BYTES, "tile images must fit the staging area");

@@ -213,7 +213,9 @@ __device__ __forceinline__ void wave_unit(const Job &job, int c, int bi, int bj,
     __syncthreads();
     for (int ch = 0; ch < nchunk; ++ch) {
         const uint8_t *buf = lds + (ch & 1) * STAGE;
-        if (ch + 1 < nchunk) load_chunk(pre, (ch + 1) * KT);
+        const bool more = ch + 1 < nchunk;
+        uint8_t *next = lds + ((ch & 1) ^ 1) * STAGE;
+        if (more) load_chunk(pre, (ch + 1) * KT);
         // This group's k-steps of the chunk: ks = grp, grp + TS, ...  The next
         // k-step's fragments are read from LDS before the current k-step's
         // MFMAs are issued, and the MFMAs are ordered by product kind so that
@@ -252,9 +254,13 @@ __device__ __forceinline__ void wave_unit(const Job &job, int c, int bi, int bj,
 #pragma unroll
                 for (int s = 0; s < NT; ++s)
                     aim[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[SC::a_of(s)].x, nby[SC::b_of(s)], aim[s], 0, 0, 0);
+                // the next chunk goes to the other buffer (free since the last
+                // barrier) behind this wave's last queued MFMAs
+                if (i == NK - 1 && more) lstore<TS>(pre, next, DIAG, tid);
             }
+        } else if (more) {
+            lstore<TS>(pre, next, DIAG, tid);
         }
-        if (ch + 1 < nchunk) lstore<TS>(pre, lds + ((ch & 1) ^ 1) * STAGE, DIAG, tid);
         __syncthreads();
     }
 

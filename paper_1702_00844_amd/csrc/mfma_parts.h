@@ -58,6 +58,17 @@ __device__ __forceinline__ uint32_t conj_swap_i8(uint32_t w) {
     // bytes: [re0 im0 re1 im1] -> [-im0 re0 -im1 re1]
     return __builtin_amdgcn_perm(neg, w, 0x02070005u);
 }
+// (re, im) pairs -> (im, -re) pairs, i.e. -i times the conjugate swap above:
+// products with it accumulate minus the imaginary part.  Each 16-bit half
+// h = re + 256 im times 0xff00 is 256 (-re) modulo 2^16; adding im (moved to
+// the low byte by a permute) completes the pair.  Two instructions per word.
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t conj_neg_i8(uint32_t w) {
+    const uint32_t im = __builtin_amdgcn_perm(0u, w, 0x0c030c01u);   // [im0 0 im1 0]
+    const u16x2 h = __builtin_bit_cast(u16x2, w);
+    const u16x2 r = h * (u16x2){0xff00, 0xff00} + __builtin_bit_cast(u16x2, im);
+    return __builtin_bit_cast(uint32_t, r);
+}
 __device__ __forceinline__ uint32_t conj_swap_h(uint32_t w) {
     // halves: [re im] -> [-im re]   (sign-bit flip is exact negation)
     const uint32_t sw = __builtin_amdgcn_perm(w, w, 0x01000302u);
@@ -297,11 +308,12 @@ __device__ __forceinline__ void lstore(const Pre<KIND, SB> &p, uint8_t *lds, con
 // One chunk of MFMAs for one wave's quadrant.  ALL: every tile of the quadrant
 // is computed (no per-tile checks in the instruction stream); otherwise tiles
 // with run[] false are skipped.  The fragments of the next k-step are read
-// from LDS before the current k-step's MFMAs are issued.
-template <int KIND, int SB, bool ALL>
+// from LDS before the current k-step's MFMAs are issued.  mid() is called
+// half-way through the k-steps, behind the MFMAs queued so far.
+template <int KIND, int SB, bool ALL, typename MID>
 __device__ __forceinline__ void compute_chunk(const uint8_t *lds, typename Acc<KIND>::type (&are)[SB / 32][SB / 32],
                                               typename Acc<KIND>::type (&aim)[SB / 32][SB / 32], int arow0,
-                                              int brow0, const bool (&run)[SB / 32][SB / 32], int lane) {
+                                              int brow0, const bool (&run)[SB / 32][SB / 32], int lane, MID &&mid) {
     typedef Geo<KIND, SB> G;
     constexpr int NS = G::NS;
     const int r32 = lane & 31;
@@ -328,6 +340,7 @@ __device__ __forceinline__ void compute_chunk(const uint8_t *lds, typename Acc<K
                     aim[rs][cs] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[rs].x, -b[cs].y, aim[rs][cs], 0, 0, 0);
                 }
             }
+            if (ks == G::KT / 4 - 1) mid();
         }
     } else {
         constexpr int NSTEP = G::KT / G::STEP_T;  // 4
@@ -354,7 +367,7 @@ __device__ __forceinline__ void compute_chunk(const uint8_t *lds, typename Acc<K
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
                     const uint32_t w = (uint32_t)b[cs][e];
-                    bi[cs][e] = (int)(KIND == K_I8 ? conj_swap_i8(w) : conj_swap_h(w));
+                    bi[cs][e] = (int)(KIND == K_I8 ? conj_neg_i8(w) : conj_swap_h(w));
                 }
             // real parts of every tile first, then imaginary parts
 #pragma unroll
@@ -387,6 +400,7 @@ __device__ __forceinline__ void compute_chunk(const uint8_t *lds, typename Acc<K
                             __builtin_bit_cast(v8bf, a[rs]), __builtin_bit_cast(v8bf, bi[cs]), aim[rs][cs], 0, 0, 0);
                 }
             }
+            if (ks == NSTEP / 2 - 1) mid();
         }
     }
 }

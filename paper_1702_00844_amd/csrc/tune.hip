@@ -13,6 +13,10 @@ static std::vector<xc_config> candidates(xc_in_type in_type) {
     std::vector<xc_config> v;
     v.push_back(xc_config{XC_KERNEL_MFMA, 32, 0, 0});
     v.push_back(xc_config{XC_KERNEL_MFMA, 64, 0, 1});
+    if (in_type == XC_IN_CI8) {   // both int8 staging schemes (the 32-step one needs S % 4 == 0)
+        v.push_back(xc_config{XC_KERNEL_MFMA, 64, 32, 1});
+        v.push_back(xc_config{XC_KERNEL_MFMA, 64, 64, 1});
+    }
     if (in_type == XC_IN_CF32) v.push_back(xc_config{XC_KERNEL_MFMA, 64, 0, 2});
     if (in_type == XC_IN_CF32) {
         const int opts[][2] = {{16, 1}, {16, 2}, {16, 4}, {32, 2}, {32, 4}, {32, 8}};

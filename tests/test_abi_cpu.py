@@ -121,8 +121,18 @@ def test_config_resolution():
     assert r == {"kernel": 2, "block": 32, "time_chunk": 16, "time_split": 1}
     with pytest.raises(xe.XengineError):
         xe.resolve_config((_lib.XC_IN_CI8, 4, 16, 8, 2), _lib.XC_OUT_CI32, config={"kernel": 2, "time_split": 2})
+    # int8: 32-step chunks (staged straight into LDS) when n_stations % 4 == 0,
+    # otherwise 64-step chunks staged through registers
     r = xe.resolve_config((_lib.XC_IN_CI8, 1024, 1024, 256, 2), _lib.XC_OUT_CI32)
+    assert r == {"kernel": 2, "block": 64, "time_chunk": 32, "time_split": 1}
+    r = xe.resolve_config((_lib.XC_IN_CI8, 8, 64, 70, 2), _lib.XC_OUT_CI32)
     assert r == {"kernel": 2, "block": 64, "time_chunk": 64, "time_split": 1}
+    r = xe.resolve_config((_lib.XC_IN_CI8, 8, 64, 68, 2), _lib.XC_OUT_CI32, config={"kernel": 2, "time_chunk": 64})
+    assert r == {"kernel": 2, "block": 64, "time_chunk": 64, "time_split": 1}
+    with pytest.raises(xe.XengineError):
+        xe.resolve_config((_lib.XC_IN_CI8, 8, 64, 70, 2), config={"kernel": 2, "time_chunk": 32})
+    with pytest.raises(xe.XengineError):
+        xe.resolve_config((_lib.XC_IN_CI8, 8, 64, 68, 2), config={"kernel": 2, "block": 32, "time_chunk": 32})
     r = xe.resolve_config((_lib.XC_IN_CF16, 1024, 1024, 256, 2))
     assert r == {"kernel": 2, "block": 64, "time_chunk": 32, "time_split": 1}
     with pytest.raises(xe.XengineError):

@@ -16,6 +16,8 @@ pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
 
 SHAPES = [(24, 5, 768), (70, 3, 300), (130, 2, 128), (8, 16, 256), (1, 4, 33), (65, 1, 1000)]
+# station counts that are multiples of 4: int8 batches run the direct-to-LDS kernel
+SHAPES4 = [(24, 5, 768), (68, 3, 300), (132, 2, 128), (8, 16, 256), (4, 4, 33), (64, 1, 1000)]
 
 
 def _make(kind, shapes, seed=40):
@@ -46,22 +48,23 @@ def _check(kind, xs, outs, base=None):
             assert rel_err(got, ref) <= 1e-5, k
 
 
-@pytest.mark.parametrize("kind,config", [
-    ("ci8", None), ("cf16", None), ("cbf16", None),
-    ("cf32", {"kernel": xe.XC_KERNEL_MFMA, "block": 32}),
-    ("cf32", {"kernel": xe.XC_KERNEL_MFMA, "block": 64, "time_split": 1}),
-    ("cf32", {"kernel": xe.XC_KERNEL_MFMA, "block": 64, "time_split": 2}),
-    ("cf32", {"kernel": xe.XC_KERNEL_VALU, "time_chunk": 32, "time_split": 8}),
-    ("cf32", {"kernel": xe.XC_KERNEL_VALU, "time_chunk": 16, "time_split": 1}),
-], ids=["ci8", "cf16", "cbf16", "f32mfma32", "f32mfma64ts1", "f32mfma64ts2", "valu_ts8", "valu_ts1"])
+@pytest.mark.parametrize("kind,config,shapes", [
+    ("ci8", None, SHAPES4), ("ci8", None, SHAPES), ("cf16", None, SHAPES), ("cbf16", None, SHAPES),
+    ("cf32", {"kernel": xe.XC_KERNEL_MFMA, "block": 32}, SHAPES),
+    ("cf32", {"kernel": xe.XC_KERNEL_MFMA, "block": 64, "time_split": 1}, SHAPES),
+    ("cf32", {"kernel": xe.XC_KERNEL_MFMA, "block": 64, "time_split": 2}, SHAPES),
+    ("cf32", {"kernel": xe.XC_KERNEL_VALU, "time_chunk": 32, "time_split": 8}, SHAPES),
+    ("cf32", {"kernel": xe.XC_KERNEL_VALU, "time_chunk": 16, "time_split": 1}, SHAPES),
+], ids=["ci8_lds", "ci8_mixed", "cf16", "cbf16", "f32mfma32", "f32mfma64ts1", "f32mfma64ts2", "valu_ts8",
+        "valu_ts1"])
 @pytest.mark.parametrize("use_graph", [True, False], ids=["graph", "direct"])
-def test_batch_matches_oracle(kind, config, use_graph):
-    xs = _make(kind, SHAPES)
+def test_batch_matches_oracle(kind, config, shapes, use_graph):
+    xs = _make(kind, shapes)
     out_dtype = torch.int32 if kind == "ci8" else torch.complex64
     ot = xe.XC_OUT_CI32 if kind == "ci8" else xe.XC_OUT_CF32
-    outs = [torch.full(xe.vis_shape(s[1], s[0], ot), 7, dtype=out_dtype, device=DEV) for s in SHAPES]
+    outs = [torch.full(xe.vis_shape(s[1], s[0], ot), 7, dtype=out_dtype, device=DEV) for s in shapes]
     plan = xe.BatchPlan(xs, outs, config=config, use_graph=use_graph)
-    assert plan.units == len(xe.batch_worklist(SHAPES, xe.resolve_config(
+    assert plan.units == len(xe.batch_worklist(shapes, xe.resolve_config(
         (xe.in_type_of(xs[0])[0], 1, 1, 1, 2), ot, config)["block"]))
     for rep in range(3):
         for o in outs:
@@ -105,9 +108,10 @@ def test_autotune_and_cache(tmp_path):
     assert rel_err(gpu_vis_numpy(v), oracle_vis(x)) <= 1e-5
 
 
-@pytest.mark.parametrize("kind", ["ci8", "cf32"])
-def test_stream_integrations_match_oracle(kind):
-    S, C, bt, bpi, k = 20, 3, 32, 6, 2
+# block_times 24: the int8 kernel's 32-step chunks straddle the ring slots of a fold
+@pytest.mark.parametrize("kind,bt", [("ci8", 32), ("ci8", 24), ("cf32", 32)])
+def test_stream_integrations_match_oracle(kind, bt):
+    S, C, bpi, k = 20, 3, 6, 2
     n_int = 2
     srv = xe.Server()
     in_type = xe.XC_IN_CI8 if kind == "ci8" else xe.XC_IN_CF32

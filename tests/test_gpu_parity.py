@@ -52,12 +52,21 @@ def test_cf32_parity(shape, cfg):
     assert_hermitian_autos(got, S)
 
 
-@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "S%d_C%d_T%d" % s)
+# int8 kernels: the default (staged straight into LDS when S % 4 == 0), the
+# register-staged one on 64-station blocks, and 32-station blocks; extra shapes
+# with S % 4 == 0 give the direct-to-LDS kernel diagonal and off-diagonal
+# blocks, ragged blocks and ragged time tails
+I8_CFGS = [None, dict(kernel=xe.XC_KERNEL_MFMA, block=64, time_chunk=64), dict(kernel=xe.XC_KERNEL_MFMA, block=32)]
+I8_SHAPES = SHAPES + [(4, 1, 5), (68, 2, 100), (128, 1, 97), (132, 2, 33), (192, 1, 64)]
+
+
+@pytest.mark.parametrize("shape", I8_SHAPES, ids=lambda s: "S%d_C%d_T%d" % s)
 @pytest.mark.parametrize("out_type", [xe.XC_OUT_CI32, xe.XC_OUT_CF32], ids=["ci32", "cf32"])
-def test_ci8_bit_exact(shape, out_type):
+@pytest.mark.parametrize("cfg", I8_CFGS, ids=["default", "b64_regs", "b32"])
+def test_ci8_bit_exact(shape, out_type, cfg):
     S, C, T = shape
     x = inputs.ci8_gaussian(C, T, S, seed=S + 7 * T, device=DEV)
-    v = xe.correlate(x, out_type=out_type)
+    v = xe.correlate(x, out_type=out_type, config=cfg)
     torch.cuda.synchronize()
     ref = oracle_vis(x)
     got = gpu_vis_numpy(v)
@@ -144,8 +153,9 @@ def test_accumulate_mode(cfg):
     assert rel_err(gpu_vis_numpy(v), ref) <= FP32_TOL
 
 
-def test_accumulate_int_exact():
-    S, C, T = 66, 2, 128
+@pytest.mark.parametrize("S", [66, 68])
+def test_accumulate_int_exact(S):
+    C, T = 2, 128
     x1 = inputs.ci8_gaussian(C, T, S, seed=21, device=DEV)
     x2 = inputs.ci8_gaussian(C, T, S, seed=22, device=DEV)
     v = xe.correlate(x1)
@@ -154,9 +164,10 @@ def test_accumulate_int_exact():
     assert np.array_equal(gpu_vis_numpy(v), oracle_vis(torch.cat([x1, x2], dim=1)))
 
 
-def test_int32_worst_case():
+@pytest.mark.parametrize("S", [9, 12])
+def test_int32_worst_case(S):
     """All samples (127, -127): V = 2 * 127^2 * T exactly, at a ragged T."""
-    S, C, T = 9, 1, 1000
+    C, T = 1, 1000
     x = torch.empty((C, T, S, 2, 2), dtype=torch.int8, device=DEV)
     x[..., 0] = 127
     x[..., 1] = -127
@@ -208,9 +219,10 @@ def test_config3_sampled_channels():
     x = inputs.ci8_gaussian(C, T, S, seed=3, device=DEV)
     chans = [0, 1, 517, C - 1]
     ref = oracle_vis(x, chans)
-    v = xe.correlate(x)
-    assert np.array_equal(gpu_vis_numpy(v, chans), ref)
-    del v
+    for cfg in I8_CFGS[:2]:
+        v = xe.correlate(x, config=cfg)
+        assert np.array_equal(gpu_vis_numpy(v, chans), ref)
+        del v
     refc = ref[..., 0] + 1j * ref[..., 1]
     for dtype in (torch.float16, torch.bfloat16):
         vh = xe.correlate(x.to(dtype))
