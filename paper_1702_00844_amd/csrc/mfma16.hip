@@ -15,11 +15,18 @@
 //  * TS = 2 splits every staged chunk of time steps between two groups of four
 //    waves (two waves per SIMD); the second group's partial sums are added
 //    into the first's through LDS before the single store.
-//  * Samples are staged per chunk of 16 (or 32) time steps through LDS in their
-//    time-major layout, double-buffered through registers.  A fragment is one
-//    (re, im) sample per lane: lane l holds row l % 16 at time step l / 16 of
-//    the k-step, for both the A (block I) and B (block J) operands.
+//  * Samples go from HBM straight into LDS (global_load_lds, see lds_dma.h),
+//    in their time-major layout: one 1 KiB row per block and time step (block
+//    I only on the diagonal, I then J elsewhere).  Two stages of 64 KiB (two
+//    time groups) or 32 KiB (one) alternate: the next chunk is copied while
+//    the current one is computed, with one barrier per chunk.  A diagonal
+//    unit stages half the bytes per time step, so its chunks are twice as
+//    long (64 or 32 time steps against 32 or 16).
+//  * A fragment is one (re, im) sample per lane: lane l holds row l % 16 at
+//    time step l / 16 of the k-step, for both the A (block I) and B (block J)
+//    operands.
 #include "common.h"
+#include "lds_dma.h"
 
 namespace xc {
 namespace mfma16 {
@@ -28,13 +35,16 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 
 constexpr int SB = 64;              // stations per block
 constexpr int RB = 2 * SB;          // rows per block
-constexpr int PITCH = 2 * RB * 8;   // bytes per staged time step (I then J rows)
-// time steps per staged chunk: 16, or 32 when two wave groups share the
-// workgroup (one workgroup per CU then, so the larger buffers fit)
+constexpr int BROW = RB * 8;        // bytes of one block's time step (1 KiB)
+// bytes per stage: 64 KiB with two time groups (one workgroup per CU), 32 KiB
+// with one (two workgroups per CU)
 template <int TS>
-constexpr int kt() { return TS == 2 ? 32 : 16; }
-template <int TS>
-constexpr int stage() { return kt<TS>() * PITCH; }
+constexpr int stage() { return TS == 2 ? 65536 : 32768; }
+// bytes per staged time step: block I only on the diagonal, I then J elsewhere
+template <bool DIAG>
+constexpr int pitch() { return DIAG ? BROW : 2 * BROW; }
+template <bool DIAG, int TS>
+constexpr int kt() { return stage<TS>() / pitch<DIAG>(); }
 
 // Tile coordinates (tile row, tile column) of wave w's slot s.
 template <bool DIAG, int W>
@@ -60,62 +70,6 @@ struct Sched<true, W> {
     __device__ static constexpr int arow(int a) { return a == 0 ? W : 7 - W; }
     __device__ static constexpr int bcol(int b) { return LO + b; }
 };
-
-// Staging: the chunk's time steps x 2 SB station samples (float4 = both pols) are
-// spread over all 256 TS threads of the workgroup.
-template <int TS>
-struct Pre {
-    static constexpr int N = kt<TS>() * 2 * SB / (256 * TS);
-    float4 v[N];
-};
-
-template <int TS>
-__device__ __forceinline__ void gload(Pre<TS> &p, const Job &job, int c, int I0, int J0, bool diag, int t0,
-                                      int tid) {
-    const float4 *xs = static_cast<const float4 *>(job.x);
-#pragma unroll
-    for (int k = 0; k < Pre<TS>::N; ++k) {
-        const int task = tid + 256 * TS * k;
-        const int t = task / (2 * SB);
-        const int s2 = task % (2 * SB);
-        const int blk = s2 / SB;
-        const int st = (blk ? J0 : I0) + s2 % SB;
-        // out-of-range samples read a clamped, valid address and become zeros
-        const bool ok = !(blk && diag) && (t0 + t < job.T) && st < job.S;
-        const int tc = t0 + t < job.T ? t0 + t : job.T - 1;
-        const int sc = st < job.S ? st : 0;
-        const float4 v = xs[row_offset(job, c, tc) + sc];
-        p.v[k] = ok ? v : make_float4(0.f, 0.f, 0.f, 0.f);
-    }
-}
-
-// Loads of a full chunk whose time steps are consecutive rows in memory: one
-// uniform base address per chunk plus a per-thread byte offset fixed for the
-// whole unit, so a load needs no address arithmetic.  A thread's k-th sample
-// is 2 TS rows after its (k-1)-th.  Stations past the last one read the last
-// station's sample instead of zeros: they only feed output rows and columns
-// that are never stored.  skip (uniform per wave): the thread's samples are
-// block J's of a diagonal pair, which are block I's.
-template <int TS>
-__device__ __forceinline__ void gload_full(Pre<TS> &p, const uint8_t *base, uint32_t voff, uint32_t kstride,
-                                           bool skip) {
-    if (skip) return;
-#pragma unroll
-    for (int k = 0; k < Pre<TS>::N; ++k)
-        p.v[k] = *reinterpret_cast<const float4 *>(base + (size_t)k * kstride + voff);
-}
-
-template <int TS>
-__device__ __forceinline__ void lstore(const Pre<TS> &p, uint8_t *lds, bool diag, int tid) {
-#pragma unroll
-    for (int k = 0; k < Pre<TS>::N; ++k) {
-        const int task = tid + 256 * TS * k;
-        const int t = task / (2 * SB);
-        const int s2 = task % (2 * SB);
-        if (s2 >= SB && diag) continue;
-        *reinterpret_cast<float4 *>(lds + t * PITCH + s2 * 16) = p.v[k];
-    }
-}
 
 template <typename OUT>
 struct Out;
@@ -191,31 +145,57 @@ __device__ __forceinline__ void wave_unit(const Job &job, int c, int bi, int bj,
         aim[s] = v4f{0.f, 0.f, 0.f, 0.f};
     }
 
-    constexpr int KT = kt<TS>();
+    constexpr int PITCH = pitch<DIAG>();
+    constexpr int KT = kt<DIAG, TS>();
     constexpr int STAGE = stage<TS>();
-    // this thread's sample in every chunk: row tid / 2 SB, station s2 of the pair
-    const int s2 = tid % (2 * SB);
-    const int st = (s2 < SB ? I0 : J0) + s2 % SB;
-    const uint32_t voff = (uint32_t)(((tid / (2 * SB)) * S + (st < S ? st : S - 1)) * 16);
-    const uint32_t kstride = (uint32_t)(2 * TS * S * 16);
-    const bool skip = DIAG && __builtin_amdgcn_readfirstlane(s2 >= SB);
+    // Copies: a stage holds KT rows of one block (diagonal) or 2 KT rows
+    // alternating I and J; each of the 4 TS waves copies 8 of them per chunk,
+    // one 1 KiB row (64 stations x 16 bytes, lane = station) per instruction.
+    // Stations past the last one copy the last station: they only feed output
+    // rows and columns that are never stored.
+    constexpr int NW = 4 * TS;
+    constexpr int NCOPY = (DIAG ? KT : 2 * KT) / NW;
+    static_assert(NCOPY == 8, "eight copies per wave and chunk");
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int blk = DIAG ? 0 : (wave & 1);                  // NW is even: row parity = wave parity
+    const int trow0 = DIAG ? wave : (wave >> 1);            // time row of copy 0
+    constexpr int TSTEP = DIAG ? NW : NW / 2;               // time rows between copies
+    const int st = (blk ? J0 : I0) + lane;
+    const int stc = st < S ? st : S - 1;
+    const uint32_t off = (uint32_t)((trow0 * S + stc) * 16);
+    const uint32_t step = (uint32_t)(TSTEP * S * 16);
+    const uint32_t dst0 = lds_addr(lds) + trow0 * PITCH + blk * BROW;
     const uint8_t *x8 = static_cast<const uint8_t *>(job.x);
-    auto load_chunk = [&](Pre<TS> &p, int t0) {
-        if (t0 + KT <= job.T && rows_contiguous(job, t0, KT))
-            gload_full<TS>(p, x8 + row_offset(job, c, t0) * 16, voff, kstride, skip);
-        else
-            gload<TS>(p, job, c, I0, J0, DIAG, t0, tid);
+    const int T = job.T;
+    auto issue = [&](int ch) {
+        const int t0 = ch * KT;
+        const uint32_t dst = dst0 + (ch & 1) * STAGE;
+        if (t0 + KT <= T && rows_contiguous(job, t0, KT)) {
+            const uint8_t *src = x8 + row_offset(job, c, t0) * 16 + off;
+#pragma unroll
+            for (int k = 0; k < NCOPY; ++k) dma16(src + k * step, dst + k * TSTEP * PITCH);
+        } else {
+#pragma unroll
+            for (int k = 0; k < NCOPY; ++k) {
+                const int t = t0 + trow0 + k * TSTEP;
+                const void *src = t < T ? static_cast<const void *>(x8 + (row_offset(job, c, t) + stc) * 16)
+                                        : static_cast<const void *>(g_zero16);
+                dma16(src, dst + k * TSTEP * PITCH);
+            }
+        }
     };
-    Pre<TS> pre;
-    const int nchunk = (job.T + KT - 1) / KT;
-    load_chunk(pre, 0);
-    lstore<TS>(pre, lds, DIAG, tid);
-    __syncthreads();
+
+    const int nchunk = (T + KT - 1) / KT;
+    issue(0);
     for (int ch = 0; ch < nchunk; ++ch) {
+        // this wave's copies of chunk ch are the only ones pending; once every
+        // wave is past the barrier they are visible, and the other stage (chunk
+        // ch - 1) is free for chunk ch + 1
+        wait_vm<0>();
+        barrier_lds();
+        if (ch + 1 < nchunk) issue(ch + 1);
+        if (!any) continue;
         const uint8_t *buf = lds + (ch & 1) * STAGE;
-        const bool more = ch + 1 < nchunk;
-        uint8_t *next = lds + ((ch & 1) ^ 1) * STAGE;
-        if (more) load_chunk(pre, (ch + 1) * KT);
         // This group's k-steps of the chunk: ks = grp, grp + TS, ...  The next
         // k-step's fragments are read from LDS before the current k-step's
         // MFMAs are issued, and the MFMAs are ordered by product kind so that
@@ -231,38 +211,32 @@ __device__ __forceinline__ void wave_unit(const Job &job, int c, int bi, int bj,
             for (int k = 0; k < SC::NB; ++k)
                 b[k] = *reinterpret_cast<const float2 *>(buf + t * PITCH + (brow_base + SC::bcol(k) * 16 + r16) * 8);
         };
-        if (any) {
-            frag(grp, fa[0], fb[0]);
+        frag(grp, fa[0], fb[0]);
 #pragma unroll
-            for (int i = 0; i < NK; ++i) {
-                const int cur = i & 1;
-                if (i + 1 < NK) frag(grp + (i + 1) * TS, fa[cur ^ 1], fb[cur ^ 1]);
-                const float2(&a)[SC::NA] = fa[cur];
-                const float2(&b)[SC::NB] = fb[cur];
+        for (int i = 0; i < NK; ++i) {
+            const int cur = i & 1;
+            if (i + 1 < NK) frag(grp + (i + 1) * TS, fa[cur ^ 1], fb[cur ^ 1]);
+            const float2(&a)[SC::NA] = fa[cur];
+            const float2(&b)[SC::NB] = fb[cur];
 #pragma unroll
-                for (int s = 0; s < NT; ++s)
-                    are[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[SC::a_of(s)].x, b[SC::b_of(s)].x, are[s], 0, 0, 0);
+            for (int s = 0; s < NT; ++s)
+                are[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[SC::a_of(s)].x, b[SC::b_of(s)].x, are[s], 0, 0, 0);
 #pragma unroll
-                for (int s = 0; s < NT; ++s)
-                    aim[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[SC::a_of(s)].y, b[SC::b_of(s)].x, aim[s], 0, 0, 0);
+            for (int s = 0; s < NT; ++s)
+                aim[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[SC::a_of(s)].y, b[SC::b_of(s)].x, aim[s], 0, 0, 0);
 #pragma unroll
-                for (int s = 0; s < NT; ++s)
-                    are[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[SC::a_of(s)].y, b[SC::b_of(s)].y, are[s], 0, 0, 0);
-                float nby[SC::NB];
+            for (int s = 0; s < NT; ++s)
+                are[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[SC::a_of(s)].y, b[SC::b_of(s)].y, are[s], 0, 0, 0);
+            float nby[SC::NB];
 #pragma unroll
-                for (int k = 0; k < SC::NB; ++k) nby[k] = -b[k].y;
+            for (int k = 0; k < SC::NB; ++k) nby[k] = -b[k].y;
 #pragma unroll
-                for (int s = 0; s < NT; ++s)
-                    aim[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[SC::a_of(s)].x, nby[SC::b_of(s)], aim[s], 0, 0, 0);
-                // the next chunk goes to the other buffer (free since the last
-                // barrier) behind this wave's last queued MFMAs
-                if (i == NK - 1 && more) lstore<TS>(pre, next, DIAG, tid);
-            }
-        } else if (more) {
-            lstore<TS>(pre, next, DIAG, tid);
+            for (int s = 0; s < NT; ++s)
+                aim[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[SC::a_of(s)].x, nby[SC::b_of(s)], aim[s], 0, 0, 0);
         }
-        __syncthreads();
     }
+    // every wave is done with the stages before they are reused below
+    __syncthreads();
 
     if constexpr (TS > 1) {
         // group 1 hands its partial sums to group 0 through LDS (staging is free now)

@@ -21,15 +21,13 @@
 //  * Granule g of time row t is stored at granule g ^ 4 (t mod 4), so that the
 //    four time rows read by one transpose group fall on different banks.
 //
-// The compiler does not see these copies (they are issued from inline
-// assembly, so that it does not wait for all of them before every LDS read);
-// every wait for them is explicit: a wave's copies of a chunk are complete when
-// vmcnt has dropped to the number of copies it issued after them.
+// The copies are issued as in lds_dma.h: every wait for them is explicit.
 //
 // Requires n_stations % 4 == 0 (whole granules); other station counts use the
 // register-staged kernel.
 #include "common.h"
 
+#include "lds_dma.h"
 #include "mfma_parts.h"
 
 namespace xc {
@@ -53,24 +51,14 @@ typedef short v4s __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(3))) uint8_t lds_u8;
 typedef __attribute__((address_space(3))) v4s lds_v4s;
 
-// Source of the time steps past the end of a channel.
-__device__ __attribute__((aligned(16))) uint32_t g_zero16[4] = {0u, 0u, 0u, 0u};
-
-// Lane L's 16-byte granule at src goes to LDS byte address lds + 16 L.
-__device__ __forceinline__ void dma16(const void *src, uint32_t lds) {
-    asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off" ::"v"(src), "s"(lds)
-                 : "memory", "m0");
-}
-
 // Wait until at most n of this wave's vector-memory operations are pending
 // (n in {0, 2, 4, 8}).
-__device__ __forceinline__ void wait_vm(int n) {
-    constexpr int rest = (7 << 4) | (15 << 8);   // expcnt, lgkmcnt: no wait
+__device__ __forceinline__ void wait_vm_n(int n) {
     switch (n) {
-    case 0: __builtin_amdgcn_s_waitcnt(rest | 0); break;
-    case 2: __builtin_amdgcn_s_waitcnt(rest | 2); break;
-    case 4: __builtin_amdgcn_s_waitcnt(rest | 4); break;
-    default: __builtin_amdgcn_s_waitcnt(rest | 8); break;
+    case 0: wait_vm<0>(); break;
+    case 2: wait_vm<2>(); break;
+    case 4: wait_vm<4>(); break;
+    default: wait_vm<8>(); break;
     }
 }
 
@@ -96,7 +84,7 @@ template <typename OUT>
 __device__ __forceinline__ void unit(const Job &job, int c, int bi, int bj, uint8_t *lds_generic) {
     typedef typename Acc<K_I8>::type acc_t;
     const lds_u8 *lds = (const lds_u8 *)lds_generic;
-    const uint32_t lds_base = (uint32_t)(uintptr_t)lds;
+    const uint32_t lds_base = lds_addr(lds_generic);
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -175,8 +163,8 @@ __device__ __forceinline__ void unit(const Job &job, int c, int bi, int bj, uint
         // this wave's copies of chunk ch are done once only those of the
         // (at most two) chunks issued after it may be pending
         const int later = min(nchunk - 1 - ch, NSTAGE - 2);
-        wait_vm(later * nload);
-        __builtin_amdgcn_s_barrier();
+        wait_vm_n(later * nload);
+        barrier_lds();
         // every wave is past chunk ch - 1: its stage takes chunk ch + 3
         if (ch + NSTAGE - 1 < nchunk) issue(ch + NSTAGE - 1);
         if (!any) continue;
