@@ -134,16 +134,18 @@ xc_status resolve(const xc_config *cfg_in, xc_in_type in_type, xc_out_type out_t
         const bool f16tile = in_type == XC_IN_CF32 && p.block == 64;
         p.time_split = cfg.time_split ? cfg.time_split : (f16tile && S <= 64 ? 2 : 1);
         const int chunk = (f16tile && p.time_split == 2) ? 32 : mfma_chunk(in_type, p.block);
-        // int8 on 64-station blocks: 32-step chunks select the kernel that
-        // stages samples straight from HBM into LDS (whole 4-station granules:
-        // n_stations % 4 == 0), 64-step chunks the register-staged one
-        const bool dma_ok = in_type == XC_IN_CI8 && p.block == 64 && S % 4 == 0;
-        p.time_chunk = cfg.time_chunk ? cfg.time_chunk : (dma_ok ? 32 : chunk);
-        if (!(p.time_chunk == chunk || (dma_ok && p.time_chunk == 32))) {
-            if (in_type == XC_IN_CI8 && p.block == 64)
+        // int8 and 16-bit samples on 64-station blocks: the chunk length
+        // selects the kernel that stages samples straight from HBM into LDS
+        // (32 int8 / 16 16-bit steps; whole granules: n_stations % 4 == 0 for
+        // int8, % 2 == 0 for 16-bit) or the register-staged one (64 / 32)
+        const int dchunk = p.block == 64 ? dma_chunk(in_type) : 0;
+        const bool dma_ok = dchunk != 0 && S % dma_granule(in_type) == 0;
+        p.time_chunk = cfg.time_chunk ? cfg.time_chunk : (dma_ok ? dchunk : chunk);
+        if (!(p.time_chunk == chunk || (dma_ok && p.time_chunk == dchunk))) {
+            if (dchunk != 0)
                 return set_error(XC_ERR_INVALID_ARG,
-                                 "int8 MFMA time_chunk must be 64, or 32 when n_stations %% 4 == 0 (got %d)",
-                                 p.time_chunk);
+                                 "MFMA time_chunk must be %d, or %d when n_stations %% %d == 0 (got %d)", chunk,
+                                 dchunk, dma_granule(in_type), p.time_chunk);
             return set_error(XC_ERR_INVALID_ARG, "MFMA time_chunk for this configuration must be %d", chunk);
         }
         if (!(p.time_split == 1 || (f16tile && p.time_split == 2)))
@@ -220,7 +222,7 @@ xc_status launch_plan(const Plan &plan, xc_in_type in_type, xc_out_type out_type
     hipError_t e;
     if (plan.kernel == XC_KERNEL_VALU) e = launch_valu(plan, job, stream);
     else if (in_type == XC_IN_CF32 && plan.block == 64) e = launch_mfma16(plan, job, stream);
-    else if (plan_is_dma(plan, in_type)) e = launch_mfma_dma(out_type, job, stream);
+    else if (plan_is_dma(plan, in_type)) e = launch_mfma_dma(in_type, out_type, job, stream);
     else e = launch_mfma(plan, in_type, out_type, job, stream);
     if (e != hipSuccess) return hip_error(e, "kernel launch");
     return XC_OK;

@@ -86,7 +86,7 @@ static hipError_t plan_enqueue(xc_batch_plan *p, hipStream_t s) {
     if (p->in_type == XC_IN_CF32 && p->plan.block == 64)
         return launch_mfma16_batch(p->plan, p->d_jobs, p->d_units, q, p->grid, s);
     if (plan_is_dma(p->plan, p->in_type))
-        return launch_mfma_dma_batch(p->out_type, p->d_jobs, p->d_units, q, p->grid, s);
+        return launch_mfma_dma_batch(p->in_type, p->out_type, p->d_jobs, p->d_units, q, p->grid, s);
     return launch_mfma_batch(p->plan, p->in_type, p->out_type, p->d_jobs, p->d_units, q, p->grid, s);
 }
 
@@ -134,8 +134,8 @@ xc_status xc_batch_plan_create(const xc_subarray *items, int32_t n_items, int32_
             return set_error(XC_ERR_INVALID_ARG, "item %d: pointers must be 16-byte aligned", i);
         if (i == 0) plan = pi;
         // one persistent kernel serves every item: without an explicit
-        // time_chunk, an int8 item that the direct-to-LDS kernel cannot take
-        // moves the whole batch to the register-staged one
+        // time_chunk, an item that the direct-to-LDS kernel cannot take moves
+        // the whole batch to the register-staged one
         if (pi.time_chunk != plan.time_chunk && plan_is_dma(plan, in_type) && cfg->time_chunk == 0)
             plan.time_chunk = pi.time_chunk;
         S[i] = items[i].n_stations;
@@ -186,7 +186,7 @@ xc_status xc_batch_plan_create(const xc_subarray *items, int32_t n_items, int32_
     const int cus = device_cu_count();
     const int per_cu = plan.kernel == XC_KERNEL_VALU                    ? occupancy_valu_batch(plan)
                        : (in_type == XC_IN_CF32 && plan.block == 64) ? occupancy_mfma16_batch(plan)
-                       : plan_is_dma(plan, in_type)                  ? occupancy_mfma_dma_batch(out_type)
+                       : plan_is_dma(plan, in_type)                  ? occupancy_mfma_dma_batch(in_type, out_type)
                                                                      : occupancy_mfma_batch(plan, in_type, out_type);
     p->grid = (int)std::min<int64_t>((int64_t)cus * per_cu, n_units);
     if (use_graph) {

@@ -1,30 +1,35 @@
-// int8 matrix-core correlator kernel with direct global-to-LDS staging (gfx950).
+// Matrix-core correlator kernels for int8 and 16-bit samples with direct
+// global-to-LDS staging (gfx950).
 //
-// The product and the tiling are those of the register-staged kernel: a
+// The product and the tiling are those of the register-staged kernels: a
 // workgroup owns one (channel, block pair bi <= bj) of 64-station blocks, a
 // 128 x 128 square of (station, pol) rows; each of its four waves holds a
 // 64 x 64 quadrant as 2 x 2 tiles of 32 x 32, and V is accumulated over time
-// as Re V = [Xr Xi][Xr Xi]^T and (minus) Im V = [Xr Xi][Xi -Xr]^T on i8 MFMAs
-// with 32-bit integer sums.  What differs is how samples reach the matrix
-// cores:
+// as Re V = [Xr Xi][Xr Xi]^T and Im V = [Xr Xi][-Xi Xr]^T (int8: minus
+// [Xr Xi][Xi -Xr]^T, negated at the store) on 32x32 MFMAs.  What differs is
+// how samples reach the matrix cores:
 //
-//  * global_load_lds copies 16-byte granules (4 stations, both pols, one time
-//    step) from HBM straight into LDS, without passing through registers.  A
-//    ring of four stages of 32 time steps keeps three chunks in flight while a
-//    fourth is computed; one barrier per chunk both publishes a stage and
-//    frees the one that is refilled next.
-//  * LDS keeps the time-major layout of the input: one 256-byte row per block
-//    and time step.  The corner turn to the MFMA operand layout (a (station,
-//    pol) row per lane, time along K) is done by ds_read_b64_tr_b16, which
-//    hands every lane four consecutive time steps of one 16-bit (re, im)
-//    element; two such reads make a lane's 16-byte fragment.
-//  * Granule g of time row t is stored at granule g ^ 4 (t mod 4), so that the
-//    four time rows read by one transpose group fall on different banks.
+//  * global_load_lds copies 16-byte granules (4 int8 or 2 16-bit stations,
+//    both pols, one time step) from HBM straight into LDS, without passing
+//    through registers (see lds_dma.h).  A ring of four 16 KiB stages (32 int8
+//    or 16 16-bit time steps each) keeps three chunks in flight while a fourth
+//    is computed; one barrier per chunk both publishes a stage and frees the
+//    one that is refilled next.
+//  * LDS keeps the time-major layout of the input: one row per block and time
+//    step (256 bytes int8, 512 bytes 16-bit).  The corner turn to the MFMA
+//    operand layout (a (station, pol) row per lane, time along K) happens on
+//    the way out of LDS: for int8, ds_read_b64_tr_b16 hands every lane four
+//    consecutive time steps of one 16-bit (re, im) element, and two such reads
+//    make a lane's 16-byte fragment; for 16-bit samples, whose (re, im) pairs
+//    are 32 bits, a lane reads its row at four consecutive time steps with
+//    four 4-byte reads.
+//  * Granules are XOR-swizzled by time row so that the rows read together fall
+//    on different banks: int8 granule g of row t is stored at g ^ 4 (t mod 4)
+//    (the four rows of a transpose group), 16-bit granule g at
+//    g ^ 8 ((t / 4) mod 2) (the two row sets of a wave's 4-byte reads).
 //
-// The copies are issued as in lds_dma.h: every wait for them is explicit.
-//
-// Requires n_stations % 4 == 0 (whole granules); other station counts use the
-// register-staged kernel.
+// Requires whole granules: n_stations % 4 == 0 (int8) or % 2 == 0 (16-bit);
+// other station counts use the register-staged kernels.
 #include "common.h"
 
 #include "lds_dma.h"
@@ -34,22 +39,38 @@ namespace xc {
 namespace dma {
 
 using mfma::Acc;
+using mfma::K_BF16;
+using mfma::K_F16;
 using mfma::K_I8;
-using mfma::v16i;
 using mfma::v4i;
+using mfma::v8bf;
+using mfma::v8h;
 
 constexpr int SB = 64;              // stations per block
-constexpr int ROWB = SB * 4;        // bytes of one block's time step
-constexpr int KT = 32;              // time steps per stage
-constexpr int BLK = KT * ROWB;      // one block's share of a stage (8 KiB)
-constexpr int STAGE = 2 * BLK;      // 16 KiB
+constexpr int STAGE = 16384;        // bytes per stage (both blocks)
 constexpr int NSTAGE = 4;
 constexpr int LDS_BYTES = NSTAGE * STAGE;
 static_assert(4 * mfma::IMG_BYTES <= LDS_BYTES, "tile images must fit the staging ring");
 
+template <int KIND>
+struct Geo {
+    static constexpr bool I8 = KIND == K_I8;
+    static constexpr int SAMPLE = I8 ? 4 : 8;          // bytes per station (2 pols x (re, im))
+    static constexpr int ROWB = SB * SAMPLE;           // bytes of one block's time step
+    static constexpr int BLK = STAGE / 2;              // one block's share of a stage
+    static constexpr int KT = BLK / ROWB;              // time steps per stage: 32 or 16
+    static constexpr int GS = 16 / SAMPLE;             // stations per granule
+    static constexpr int LPR = ROWB / 16;              // lanes (granules) per time row: 16 or 32
+    static constexpr int RPC = 64 / LPR;               // time rows per copy instruction: 4 or 2
+    static constexpr int STEP_T = I8 ? 16 : 8;         // time steps per MFMA k-step
+    // LDS granule of logical granule g in time row t (an involution)
+    __device__ static int swz(int g, int t) { return I8 ? g ^ (4 * (t & 3)) : g ^ (8 * ((t >> 2) & 1)); }
+};
+
 typedef short v4s __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(3))) uint8_t lds_u8;
 typedef __attribute__((address_space(3))) v4s lds_v4s;
+typedef __attribute__((address_space(3))) uint32_t lds_u32;
 
 // Wait until at most n of this wave's vector-memory operations are pending
 // (n in {0, 2, 4, 8}).
@@ -62,27 +83,58 @@ __device__ __forceinline__ void wait_vm_n(int n) {
     }
 }
 
-__device__ __forceinline__ v4i tr_frag(const lds_u8 *p) {
-    const v4s lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4s *)p);
-    const v4s hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4s *)(p + 4 * ROWB));
-    const int2 l = __builtin_bit_cast(int2, lo), h = __builtin_bit_cast(int2, hi);
-    return v4i{l.x, l.y, h.x, h.y};
+// Byte offset, within a block's image, of this lane's first read of the 32
+// rows from n0 on at the first time step of a k-step.
+//  int8: lane group g = lane / 16 takes rows n0 + 16 (g % 2) on and K half
+//  g / 2 (time steps 8 (g / 2) on); lane j of a group addresses time step j / 4
+//  and the four elements from row 4 (j % 4) (the transpose read then gives
+//  lane j row j at four time steps).
+//  16-bit: lane l reads row n0 + l % 32 at time step 4 (l / 32) (then + 1, 2, 3).
+template <int KIND>
+__device__ __forceinline__ uint32_t frag_offset(int n0, int lane) {
+    typedef Geo<KIND> G;
+    if constexpr (G::I8) {
+        const int t = 8 * (lane >> 5) + ((lane & 15) >> 2);
+        const int n = n0 + 16 * ((lane >> 4) & 1) + 4 * (lane & 3);
+        return t * G::ROWB + (G::swz(n >> 3, t) << 4) + (n & 7) * 2;
+    } else {
+        const int t = 4 * (lane >> 5);
+        const int n = n0 + (lane & 31);
+        return t * G::ROWB + (G::swz(n >> 2, t) << 4) + (n & 3) * 4;
+    }
 }
 
-// Byte offset, within a block's image, of the transpose read of lane `lane`
-// for the 32 rows starting at n0 at the first time step of a k-step: lane
-// group g = lane / 16 takes rows n0 + 16 (g % 2) on and K half g / 2 (time
-// steps 8 (g / 2) on); lane j of a group reads time step j / 4 and the four
-// elements from row 4 (j % 4).
-__device__ __forceinline__ uint32_t tr_offset(int n0, int lane) {
-    const int t = 8 * (lane >> 5) + ((lane & 15) >> 2);
-    const int n = n0 + 16 * ((lane >> 4) & 1) + 4 * (lane & 3);
-    return t * ROWB + (((n >> 3) ^ (4 * (t & 3))) << 4) + (n & 7) * 2;
+// A lane's 16-byte fragment (K = 8 or 4 time steps of (re, im)) at p.
+template <int KIND>
+__device__ __forceinline__ v4i frag(const lds_u8 *p) {
+    typedef Geo<KIND> G;
+    if constexpr (G::I8) {
+        const v4s lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4s *)p);
+        const v4s hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4s *)(p + 4 * G::ROWB));
+        const int2 l = __builtin_bit_cast(int2, lo), h = __builtin_bit_cast(int2, hi);
+        return v4i{l.x, l.y, h.x, h.y};
+    } else {
+        return v4i{(int)*(const lds_u32 *)p, (int)*(const lds_u32 *)(p + G::ROWB),
+                   (int)*(const lds_u32 *)(p + 2 * G::ROWB), (int)*(const lds_u32 *)(p + 3 * G::ROWB)};
+    }
 }
 
-template <typename OUT>
+template <int KIND, typename ACC>
+__device__ __forceinline__ ACC mma(const v4i &a, const v4i &b, const ACC &c) {
+    if constexpr (KIND == K_I8)
+        return __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b, c, 0, 0, 0);
+    else if constexpr (KIND == K_F16)
+        return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(v8h, a), __builtin_bit_cast(v8h, b), c, 0, 0,
+                                                      0);
+    else
+        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(v8bf, a), __builtin_bit_cast(v8bf, b), c, 0,
+                                                       0, 0);
+}
+
+template <int KIND, typename OUT>
 __device__ __forceinline__ void unit(const Job &job, int c, int bi, int bj, uint8_t *lds_generic) {
-    typedef typename Acc<K_I8>::type acc_t;
+    typedef Geo<KIND> G;
+    typedef typename Acc<KIND>::type acc_t;
     const lds_u8 *lds = (const lds_u8 *)lds_generic;
     const uint32_t lds_base = lds_addr(lds_generic);
     const int tid = threadIdx.x;
@@ -94,40 +146,44 @@ __device__ __forceinline__ void unit(const Job &job, int c, int bi, int bj, uint
     const bool diag = bi == bj;
     const uint8_t *x = static_cast<const uint8_t *>(job.x);
 
-    // -- copies: wave w fills 8 (diagonal) or 16 time rows of one block per chunk,
-    // four rows (1 KiB) per instruction
+    // -- copies: per chunk, wave w fills a quarter (diagonal: block I only) or
+    // half (elsewhere) of one block's time rows, RPC rows (1 KiB) per copy
     const int blk = diag ? 0 : (wave >> 1);
-    const int rbase = diag ? wave * 8 : (wave & 1) * 16;
+    const int rbase = diag ? wave * (G::KT / 4) : (wave & 1) * (G::KT / 2);
     const int nload = diag ? 2 : 4;
-    const int lrow = lane >> 4;                         // = t mod 4 of the lane's rows
-    const int gran = (lane & 15) ^ (4 * lrow);          // source granule of LDS granule lane % 16
-    const int st = (blk ? J0 : I0) + 4 * gran;
-    const int stc = st < S ? st : S - 4;                // past the last station: a valid granule
-    const uint32_t off = (uint32_t)(((rbase + lrow) * S + stc) * 4);
-    const uint32_t step = (uint32_t)(4 * S * 4);        // four time rows
-    const uint32_t dst0 = lds_base + blk * BLK + rbase * ROWB;
+    const int lrow = lane / G::LPR;
+    uint32_t off[4];      // byte offset of this lane's granule in copy i, from the chunk base
+    int stc[4];           // its first station (past the last station: a valid granule)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int row = rbase + G::RPC * i + lrow;
+        const int st = (blk ? J0 : I0) + G::GS * G::swz(lane % G::LPR, row);
+        stc[i] = st < S ? st : S - G::GS;
+        off[i] = (uint32_t)((row * S + stc[i]) * G::SAMPLE);
+    }
+    const uint32_t dst0 = lds_base + blk * G::BLK + rbase * G::ROWB;
 
     auto issue = [&](int ch) {
-        const int t0 = ch * KT;
+        const int t0 = ch * G::KT;
         const uint32_t dst = dst0 + (ch % NSTAGE) * STAGE;
-        if (t0 + KT <= T && rows_contiguous(job, t0, KT)) {
-            const uint8_t *src = x + row_offset(job, c, t0) * 4 + off;
+        if (t0 + G::KT <= T && rows_contiguous(job, t0, G::KT)) {
+            const uint8_t *src = x + row_offset(job, c, t0) * G::SAMPLE;
 #pragma unroll
             for (int i = 0; i < 4; ++i)
-                if (i < nload) dma16(src + i * step, dst + i * 4 * ROWB);
+                if (i < nload) dma16(src + off[i], dst + i * G::RPC * G::ROWB);
         } else {
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 if (i >= nload) break;
-                const int t = t0 + rbase + 4 * i + lrow;
-                const void *src =
-                    t < T ? static_cast<const void *>(x + (row_offset(job, c, t) + stc) * 4) : g_zero16;
-                dma16(src, dst + i * 4 * ROWB);
+                const int t = t0 + rbase + G::RPC * i + lrow;
+                const void *src = t < T ? static_cast<const void *>(x + (row_offset(job, c, t) + stc[i]) * G::SAMPLE)
+                                        : static_cast<const void *>(g_zero16);
+                dma16(src, dst + i * G::RPC * G::ROWB);
             }
         }
     };
 
-    // -- tiles of this wave (as in the register-staged kernel)
+    // -- tiles of this wave (as in the register-staged kernels)
     bool run[2][2];
     bool any = false;
 #pragma unroll
@@ -151,11 +207,11 @@ __device__ __forceinline__ void unit(const Job &job, int c, int bi, int bj, uint
     uint32_t aoff[2], boff[2];
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
-        aoff[k] = tr_offset(wr * SB + 32 * k, lane);
-        boff[k] = (diag ? 0 : BLK) + tr_offset(wc * SB + 32 * k, lane);
+        aoff[k] = frag_offset<KIND>(wr * SB + 32 * k, lane);
+        boff[k] = (diag ? 0 : G::BLK) + frag_offset<KIND>(wc * SB + 32 * k, lane);
     }
 
-    const int nchunk = (T + KT - 1) / KT;
+    const int nchunk = (T + G::KT - 1) / G::KT;
 #pragma unroll
     for (int k = 0; k < NSTAGE - 1; ++k)
         if (k < nchunk) issue(k);
@@ -170,27 +226,26 @@ __device__ __forceinline__ void unit(const Job &job, int c, int bi, int bj, uint
         if (!any) continue;
         const lds_u8 *sb = lds + (ch % NSTAGE) * STAGE;
 #pragma unroll
-        for (int ks = 0; ks < KT / 16; ++ks) {
+        for (int ks = 0; ks < G::KT / G::STEP_T; ++ks) {
             v4i a[2], b[2], bn[2];
 #pragma unroll
             for (int k = 0; k < 2; ++k) {
-                a[k] = tr_frag(sb + aoff[k] + ks * 16 * ROWB);
-                b[k] = tr_frag(sb + boff[k] + ks * 16 * ROWB);
+                a[k] = frag<KIND>(sb + aoff[k] + ks * G::STEP_T * G::ROWB);
+                b[k] = frag<KIND>(sb + boff[k] + ks * G::STEP_T * G::ROWB);
             }
 #pragma unroll
             for (int k = 0; k < 2; ++k)
 #pragma unroll
-                for (int e = 0; e < 4; ++e) bn[k][e] = (int)mfma::conj_neg_i8((uint32_t)b[k][e]);
+                for (int e = 0; e < 4; ++e)
+                    bn[k][e] = (int)(G::I8 ? mfma::conj_neg_i8((uint32_t)b[k][e]) : mfma::conj_swap_h((uint32_t)b[k][e]));
 #pragma unroll
             for (int rs = 0; rs < 2; ++rs)
 #pragma unroll
-                for (int cs = 0; cs < 2; ++cs)
-                    are[rs][cs] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[rs], b[cs], are[rs][cs], 0, 0, 0);
+                for (int cs = 0; cs < 2; ++cs) are[rs][cs] = mma<KIND>(a[rs], b[cs], are[rs][cs]);
 #pragma unroll
             for (int rs = 0; rs < 2; ++rs)
 #pragma unroll
-                for (int cs = 0; cs < 2; ++cs)
-                    aim[rs][cs] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[rs], bn[cs], aim[rs][cs], 0, 0, 0);
+                for (int cs = 0; cs < 2; ++cs) aim[rs][cs] = mma<KIND>(a[rs], bn[cs], aim[rs][cs]);
         }
     }
     // all copies are complete (the last chunk waited for none pending); the
@@ -203,13 +258,14 @@ __device__ __forceinline__ void unit(const Job &job, int c, int bi, int bj, uint
 #pragma unroll
         for (int cs = 0; cs < 2; ++cs)
             if (run[rs][cs]) {
-                acc_t im = -aim[rs][cs];   // the accumulators hold minus the imaginary part
+                // the int8 accumulators hold minus the imaginary part
+                const acc_t im = G::I8 ? -aim[rs][cs] : aim[rs][cs];
                 mfma::store_tile_lds<acc_t, OUT>(job, c, are[rs][cs], im, I0 * 2 + wr * SB + rs * 32,
                                                  J0 * 2 + wc * SB + cs * 32, lane, img);
             }
 }
 
-template <typename OUT>
+template <int KIND, typename OUT>
 __global__ __launch_bounds__(256, 2) void kernel(Job job, int nwork) {
     __shared__ __attribute__((aligned(16))) uint8_t lds[LDS_BYTES];
     const int w = xcd_remap(blockIdx.x, nwork);
@@ -217,46 +273,67 @@ __global__ __launch_bounds__(256, 2) void kernel(Job job, int nwork) {
     const int c = w / job.npairs;
     int bi, bj;
     pair_decode(w - c * job.npairs, bi, bj);
-    unit<OUT>(job, c, bi, bj, lds);
+    unit<KIND, OUT>(job, c, bi, bj, lds);
 }
 
-template <typename OUT>
+template <int KIND, typename OUT>
 __global__ __launch_bounds__(256, 2) void kernel_batch(const Job *__restrict__ jobs, const Unit *__restrict__ units,
                                                        Queues q) {
     __shared__ __attribute__((aligned(16))) uint8_t lds[LDS_BYTES];
     __shared__ int next;
     drain_queues(units, q, &next, [&](const Unit &un) {
         const Job job = jobs[un.item];
-        unit<OUT>(job, un.channel, un.bi, un.bj, lds);
+        unit<KIND, OUT>(job, un.channel, un.bi, un.bj, lds);
     });
 }
 
+template <int KIND, typename OUT>
+hipError_t launch_t(const Job &job, hipStream_t stream) {
+    const int nwork = job.C * job.npairs;
+    hipLaunchKernelGGL((kernel<KIND, OUT>), dim3(xcd_grid(nwork)), dim3(256), 0, stream, job, nwork);
+    return hipGetLastError();
+}
+template <int KIND, typename OUT>
+hipError_t launch_batch_t(const Job *jobs, const Unit *units, Queues q, int grid, hipStream_t stream) {
+    hipLaunchKernelGGL((kernel_batch<KIND, OUT>), dim3(grid), dim3(256), 0, stream, jobs, units, q);
+    return hipGetLastError();
+}
+template <int KIND, typename OUT>
+int occupancy_t() {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel_batch<KIND, OUT>, 256, 0) != hipSuccess || n < 1)
+        n = 1;
+    return n;
+}
+
+#define XC_DMA_DISPATCH(FN, ...)                                                                      \
+    switch (in_type) {                                                                                \
+    case XC_IN_CI8:                                                                                   \
+        return out_type == XC_OUT_CI32 ? FN<K_I8, int2>(__VA_ARGS__) : FN<K_I8, float2>(__VA_ARGS__); \
+    case XC_IN_CF16: return FN<K_F16, float2>(__VA_ARGS__);                                           \
+    case XC_IN_CBF16: return FN<K_BF16, float2>(__VA_ARGS__);                                         \
+    default: break;                                                                                   \
+    }
+
 }  // namespace dma
 
-hipError_t launch_mfma_dma(xc_out_type out_type, const Job &job, hipStream_t stream) {
-    const int nwork = job.C * job.npairs;
-    if (out_type == XC_OUT_CI32)
-        hipLaunchKernelGGL(dma::kernel<int2>, dim3(xcd_grid(nwork)), dim3(256), 0, stream, job, nwork);
-    else
-        hipLaunchKernelGGL(dma::kernel<float2>, dim3(xcd_grid(nwork)), dim3(256), 0, stream, job, nwork);
-    return hipGetLastError();
+hipError_t launch_mfma_dma(xc_in_type in_type, xc_out_type out_type, const Job &job, hipStream_t stream) {
+    using namespace dma;
+    XC_DMA_DISPATCH(launch_t, job, stream)
+    return hipErrorInvalidValue;
 }
 
-hipError_t launch_mfma_dma_batch(xc_out_type out_type, const Job *jobs, const Unit *units, Queues q, int grid,
-                                 hipStream_t stream) {
-    if (out_type == XC_OUT_CI32)
-        hipLaunchKernelGGL(dma::kernel_batch<int2>, dim3(grid), dim3(256), 0, stream, jobs, units, q);
-    else
-        hipLaunchKernelGGL(dma::kernel_batch<float2>, dim3(grid), dim3(256), 0, stream, jobs, units, q);
-    return hipGetLastError();
+hipError_t launch_mfma_dma_batch(xc_in_type in_type, xc_out_type out_type, const Job *jobs, const Unit *units,
+                                 Queues q, int grid, hipStream_t stream) {
+    using namespace dma;
+    XC_DMA_DISPATCH(launch_batch_t, jobs, units, q, grid, stream)
+    return hipErrorInvalidValue;
 }
 
-int occupancy_mfma_dma_batch(xc_out_type out_type) {
-    int n = 0;
-    hipError_t e = out_type == XC_OUT_CI32
-                       ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, dma::kernel_batch<int2>, 256, 0)
-                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, dma::kernel_batch<float2>, 256, 0);
-    return (e != hipSuccess || n < 1) ? 1 : n;
+int occupancy_mfma_dma_batch(xc_in_type in_type, xc_out_type out_type) {
+    using namespace dma;
+    XC_DMA_DISPATCH(occupancy_t)
+    return 1;
 }
 
 }  // namespace xc

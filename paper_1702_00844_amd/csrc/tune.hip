@@ -13,9 +13,9 @@ static std::vector<xc_config> candidates(xc_in_type in_type) {
     std::vector<xc_config> v;
     v.push_back(xc_config{XC_KERNEL_MFMA, 32, 0, 0});
     v.push_back(xc_config{XC_KERNEL_MFMA, 64, 0, 1});
-    if (in_type == XC_IN_CI8) {   // both int8 staging schemes (the 32-step one needs S % 4 == 0)
-        v.push_back(xc_config{XC_KERNEL_MFMA, 64, 32, 1});
-        v.push_back(xc_config{XC_KERNEL_MFMA, 64, 64, 1});
+    if (dma_chunk(in_type) != 0) {   // both staging schemes (direct-to-LDS needs whole granules)
+        v.push_back(xc_config{XC_KERNEL_MFMA, 64, dma_chunk(in_type), 1});
+        v.push_back(xc_config{XC_KERNEL_MFMA, 64, in_type == XC_IN_CI8 ? 64 : 32, 1});
     }
     if (in_type == XC_IN_CF32) v.push_back(xc_config{XC_KERNEL_MFMA, 64, 0, 2});
     if (in_type == XC_IN_CF32) {

@@ -133,8 +133,13 @@ def test_config_resolution():
         xe.resolve_config((_lib.XC_IN_CI8, 8, 64, 70, 2), config={"kernel": 2, "time_chunk": 32})
     with pytest.raises(xe.XengineError):
         xe.resolve_config((_lib.XC_IN_CI8, 8, 64, 68, 2), config={"kernel": 2, "block": 32, "time_chunk": 32})
+    # 16-bit: 16-step chunks (staged straight into LDS) when n_stations is even
     r = xe.resolve_config((_lib.XC_IN_CF16, 1024, 1024, 256, 2))
+    assert r == {"kernel": 2, "block": 64, "time_chunk": 16, "time_split": 1}
+    r = xe.resolve_config((_lib.XC_IN_CBF16, 8, 64, 33, 2))
     assert r == {"kernel": 2, "block": 64, "time_chunk": 32, "time_split": 1}
+    with pytest.raises(xe.XengineError):
+        xe.resolve_config((_lib.XC_IN_CBF16, 8, 64, 33, 2), config={"kernel": 2, "time_chunk": 16})
     with pytest.raises(xe.XengineError):
         xe.resolve_config((_lib.XC_IN_CI8, 4, 16, 8, 2), config={"kernel": _lib.XC_KERNEL_VALU})
     with pytest.raises(xe.XengineError):

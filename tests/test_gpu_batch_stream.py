@@ -16,7 +16,7 @@ pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
 
 SHAPES = [(24, 5, 768), (70, 3, 300), (130, 2, 128), (8, 16, 256), (1, 4, 33), (65, 1, 1000)]
-# station counts that are multiples of 4: int8 batches run the direct-to-LDS kernel
+# station counts that are multiples of 4: int8 and 16-bit batches run the direct-to-LDS kernels
 SHAPES4 = [(24, 5, 768), (68, 3, 300), (132, 2, 128), (8, 16, 256), (4, 4, 33), (64, 1, 1000)]
 
 
@@ -49,13 +49,14 @@ def _check(kind, xs, outs, base=None):
 
 
 @pytest.mark.parametrize("kind,config,shapes", [
-    ("ci8", None, SHAPES4), ("ci8", None, SHAPES), ("cf16", None, SHAPES), ("cbf16", None, SHAPES),
+    ("ci8", None, SHAPES4), ("ci8", None, SHAPES), ("cf16", None, SHAPES4), ("cf16", None, SHAPES),
+    ("cbf16", None, SHAPES),
     ("cf32", {"kernel": xe.XC_KERNEL_MFMA, "block": 32}, SHAPES),
     ("cf32", {"kernel": xe.XC_KERNEL_MFMA, "block": 64, "time_split": 1}, SHAPES),
     ("cf32", {"kernel": xe.XC_KERNEL_MFMA, "block": 64, "time_split": 2}, SHAPES),
     ("cf32", {"kernel": xe.XC_KERNEL_VALU, "time_chunk": 32, "time_split": 8}, SHAPES),
     ("cf32", {"kernel": xe.XC_KERNEL_VALU, "time_chunk": 16, "time_split": 1}, SHAPES),
-], ids=["ci8_lds", "ci8_mixed", "cf16", "cbf16", "f32mfma32", "f32mfma64ts1", "f32mfma64ts2", "valu_ts8",
+], ids=["ci8_lds", "ci8_mixed", "cf16_lds", "cf16_mixed", "cbf16", "f32mfma32", "f32mfma64ts1", "f32mfma64ts2", "valu_ts8",
         "valu_ts1"])
 @pytest.mark.parametrize("use_graph", [True, False], ids=["graph", "direct"])
 def test_batch_matches_oracle(kind, config, shapes, use_graph):

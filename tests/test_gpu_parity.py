@@ -102,13 +102,19 @@ def _half_bound(xf, dtype):
     return (2 * u + u * u + T * 2.0 ** -24) * vabs * 1.001 + eta * (1 + u) * lin * 1.001
 
 
+# 16-bit kernels: the default (staged straight into LDS when S is even), the
+# register-staged one on 64-station blocks, and 32-station blocks
+HALF_CFGS = [None, dict(kernel=xe.XC_KERNEL_MFMA, block=64, time_chunk=32), dict(kernel=xe.XC_KERNEL_MFMA, block=32)]
+
+
 @pytest.mark.parametrize("dtype", [torch.float16, torch.bfloat16], ids=["f16", "bf16"])
-@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "S%d_C%d_T%d" % s)
-def test_half_parity(shape, dtype):
+@pytest.mark.parametrize("shape", I8_SHAPES, ids=lambda s: "S%d_C%d_T%d" % s)
+@pytest.mark.parametrize("cfg", HALF_CFGS, ids=["default", "b64_regs", "b32"])
+def test_half_parity(shape, dtype, cfg):
     S, C, T = shape
     xf = _cf32(S, C, T, seed=S * 31 + T)
     xh = torch.view_as_real(xf).to(dtype).contiguous()
-    v = xe.correlate(xh)
+    v = xe.correlate(xh, config=cfg)
     torch.cuda.synchronize()
     got = gpu_vis_numpy(v)
     acc_err = rel_err(got, oracle_vis(xh))          # same rounded samples: accumulation only
@@ -130,11 +136,12 @@ def test_half_normwise_on_workload_shape(dtype):
 
 
 @pytest.mark.parametrize("dtype", [torch.float16, torch.bfloat16], ids=["f16", "bf16"])
-def test_half_exact_on_integer_samples(dtype):
+@pytest.mark.parametrize("cfg", HALF_CFGS, ids=["default", "b64_regs", "b32"])
+def test_half_exact_on_integer_samples(dtype, cfg):
     S, C, T = 70, 2, 200
     xi = inputs.ci8_gaussian(C, T, S, seed=5, device=DEV)
     xh = xi.to(dtype)                                # |v| <= 127: exact in f16 and bf16
-    v = xe.correlate(xh)
+    v = xe.correlate(xh, config=cfg)
     torch.cuda.synchronize()
     ref = oracle_vis(xi)
     assert np.abs(ref).max() < 2 ** 24
@@ -225,9 +232,10 @@ def test_config3_sampled_channels():
         del v
     refc = ref[..., 0] + 1j * ref[..., 1]
     for dtype in (torch.float16, torch.bfloat16):
-        vh = xe.correlate(x.to(dtype))
-        assert np.array_equal(gpu_vis_numpy(vh, chans), refc)
-        del vh
+        for cfg in HALF_CFGS[:2]:
+            vh = xe.correlate(x.to(dtype), config=cfg)
+            assert np.array_equal(gpu_vis_numpy(vh, chans), refc)
+            del vh
     xf = torch.view_as_complex(x.to(torch.float32))
     for cfg in [VALU[2]] + MFMA_F32:
         vf = xe.correlate(xf, config=cfg)
