@@ -33,13 +33,22 @@ PEAKS = {  # MI355X published dense peaks
     "int8_mfma_TOPS": 5000.0,
     "fp32_valu_TF": 157.3,
 }
-KERNEL_SOURCES = {"mfma": "paper_1702_00844_amd/csrc/mfma.hip", "mfma16": "paper_1702_00844_amd/csrc/mfma16.hip",
-                  "valu": "paper_1702_00844_amd/csrc/valu.hip"}
+_CSRC = "paper_1702_00844_amd/csrc/"
+# the sources each kernel family is compiled from
+KERNEL_SOURCES = {
+    "valu": [_CSRC + "valu.hip", _CSRC + "common.h"],
+    "mfma": [_CSRC + "mfma.hip", _CSRC + "mfma_parts.h", _CSRC + "common.h"],
+    "mfma16": [_CSRC + "mfma16.hip", _CSRC + "lds_dma.h", _CSRC + "common.h"],
+    "dma": [_CSRC + "mfma_dma.hip", _CSRC + "lds_dma.h", _CSRC + "mfma_parts.h", _CSRC + "common.h"],
+}
 
 
 def source_sha(kind: str) -> str:
-    with open(os.path.join(ROOT, KERNEL_SOURCES[kind]), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for path in KERNEL_SOURCES[kind]:
+        with open(os.path.join(ROOT, path), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def load_traffic(key: str, kind: str):
@@ -200,7 +209,9 @@ def main():
     in_type = xe.in_type_of(x)[0]
     resolved = xe.resolve_config((in_type, C, T, S, 2), out_type, config=cfg)
     kind = "mfma" if resolved["kernel"] == xe.XC_KERNEL_MFMA else "valu"
-    src_kind = "mfma16" if (kind == "mfma" and kind_in == "cf32" and resolved["block"] == 64) else kind
+    src_kind = kind
+    if kind == "mfma" and resolved["block"] == 64:
+        src_kind = "mfma16" if kind_in == "cf32" else ("dma" if resolved["staging"] == xe.XC_STAGING_LDS else "mfma")
 
     def step():
         xe.correlate_into(x, out, config=cfg, stream=stream)

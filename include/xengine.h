@@ -77,6 +77,15 @@ typedef enum xc_kernel {
     XC_KERNEL_MFMA = 2    /* matrix cores: f32, f16, bf16 or i8 by input type        */
 } xc_kernel;
 
+/* How samples travel from HBM to LDS (matrix-core kernels). */
+typedef enum xc_staging {
+    XC_STAGING_AUTO = 0,
+    XC_STAGING_REGISTERS = 1, /* loaded into registers, corner-turned and stored to LDS */
+    XC_STAGING_LDS = 2        /* copied straight into LDS (global_load_lds); needs whole
+                                 16-byte granules: n_stations % 4 == 0 for int8,
+                                 % 2 == 0 for 16-bit samples                          */
+} xc_staging;
+
 /* Largest integration for which XC_OUT_CI32 is exact for every input:
  * |re|,|im| <= 2 * 127^2 * T <= 2^31 - 1  <=>  T <= 66572. */
 #define XC_CI32_MAX_TIMES 66572
@@ -128,17 +137,27 @@ xc_status xc_correlate(const void *samples, xc_in_type in_type, int32_t n_statio
  *   kernel        xc_kernel
  *   block         stations per block of the triangle's block grid (Section 4.5
  *                 splits large triangles into blocks).  VALU: 32.  MFMA: 32 or 64.
- *   time_chunk    time steps staged in LDS per pipeline stage.
+ *   time_chunk    time steps staged in LDS per pipeline stage (fixed by the
+ *                 other fields except for VALU: 16 or 32; complex-float32 on
+ *                 64-station blocks reports its off-diagonal chunk, diagonal
+ *                 block pairs stage one block with twice as many steps).
  *   time_split    waves of a workgroup that share one output block, each
  *                 integrating a different part of every time chunk; their
  *                 partial sums are added in LDS before the single store.
- *                 VALU: 1, 2, 4 or 8.  MFMA: 1.
+ *                 VALU: 1, 2, 4 or 8.  MFMA: 1, or 2 for complex-float32 on
+ *                 64-station blocks.
+ *   staging       xc_staging.  Complex-float32 on 64-station blocks always
+ *                 copies straight into LDS; VALU and 32-station blocks always
+ *                 stage through registers; int8 and 16-bit samples on
+ *                 64-station blocks take either (AUTO: LDS when the station
+ *                 count allows it).
  */
 typedef struct xc_config {
     int32_t kernel;
     int32_t block;
     int32_t time_chunk;
     int32_t time_split;
+    int32_t staging;
 } xc_config;
 
 /* Checks a configuration against a shape without touching the device.

@@ -20,7 +20,8 @@ import torch
 
 from . import _lib
 from ._lib import (XC_CI32_MAX_TIMES, XC_IN_CBF16, XC_IN_CF16, XC_IN_CF32, XC_IN_CI8, XC_KERNEL_AUTO,
-                   XC_KERNEL_MFMA, XC_KERNEL_VALU, XC_OUT_CF32, XC_OUT_CI32, XengineError)
+                   XC_KERNEL_MFMA, XC_KERNEL_VALU, XC_OUT_CF32, XC_OUT_CI32, XC_STAGING_AUTO, XC_STAGING_LDS,
+                   XC_STAGING_REGISTERS, XengineError)
 
 __all__ = ["correlate", "correlate_into", "n_baselines", "baseline_index", "tile_cost", "perf_max", "ai_global",
            "flops", "resolve_config", "BatchPlan", "batch_worklist", "autotune", "tune_cache_load", "Server",
@@ -117,7 +118,13 @@ def _config(config):
     if isinstance(config, _lib.XcConfig):
         return config
     return _lib.XcConfig(int(config.get("kernel", 0)), int(config.get("block", 0)),
-                         int(config.get("time_chunk", 0)), int(config.get("time_split", 0)))
+                         int(config.get("time_chunk", 0)), int(config.get("time_split", 0)),
+                         int(config.get("staging", 0)))
+
+
+def _config_dict(c) -> dict:
+    return {"kernel": c.kernel, "block": c.block, "time_chunk": c.time_chunk, "time_split": c.time_split,
+            "staging": c.staging}
 
 
 def resolve_config(x_shape_type, out_type=XC_OUT_CF32, config=None) -> dict:
@@ -127,7 +134,7 @@ def resolve_config(x_shape_type, out_type=XC_OUT_CF32, config=None) -> dict:
     res = _lib.XcConfig()
     _lib.check(lib().xc_resolve_config(ctypes.byref(cfg) if cfg else None, in_type, out_type, S, P, C, T,
                                        ctypes.byref(res)))
-    return {"kernel": res.kernel, "block": res.block, "time_chunk": res.time_chunk, "time_split": res.time_split}
+    return _config_dict(res)
 
 
 def correlate_into(x: torch.Tensor, out: torch.Tensor, accumulate: bool = False, stream=None,
@@ -239,8 +246,7 @@ def autotune(x: torch.Tensor, out: torch.Tensor, cache_path: str | None = None, 
     _lib.check(lib().xc_autotune(ctypes.c_void_p(x.data_ptr()), in_type, S, P, C, T, ctypes.c_void_p(out.data_ptr()),
                                  out_type, cache_path.encode() if cache_path else None, _stream_ptr(stream),
                                  ctypes.byref(best), ctypes.byref(ms)))
-    return ({"kernel": best.kernel, "block": best.block, "time_chunk": best.time_chunk,
-             "time_split": best.time_split}, ms.value)
+    return _config_dict(best), ms.value
 
 
 def tune_cache_load(path: str) -> int:

@@ -24,8 +24,12 @@ XC_PEAK_F32_MFMA16, XC_PEAK_F32_MFMA32, XC_PEAK_I8_MFMA, XC_PEAK_F16_MFMA, XC_PE
     XC_PEAK_HBM_COPY = range(7)
 
 
+XC_STAGING_AUTO, XC_STAGING_REGISTERS, XC_STAGING_LDS = 0, 1, 2
+
+
 class XcConfig(ctypes.Structure):
-    _fields_ = [("kernel", c_i32), ("block", c_i32), ("time_chunk", c_i32), ("time_split", c_i32)]
+    _fields_ = [("kernel", c_i32), ("block", c_i32), ("time_chunk", c_i32), ("time_split", c_i32),
+                ("staging", c_i32)]
 
 
 class XcSubarray(ctypes.Structure):

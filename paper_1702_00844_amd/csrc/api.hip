@@ -100,7 +100,7 @@ xc_status resolve(const xc_config *cfg_in, xc_in_type in_type, xc_out_type out_t
         return set_error(XC_ERR_OVERFLOW_RISK, "n_times = %d > %d: int32 visibilities could overflow", T,
                          XC_CI32_MAX_TIMES);
 
-    xc_config cfg = {0, 0, 0, 0};
+    xc_config cfg = {0, 0, 0, 0, 0};
     if (cfg_in) cfg = *cfg_in;
     if (cfg.kernel == XC_KERNEL_AUTO && !cfg_in) {
         xc_config tuned;
@@ -110,6 +110,8 @@ xc_status resolve(const xc_config *cfg_in, xc_in_type in_type, xc_out_type out_t
     if (kernel == XC_KERNEL_AUTO) kernel = XC_KERNEL_MFMA;
     if (kernel != XC_KERNEL_VALU && kernel != XC_KERNEL_MFMA)
         return set_error(XC_ERR_INVALID_ARG, "invalid kernel %d", cfg.kernel);
+    if (cfg.staging < XC_STAGING_AUTO || cfg.staging > XC_STAGING_LDS)
+        return set_error(XC_ERR_INVALID_ARG, "invalid staging %d", cfg.staging);
     Plan p;
     p.kernel = kernel;
     if (kernel == XC_KERNEL_VALU) {
@@ -118,39 +120,45 @@ xc_status resolve(const xc_config *cfg_in, xc_in_type in_type, xc_out_type out_t
         p.block = cfg.block ? cfg.block : 32;
         p.time_chunk = cfg.time_chunk ? cfg.time_chunk : 16;
         p.time_split = cfg.time_split ? cfg.time_split : 4;
+        p.staging = cfg.staging ? cfg.staging : XC_STAGING_REGISTERS;
         if (p.block != 32) return set_error(XC_ERR_INVALID_ARG, "VALU block must be 32 (got %d)", p.block);
         const bool ok = (p.time_chunk == 16 && (p.time_split == 1 || p.time_split == 2 || p.time_split == 4)) ||
                         (p.time_chunk == 32 && (p.time_split == 2 || p.time_split == 4 || p.time_split == 8));
         if (!ok)
             return set_error(XC_ERR_INVALID_ARG, "VALU (time_chunk, time_split) = (%d, %d) not available",
                              p.time_chunk, p.time_split);
+        if (p.staging != XC_STAGING_REGISTERS)
+            return set_error(XC_ERR_INVALID_ARG, "the vector-ALU kernel stages through registers only");
     } else {
         p.block = cfg.block ? cfg.block : 64;
         if (p.block != 32 && p.block != 64)
             return set_error(XC_ERR_INVALID_ARG, "MFMA block must be 32 or 64 (got %d)", p.block);
         // complex-float32 on 64-station blocks uses the 16x16 tile kernel, which
-        // can split time over two wave groups (with 32-step chunks); every
-        // other variant uses one
+        // copies straight into LDS and can split time over two wave groups;
+        // int8 and 16-bit samples on 64-station blocks take either staging
+        // (straight into LDS needs whole 16-byte granules); the rest stage
+        // through registers
         const bool f16tile = in_type == XC_IN_CF32 && p.block == 64;
-        p.time_split = cfg.time_split ? cfg.time_split : (f16tile && S <= 64 ? 2 : 1);
-        const int chunk = (f16tile && p.time_split == 2) ? 32 : mfma_chunk(in_type, p.block);
-        // int8 and 16-bit samples on 64-station blocks: the chunk length
-        // selects the kernel that stages samples straight from HBM into LDS
-        // (32 int8 / 16 16-bit steps; whole granules: n_stations % 4 == 0 for
-        // int8, % 2 == 0 for 16-bit) or the register-staged one (64 / 32)
-        const int dchunk = p.block == 64 ? dma_chunk(in_type) : 0;
-        const bool dma_ok = dchunk != 0 && S % dma_granule(in_type) == 0;
-        p.time_chunk = cfg.time_chunk ? cfg.time_chunk : (dma_ok ? dchunk : chunk);
-        if (!(p.time_chunk == chunk || (dma_ok && p.time_chunk == dchunk))) {
-            if (dchunk != 0)
-                return set_error(XC_ERR_INVALID_ARG,
-                                 "MFMA time_chunk must be %d, or %d when n_stations %% %d == 0 (got %d)", chunk,
-                                 dchunk, dma_granule(in_type), p.time_chunk);
-            return set_error(XC_ERR_INVALID_ARG, "MFMA time_chunk for this configuration must be %d", chunk);
+        const bool either = in_type != XC_IN_CF32 && p.block == 64;
+        const bool lds_ok = f16tile || (either && S % dma_granule(in_type) == 0);
+        p.staging = cfg.staging ? cfg.staging : (lds_ok ? XC_STAGING_LDS : XC_STAGING_REGISTERS);
+        if (p.staging == XC_STAGING_LDS && !lds_ok) {
+            if (either)
+                return set_error(XC_ERR_INVALID_ARG, "staging straight into LDS needs n_stations %% %d == 0 (got %d)",
+                                 dma_granule(in_type), S);
+            return set_error(XC_ERR_INVALID_ARG, "this configuration stages through registers only");
         }
+        if (p.staging == XC_STAGING_REGISTERS && f16tile)
+            return set_error(XC_ERR_INVALID_ARG,
+                             "complex-float32 on 64-station blocks copies straight into LDS only");
+        p.time_split = cfg.time_split ? cfg.time_split : (f16tile && S <= 64 ? 2 : 1);
         if (!(p.time_split == 1 || (f16tile && p.time_split == 2)))
             return set_error(XC_ERR_INVALID_ARG,
                              "MFMA time_split must be 1 (or 2 for complex-float32 on 64-station blocks)");
+        const int chunk = f16tile ? (p.time_split == 2 ? 32 : 16) : mfma_chunk(in_type, p.block);
+        p.time_chunk = cfg.time_chunk ? cfg.time_chunk : chunk;
+        if (p.time_chunk != chunk)
+            return set_error(XC_ERR_INVALID_ARG, "MFMA time_chunk for this configuration must be %d", chunk);
     }
     const int64_t nb = (S + p.block - 1) / p.block;
     const int64_t nwork = (int64_t)C * (nb * (nb + 1) / 2);
@@ -271,6 +279,7 @@ xc_status xc_resolve_config(const xc_config *cfg, xc_in_type in_type, xc_out_typ
         resolved->block = p.block;
         resolved->time_chunk = p.time_chunk;
         resolved->time_split = p.time_split;
+        resolved->staging = p.staging;
     }
     return XC_OK;
 }

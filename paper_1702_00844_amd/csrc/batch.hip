@@ -121,7 +121,7 @@ xc_status xc_batch_plan_create(const xc_subarray *items, int32_t n_items, int32_
     Plan plan{};
     // Without an explicit configuration every item runs one time group per
     // workgroup, so that all items share one persistent kernel.
-    const xc_config one_group = {XC_KERNEL_AUTO, 0, 0, 1};
+    const xc_config one_group = {XC_KERNEL_AUTO, 0, 0, 1, XC_STAGING_AUTO};
     if (!cfg) cfg = &one_group;
     std::vector<int32_t> S(n_items), C(n_items), T(n_items);
     for (int i = 0; i < n_items; ++i) {
@@ -136,8 +136,8 @@ xc_status xc_batch_plan_create(const xc_subarray *items, int32_t n_items, int32_
         // one persistent kernel serves every item: without an explicit
         // time_chunk, an item that the direct-to-LDS kernel cannot take moves
         // the whole batch to the register-staged one
-        if (pi.time_chunk != plan.time_chunk && plan_is_dma(plan, in_type) && cfg->time_chunk == 0)
-            plan.time_chunk = pi.time_chunk;
+        if (pi.staging != plan.staging && plan_is_dma(plan, in_type) && cfg->staging == XC_STAGING_AUTO)
+            plan.staging = pi.staging;
         S[i] = items[i].n_stations;
         C[i] = items[i].n_channels;
         T[i] = items[i].n_times;

@@ -88,6 +88,7 @@ struct Plan {
     int block;       // stations per block
     int time_chunk;  // time steps per LDS stage
     int time_split;  // waves sharing one output block over time
+    int staging;     // XC_STAGING_REGISTERS or XC_STAGING_LDS
 };
 
 // Launchers (return hipSuccess or the launch error).
@@ -96,21 +97,16 @@ hipError_t launch_mfma(const Plan &plan, xc_in_type in_type, xc_out_type out_typ
                        const Job &job, hipStream_t stream);
 
 // int8 and 16-bit samples on 64-station blocks staged straight from HBM to
-// LDS (whole granules: n_stations % 4 == 0 for int8, % 2 == 0 for 16-bit);
-// selected by time_chunk 32 (int8) or 16 (16-bit).
+// LDS (whole granules: n_stations % 4 == 0 for int8, % 2 == 0 for 16-bit).
 hipError_t launch_mfma_dma(xc_in_type in_type, xc_out_type out_type, const Job &job, hipStream_t stream);
 hipError_t launch_mfma_dma_batch(xc_in_type in_type, xc_out_type out_type, const Job *jobs, const Unit *units,
                                  Queues q, int grid, hipStream_t stream);
 int occupancy_mfma_dma_batch(xc_in_type in_type, xc_out_type out_type);
-// Time steps per stage of the direct-to-LDS kernel for an input type (0: none).
-inline int dma_chunk(xc_in_type in_type) {
-    return in_type == XC_IN_CI8 ? 32 : ((in_type == XC_IN_CF16 || in_type == XC_IN_CBF16) ? 16 : 0);
-}
-// Station-count granule the direct-to-LDS kernel needs.
+// Station-count granule the direct-to-LDS int8/16-bit kernel needs.
 inline int dma_granule(xc_in_type in_type) { return in_type == XC_IN_CI8 ? 4 : 2; }
-// True when the plan runs a direct-to-LDS kernel.
+// True when the plan runs the direct-to-LDS int8/16-bit kernel.
 inline bool plan_is_dma(const Plan &p, xc_in_type in_type) {
-    return p.kernel == XC_KERNEL_MFMA && p.block == 64 && dma_chunk(in_type) != 0 && p.time_chunk == dma_chunk(in_type);
+    return p.kernel == XC_KERNEL_MFMA && p.block == 64 && in_type != XC_IN_CF32 && p.staging == XC_STAGING_LDS;
 }
 
 // FP32 samples on 16x16x4 matrix-core tiles (64-station blocks).

@@ -11,10 +11,13 @@
 //
 //  * global_load_lds copies 16-byte granules (4 int8 or 2 16-bit stations,
 //    both pols, one time step) from HBM straight into LDS, without passing
-//    through registers (see lds_dma.h).  A ring of four 16 KiB stages (32 int8
-//    or 16 16-bit time steps each) keeps three chunks in flight while a fourth
-//    is computed; one barrier per chunk both publishes a stage and frees the
-//    one that is refilled next.
+//    through registers (see lds_dma.h).  Two 32 KiB stages (64 int8 or 32
+//    16-bit time steps each) alternate: the next chunk is copied while the
+//    current one is computed, and one barrier per chunk both publishes a stage
+//    and frees the other.  (Measured on the 256-station workload, two long
+//    stages beat four short ones, whose extra barriers cost more than the
+//    deeper prefetch gains, and a 64 KiB pair, which leaves one workgroup per
+//    CU.)
 //  * LDS keeps the time-major layout of the input: one row per block and time
 //    step (256 bytes int8, 512 bytes 16-bit).  The corner turn to the MFMA
 //    operand layout (a (station, pol) row per lane, time along K) happens on
@@ -47,8 +50,10 @@ using mfma::v8bf;
 using mfma::v8h;
 
 constexpr int SB = 64;              // stations per block
-constexpr int STAGE = 16384;        // bytes per stage (both blocks)
-constexpr int NSTAGE = 4;
+constexpr int STAGE = 32768;        // bytes per stage (both blocks)
+constexpr int NSTAGE = 2;
+static_assert(NSTAGE >= 2 && NSTAGE <= 4, "copies in flight are counted for up to two later chunks");
+static_assert((NSTAGE - 2) * (STAGE / 2 / 2 / 1024) < 32, "pending copies fit the vmcnt wait");
 constexpr int LDS_BYTES = NSTAGE * STAGE;
 static_assert(4 * mfma::IMG_BYTES <= LDS_BYTES, "tile images must fit the staging ring");
 
@@ -72,14 +77,15 @@ typedef __attribute__((address_space(3))) uint8_t lds_u8;
 typedef __attribute__((address_space(3))) v4s lds_v4s;
 typedef __attribute__((address_space(3))) uint32_t lds_u32;
 
-// Wait until at most n of this wave's vector-memory operations are pending
-// (n in {0, 2, 4, 8}).
+// Wait until at most n (0 <= n < 32) of this wave's vector-memory operations
+// are pending.
+template <int N = 0>
 __device__ __forceinline__ void wait_vm_n(int n) {
-    switch (n) {
-    case 0: wait_vm<0>(); break;
-    case 2: wait_vm<2>(); break;
-    case 4: wait_vm<4>(); break;
-    default: wait_vm<8>(); break;
+    if constexpr (N < 31) {
+        if (n == N) wait_vm<N>();
+        else wait_vm_n<N + 1>(n);
+    } else {
+        wait_vm<31>();
     }
 }
 
@@ -148,14 +154,15 @@ __device__ __forceinline__ void unit(const Job &job, int c, int bi, int bj, uint
 
     // -- copies: per chunk, wave w fills a quarter (diagonal: block I only) or
     // half (elsewhere) of one block's time rows, RPC rows (1 KiB) per copy
+    constexpr int NC = G::KT / 2 / G::RPC;              // copies per wave and chunk (half on the diagonal)
     const int blk = diag ? 0 : (wave >> 1);
     const int rbase = diag ? wave * (G::KT / 4) : (wave & 1) * (G::KT / 2);
-    const int nload = diag ? 2 : 4;
+    const int nload = diag ? NC / 2 : NC;
     const int lrow = lane / G::LPR;
-    uint32_t off[4];      // byte offset of this lane's granule in copy i, from the chunk base
-    int stc[4];           // its first station (past the last station: a valid granule)
+    uint32_t off[NC];     // byte offset of this lane's granule in copy i, from the chunk base
+    int stc[NC];          // its first station (past the last station: a valid granule)
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < NC; ++i) {
         const int row = rbase + G::RPC * i + lrow;
         const int st = (blk ? J0 : I0) + G::GS * G::swz(lane % G::LPR, row);
         stc[i] = st < S ? st : S - G::GS;
@@ -169,11 +176,11 @@ __device__ __forceinline__ void unit(const Job &job, int c, int bi, int bj, uint
         if (t0 + G::KT <= T && rows_contiguous(job, t0, G::KT)) {
             const uint8_t *src = x + row_offset(job, c, t0) * G::SAMPLE;
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < NC; ++i)
                 if (i < nload) dma16(src + off[i], dst + i * G::RPC * G::ROWB);
         } else {
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
+            for (int i = 0; i < NC; ++i) {
                 if (i >= nload) break;
                 const int t = t0 + rbase + G::RPC * i + lrow;
                 const void *src = t < T ? static_cast<const void *>(x + (row_offset(job, c, t) + stc[i]) * G::SAMPLE)

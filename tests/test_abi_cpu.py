@@ -110,36 +110,44 @@ def test_int32_bound_is_exact():
 
 
 def test_config_resolution():
+    R, L = _lib.XC_STAGING_REGISTERS, _lib.XC_STAGING_LDS
     shp = (_lib.XC_IN_CF32, 256, 768, 64, 2)
     r = xe.resolve_config(shp, config={"kernel": _lib.XC_KERNEL_VALU})
-    assert r == {"kernel": 1, "block": 32, "time_chunk": 16, "time_split": 4}
+    assert r == {"kernel": 1, "block": 32, "time_chunk": 16, "time_split": 4, "staging": R}
     r = xe.resolve_config(shp, config={"kernel": _lib.XC_KERNEL_MFMA})
-    assert r == {"kernel": 2, "block": 64, "time_chunk": 32, "time_split": 2}
+    assert r == {"kernel": 2, "block": 64, "time_chunk": 32, "time_split": 2, "staging": L}
     r = xe.resolve_config((_lib.XC_IN_CF32, 1024, 1024, 256, 2), config={"kernel": _lib.XC_KERNEL_MFMA})
-    assert r == {"kernel": 2, "block": 64, "time_chunk": 16, "time_split": 1}
+    assert r == {"kernel": 2, "block": 64, "time_chunk": 16, "time_split": 1, "staging": L}
     r = xe.resolve_config(shp, config={"kernel": _lib.XC_KERNEL_MFMA, "block": 32})
-    assert r == {"kernel": 2, "block": 32, "time_chunk": 16, "time_split": 1}
+    assert r == {"kernel": 2, "block": 32, "time_chunk": 16, "time_split": 1, "staging": R}
+    with pytest.raises(xe.XengineError):     # FP32 on 64-station blocks copies straight into LDS only
+        xe.resolve_config(shp, config={"kernel": _lib.XC_KERNEL_MFMA, "staging": R})
+    with pytest.raises(xe.XengineError):     # VALU stages through registers only
+        xe.resolve_config(shp, config={"kernel": _lib.XC_KERNEL_VALU, "staging": L})
+    with pytest.raises(xe.XengineError):
+        xe.resolve_config(shp, config={"kernel": _lib.XC_KERNEL_MFMA, "staging": 3})
     with pytest.raises(xe.XengineError):
         xe.resolve_config((_lib.XC_IN_CI8, 4, 16, 8, 2), _lib.XC_OUT_CI32, config={"kernel": 2, "time_split": 2})
-    # int8: 32-step chunks (staged straight into LDS) when n_stations % 4 == 0,
-    # otherwise 64-step chunks staged through registers
+    # int8 and 16-bit on 64-station blocks: straight into LDS when the station
+    # count is a whole number of 16-byte granules, else through registers
     r = xe.resolve_config((_lib.XC_IN_CI8, 1024, 1024, 256, 2), _lib.XC_OUT_CI32)
-    assert r == {"kernel": 2, "block": 64, "time_chunk": 32, "time_split": 1}
+    assert r == {"kernel": 2, "block": 64, "time_chunk": 64, "time_split": 1, "staging": L}
     r = xe.resolve_config((_lib.XC_IN_CI8, 8, 64, 70, 2), _lib.XC_OUT_CI32)
-    assert r == {"kernel": 2, "block": 64, "time_chunk": 64, "time_split": 1}
-    r = xe.resolve_config((_lib.XC_IN_CI8, 8, 64, 68, 2), _lib.XC_OUT_CI32, config={"kernel": 2, "time_chunk": 64})
-    assert r == {"kernel": 2, "block": 64, "time_chunk": 64, "time_split": 1}
+    assert r == {"kernel": 2, "block": 64, "time_chunk": 64, "time_split": 1, "staging": R}
+    r = xe.resolve_config((_lib.XC_IN_CI8, 8, 64, 68, 2), _lib.XC_OUT_CI32, config={"kernel": 2, "staging": R})
+    assert r == {"kernel": 2, "block": 64, "time_chunk": 64, "time_split": 1, "staging": R}
     with pytest.raises(xe.XengineError):
-        xe.resolve_config((_lib.XC_IN_CI8, 8, 64, 70, 2), config={"kernel": 2, "time_chunk": 32})
+        xe.resolve_config((_lib.XC_IN_CI8, 8, 64, 70, 2), config={"kernel": 2, "staging": L})
     with pytest.raises(xe.XengineError):
-        xe.resolve_config((_lib.XC_IN_CI8, 8, 64, 68, 2), config={"kernel": 2, "block": 32, "time_chunk": 32})
-    # 16-bit: 16-step chunks (staged straight into LDS) when n_stations is even
+        xe.resolve_config((_lib.XC_IN_CI8, 8, 64, 68, 2), config={"kernel": 2, "block": 32, "staging": L})
+    with pytest.raises(xe.XengineError):
+        xe.resolve_config((_lib.XC_IN_CI8, 8, 64, 68, 2), config={"kernel": 2, "time_chunk": 32})
     r = xe.resolve_config((_lib.XC_IN_CF16, 1024, 1024, 256, 2))
-    assert r == {"kernel": 2, "block": 64, "time_chunk": 16, "time_split": 1}
+    assert r == {"kernel": 2, "block": 64, "time_chunk": 32, "time_split": 1, "staging": L}
     r = xe.resolve_config((_lib.XC_IN_CBF16, 8, 64, 33, 2))
-    assert r == {"kernel": 2, "block": 64, "time_chunk": 32, "time_split": 1}
+    assert r == {"kernel": 2, "block": 64, "time_chunk": 32, "time_split": 1, "staging": R}
     with pytest.raises(xe.XengineError):
-        xe.resolve_config((_lib.XC_IN_CBF16, 8, 64, 33, 2), config={"kernel": 2, "time_chunk": 16})
+        xe.resolve_config((_lib.XC_IN_CBF16, 8, 64, 33, 2), config={"kernel": 2, "staging": L})
     with pytest.raises(xe.XengineError):
         xe.resolve_config((_lib.XC_IN_CI8, 4, 16, 8, 2), config={"kernel": _lib.XC_KERNEL_VALU})
     with pytest.raises(xe.XengineError):

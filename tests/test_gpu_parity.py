@@ -56,7 +56,8 @@ def test_cf32_parity(shape, cfg):
 # register-staged one on 64-station blocks, and 32-station blocks; extra shapes
 # with S % 4 == 0 give the direct-to-LDS kernel diagonal and off-diagonal
 # blocks, ragged blocks and ragged time tails
-I8_CFGS = [None, dict(kernel=xe.XC_KERNEL_MFMA, block=64, time_chunk=64), dict(kernel=xe.XC_KERNEL_MFMA, block=32)]
+I8_CFGS = [None, dict(kernel=xe.XC_KERNEL_MFMA, block=64, staging=xe.XC_STAGING_REGISTERS),
+           dict(kernel=xe.XC_KERNEL_MFMA, block=32)]
 I8_SHAPES = SHAPES + [(4, 1, 5), (68, 2, 100), (128, 1, 97), (132, 2, 33), (192, 1, 64)]
 
 
@@ -104,7 +105,8 @@ def _half_bound(xf, dtype):
 
 # 16-bit kernels: the default (staged straight into LDS when S is even), the
 # register-staged one on 64-station blocks, and 32-station blocks
-HALF_CFGS = [None, dict(kernel=xe.XC_KERNEL_MFMA, block=64, time_chunk=32), dict(kernel=xe.XC_KERNEL_MFMA, block=32)]
+HALF_CFGS = [None, dict(kernel=xe.XC_KERNEL_MFMA, block=64, staging=xe.XC_STAGING_REGISTERS),
+             dict(kernel=xe.XC_KERNEL_MFMA, block=32)]
 
 
 @pytest.mark.parametrize("dtype", [torch.float16, torch.bfloat16], ids=["f16", "bf16"])
