@@ -287,8 +287,9 @@ template <int KIND, typename OUT>
 __global__ __launch_bounds__(256, 2) void kernel_batch(const Job *__restrict__ jobs, const Unit *__restrict__ units,
                                                        Queues q) {
     __shared__ __attribute__((aligned(16))) uint8_t lds[LDS_BYTES];
-    __shared__ int next;
-    drain_queues(units, q, &next, [&](const Unit &un) {
+    // the queue slot lives in the staging area: it is read between barriers
+    // before a unit starts and written after the unit's last barrier
+    drain_queues(units, q, reinterpret_cast<int *>(lds), [&](const Unit &un) {
         const Job job = jobs[un.item];
         unit<KIND, OUT>(job, un.channel, un.bi, un.bj, lds);
     });

@@ -465,6 +465,10 @@ __device__ __forceinline__ void store_tile(const Job &job, int c, const ACC &re,
 // Hermitian (XX, YY real; YX = conj XY) on the way out.
 constexpr int IMG_ROW = 16 * 32 + 16;   // bytes per station j in a tile image
 constexpr int IMG_BYTES = 16 * IMG_ROW;
+// Byte offset of baseline (i, j) of a tile image: the second half of a row
+// is moved up 16 bytes so that the 16 baselines a quarter-wave reads at once
+// fall on different banks (the row padding makes room for it).
+__device__ __forceinline__ int img_offset(int jl, int il) { return jl * IMG_ROW + il * 32 + (il >> 3) * 16; }
 
 template <typename OUT>
 struct Vec;
@@ -496,7 +500,7 @@ __device__ __forceinline__ void store_tile_lds(const Job &job, int c, const ACC 
         for (int r = 0; r < 16; ++r) {
             const int row = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
             const OUT v = Out<OUT>::make(re[r], im[r]);
-            *reinterpret_cast<OUT *>(img + jl * IMG_ROW + (row >> 1) * 32 + (row & 1) * 16 + q * 8) = v;
+            *reinterpret_cast<OUT *>(img + img_offset(jl, row >> 1) + (row & 1) * 16 + q * 8) = v;
         }
     }
     __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0): the image is written before any lane reads it
@@ -509,8 +513,8 @@ __device__ __forceinline__ void store_tile_lds(const Job &job, int c, const ACC 
         const int bl = lane + 64 * k;
         const int jl = bl >> 4, il = bl & 15;
         const int i = i0 + il, j = j0 + jl;
-        uint4 lo = *reinterpret_cast<const uint4 *>(img + jl * IMG_ROW + il * 32);        // XX, XY
-        uint4 hi = *reinterpret_cast<const uint4 *>(img + jl * IMG_ROW + il * 32 + 16);   // YX, YY
+        uint4 lo = *reinterpret_cast<const uint4 *>(img + img_offset(jl, il));        // XX, XY
+        uint4 hi = *reinterpret_cast<const uint4 *>(img + img_offset(jl, il) + 16);   // YX, YY
         if (j >= S || i > j) continue;
         if (i == j) {
             lo.y = 0u;                      // Im XX
