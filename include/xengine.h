@@ -194,7 +194,7 @@ double xc_ai_global(int32_t n_stations);
 double xc_flops(int32_t n_stations, int32_t n_channels, int32_t n_times);
 
 /* ------------------------------------------------------------------------ */
-/* Batches of sub-arrays in one persistent launch.                           */
+/* Batches of sub-arrays in one launch per kernel configuration.            */
 
 typedef struct xc_subarray {
     const void *samples;   /* device, x[C][T][S][2] of the batch's in_type  */
@@ -207,12 +207,16 @@ typedef struct xc_subarray {
 typedef struct xc_batch_plan xc_batch_plan;
 
 /*
- * Builds a plan for correlating every item of `items` in one persistent
- * launch.  The plan copies the item list and builds a device work list of
- * (item, channel, block pair) units ordered by decreasing cost; workgroups take
- * units from an atomic counter.  If use_graph != 0 the launch (with the reset
- * of its counter) is captured into a hipGraph on `stream` and replayed by
- * xc_batch_plan_run.  The plan owns its device work list and counter;
+ * Builds a plan for correlating every item of `items`.  Items whose resolved
+ * configurations are equal share one launch (with cfg == NULL every item runs
+ * one time group per workgroup; the staging of int8 and 16-bit samples still
+ * depends on the station count, so a batch has at most two launches).  A
+ * launch runs one workgroup per (item, channel, block pair) unit of a device
+ * work list cut into one range per XCD: whole channels are dealt to the XCD
+ * with the least work so far (items by decreasing integration length), so a
+ * channel's block pairs share an L2 and the longest units start first.  If
+ * use_graph != 0 the launches are captured into a hipGraph on `stream` and
+ * replayed by xc_batch_plan_run.  The plan owns its device work lists;
  * xc_batch_plan_destroy frees them.  Pointers in `items` are baked into the
  * plan: they must stay valid while the plan is used.
  * Errors: as xc_correlate for each item; XC_ERR_OUT_OF_MEMORY.
@@ -228,13 +232,15 @@ int64_t xc_batch_plan_units(const xc_batch_plan *plan);
 
 /*
  * Host-only work-list construction, exposed for tests: fills units[k] =
- * {item, channel, block_i, block_j} (4 int32 each) for every work unit of the
- * batch in the order the plan would use.  Returns the unit count (or -1 on
- * bad args); writes at most `capacity` units.
+ * {item, channel, block_i, block_j} (4 int32 each) for every work unit of a
+ * launch over all the items on blocks of `block` stations, in the plan's
+ * order, and, if bounds is not NULL, bounds[0..8] = the start of each XCD's
+ * range and the end of the last.  Returns the unit count (or -1 on bad args);
+ * writes at most `capacity` units.
  */
 int64_t xc_batch_worklist(const int32_t *n_stations, const int32_t *n_channels,
                           const int32_t *n_times, int32_t n_items, int32_t block,
-                          int32_t *units, int64_t capacity);
+                          int32_t *units, int64_t capacity, int32_t *bounds);
 
 /* ------------------------------------------------------------------------ */
 /* Auto-tuning (tile sizes must be tuned per platform, Section 2).           */

@@ -174,24 +174,28 @@ def correlate(x: torch.Tensor, out: torch.Tensor | None = None, accumulate: bool
     return correlate_into(x, out, accumulate=accumulate, stream=stream, config=config)
 
 
-def batch_worklist(shapes, block: int):
-    """Host-side work list [(item, channel, bi, bj), ...] of a batch of
-    (n_stations, n_channels, n_times) shapes."""
+def batch_worklist(shapes, block: int, with_bounds: bool = False):
+    """Host-side work list [(item, channel, bi, bj), ...] of a launch over a
+    batch of (n_stations, n_channels, n_times) shapes; with_bounds also returns
+    the start of each XCD's range and the end of the last (9 entries)."""
     n = len(shapes)
     S = (ctypes.c_int32 * n)(*[s[0] for s in shapes])
     C = (ctypes.c_int32 * n)(*[s[1] for s in shapes])
     T = (ctypes.c_int32 * n)(*[s[2] for s in shapes])
-    count = lib().xc_batch_worklist(S, C, T, n, block, None, 0)
+    count = lib().xc_batch_worklist(S, C, T, n, block, None, 0, None)
     if count < 0:
         raise ValueError("invalid batch shapes")
     buf = (ctypes.c_int32 * (4 * count))()
-    lib().xc_batch_worklist(S, C, T, n, block, buf, count)
-    return [tuple(buf[4 * k:4 * k + 4]) for k in range(count)]
+    bounds = (ctypes.c_int32 * 9)()
+    lib().xc_batch_worklist(S, C, T, n, block, buf, count, bounds)
+    units = [tuple(buf[4 * k:4 * k + 4]) for k in range(count)]
+    return (units, list(bounds)) if with_bounds else units
 
 
 class BatchPlan:
-    """Many sub-arrays of uneven shape correlated by one persistent launch,
-    replayed from a hipGraph when use_graph is true."""
+    """Many sub-arrays of uneven shape correlated by one launch per kernel
+    configuration (one workgroup per unit), replayed from a hipGraph when
+    use_graph is true."""
 
     def __init__(self, samples, outs, accumulate=False, config=None, use_graph=True, stream=None):
         if len(samples) != len(outs) or not samples:

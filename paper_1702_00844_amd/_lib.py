@@ -72,7 +72,7 @@ SIGNATURES = {
     "xc_batch_plan_destroy": (None, [c_vp]),
     "xc_batch_plan_units": (c_i64, [c_vp]),
     "xc_batch_worklist": (c_i64, [ctypes.POINTER(c_i32), ctypes.POINTER(c_i32), ctypes.POINTER(c_i32), c_i32,
-                                  c_i32, ctypes.POINTER(c_i32), c_i64]),
+                                  c_i32, ctypes.POINTER(c_i32), c_i64, ctypes.POINTER(c_i32)]),
     "xc_autotune": (c_i32, [c_vp, c_i32, c_i32, c_i32, c_i32, c_i32, c_vp, c_i32, c_char_p, c_vp,
                             ctypes.POINTER(XcConfig), ctypes.POINTER(c_f64)]),
     "xc_tune_cache_load": (c_i64, [c_char_p]),

@@ -48,15 +48,16 @@ struct Unit {
     int32_t item, channel, bi, bj;
 };
 
-// Work queues of a persistent batch launch: the unit list is cut into one
-// contiguous segment per XCD (bounds[x] .. bounds[x+1]); a workgroup drains
-// the segment of its own XCD first (the block pairs of one channel then share
-// that XCD's L2), then helps with the others.  counters[x] (zero at launch)
-// counts units handed out from segment x.
-struct Queues {
-    const int *bounds;   // kNumXcd + 1 entries
-    int *counters;       // kNumXcd entries
-};
+// A batch launch runs one workgroup per unit of a flat unit list that is cut
+// into one contiguous range per XCD (bounds[x] .. bounds[x+1], balanced by
+// work): workgroup g runs on XCD g % kNumXcd (workgroups are dispatched to
+// XCDs round-robin) and takes unit bounds[x] + g / kNumXcd of that range, or
+// none if the range is shorter.  Returns the unit index or -1.
+__device__ inline int batch_unit(const int *__restrict__ bounds, int phys) {
+    const int x = phys % kNumXcd;
+    const int u = bounds[x] + phys / kNumXcd;
+    return u < bounds[x + 1] ? u : -1;
+}
 
 // Pair index k (column-major over the upper triangle of the block grid,
 // k = bj (bj + 1) / 2 + bi with bi <= bj) -> (bi, bj).
@@ -100,8 +101,7 @@ hipError_t launch_mfma(const Plan &plan, xc_in_type in_type, xc_out_type out_typ
 // LDS (whole granules: n_stations % 4 == 0 for int8, % 2 == 0 for 16-bit).
 hipError_t launch_mfma_dma(xc_in_type in_type, xc_out_type out_type, const Job &job, hipStream_t stream);
 hipError_t launch_mfma_dma_batch(xc_in_type in_type, xc_out_type out_type, const Job *jobs, const Unit *units,
-                                 Queues q, int grid, hipStream_t stream);
-int occupancy_mfma_dma_batch(xc_in_type in_type, xc_out_type out_type);
+                                 const int *bounds, int grid, hipStream_t stream);
 // Station-count granule the direct-to-LDS int8/16-bit kernel needs.
 inline int dma_granule(xc_in_type in_type) { return in_type == XC_IN_CI8 ? 4 : 2; }
 // True when the plan runs the direct-to-LDS int8/16-bit kernel.
@@ -111,42 +111,14 @@ inline bool plan_is_dma(const Plan &p, xc_in_type in_type) {
 
 // FP32 samples on 16x16x4 matrix-core tiles (64-station blocks).
 hipError_t launch_mfma16(const Plan &plan, const Job &job, hipStream_t stream);
-hipError_t launch_mfma16_batch(const Plan &plan, const Job *jobs, const Unit *units, Queues q, int grid,
+hipError_t launch_mfma16_batch(const Plan &plan, const Job *jobs, const Unit *units, const int *bounds, int grid,
                                hipStream_t stream);
-int occupancy_mfma16_batch(const Plan &plan);
 
-// Persistent batch launchers: units[0..n_units) processed by a fixed grid.
-hipError_t launch_valu_batch(const Plan &plan, const Job *jobs, const Unit *units, Queues q, int grid,
+// Batch launchers: one workgroup per unit (see batch_unit).
+hipError_t launch_valu_batch(const Plan &plan, const Job *jobs, const Unit *units, const int *bounds, int grid,
                              hipStream_t stream);
 hipError_t launch_mfma_batch(const Plan &plan, xc_in_type in_type, xc_out_type out_type, const Job *jobs,
-                             const Unit *units, Queues q, int grid, hipStream_t stream);
-// Workgroups of the persistent kernel that fit on one CU at once.
-int occupancy_valu_batch(const Plan &plan);
-int occupancy_mfma_batch(const Plan &plan, xc_in_type in_type, xc_out_type out_type);
-// Resets the queue counters with a one-wave kernel (graph-safe, no memset node).
-hipError_t launch_reset_counters(int *counters, hipStream_t stream);
-
-// The persistent loop shared by every batch kernel: calls body(unit) for each
-// unit taken from the queues.  Every workgroup leaves once all segments are
-// exhausted.
-template <typename F>
-__device__ __forceinline__ void drain_queues(const Unit *__restrict__ units, Queues q, int *next, F body) {
-    const int home = blockIdx.x % kNumXcd;
-    for (int k = 0; k < kNumXcd; ++k) {
-        const int x = (home + k) % kNumXcd;
-        const int begin = q.bounds[x];
-        const int len = q.bounds[x + 1] - begin;
-        for (;;) {
-            if (threadIdx.x == 0) *next = atomicAdd(&q.counters[x], 1);
-            __syncthreads();
-            const int u = *next;
-            __syncthreads();
-            if (u >= len) break;
-            body(units[begin + u]);
-            __syncthreads();
-        }
-    }
-}
+                             const Unit *units, const int *bounds, int grid, hipStream_t stream);
 
 // Process-wide tuning cache (shape -> configuration chosen by xc_autotune).
 struct TuneKey {

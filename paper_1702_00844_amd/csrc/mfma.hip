@@ -168,13 +168,13 @@ __global__ __launch_bounds__(256, 2) void kernel(Job job, int nwork) {
 
 template <int KIND, int SB, typename OUT>
 __global__ __launch_bounds__(256, 2) void kernel_batch(const Job *__restrict__ jobs, const Unit *__restrict__ units,
-                                                       Queues q) {
+                                                       const int *__restrict__ bounds) {
     __shared__ __attribute__((aligned(16))) uint8_t lds[2 * Geo<KIND, SB>::STAGE_BYTES];
-    __shared__ int next;
-    drain_queues(units, q, &next, [&](const Unit &un) {
-        const Job job = jobs[un.item];
-        unit<KIND, SB, OUT>(job, un.channel, un.bi, un.bj, lds);
-    });
+    const int u = batch_unit(bounds, blockIdx.x);
+    if (u < 0) return;
+    const Unit un = units[u];
+    const Job job = jobs[un.item];
+    unit<KIND, SB, OUT>(job, un.channel, un.bi, un.bj, lds);
 }
 
 template <int KIND, int SB, typename OUT>
@@ -184,18 +184,10 @@ hipError_t launch_t(const Job &job, hipStream_t stream) {
     return hipGetLastError();
 }
 template <int KIND, int SB, typename OUT>
-hipError_t launch_batch_t(const Job *jobs, const Unit *units, Queues q, int grid, hipStream_t stream) {
-    hipLaunchKernelGGL((kernel_batch<KIND, SB, OUT>), dim3(grid), dim3(256), 0, stream, jobs, units, q);
+hipError_t launch_batch_t(const Job *jobs, const Unit *units, const int *bounds, int grid, hipStream_t stream) {
+    hipLaunchKernelGGL((kernel_batch<KIND, SB, OUT>), dim3(grid), dim3(256), 0, stream, jobs, units, bounds);
     return hipGetLastError();
 }
-template <int KIND, int SB, typename OUT>
-int occupancy_t() {
-    int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel_batch<KIND, SB, OUT>, 256, 0) != hipSuccess || n < 1)
-        n = 1;
-    return n;
-}
-
 // Dispatch over (input type, output type, block size).
 #define XC_MFMA_DISPATCH(FN, ...)                                                                     \
     switch (in_type) {                                                                                \
@@ -222,18 +214,11 @@ hipError_t launch_mfma(const Plan &plan, xc_in_type in_type, xc_out_type out_typ
 }
 
 hipError_t launch_mfma_batch(const Plan &plan, xc_in_type in_type, xc_out_type out_type, const Job *jobs,
-                             const Unit *units, Queues q, int grid, hipStream_t stream) {
+                             const Unit *units, const int *bounds, int grid, hipStream_t stream) {
     using namespace mfma;
     const int sb = plan.block;
-    XC_MFMA_DISPATCH(launch_batch_t, jobs, units, q, grid, stream)
+    XC_MFMA_DISPATCH(launch_batch_t, jobs, units, bounds, grid, stream)
     return hipErrorInvalidValue;
-}
-
-int occupancy_mfma_batch(const Plan &plan, xc_in_type in_type, xc_out_type out_type) {
-    using namespace mfma;
-    const int sb = plan.block;
-    XC_MFMA_DISPATCH(occupancy_t)
-    return 1;
 }
 
 }  // namespace xc

@@ -313,13 +313,14 @@ __global__ __launch_bounds__(256 * TS, 2 / TS) void kernel(Job job, int nwork) {
 
 template <int TS>
 __global__ __launch_bounds__(256 * TS, 2 / TS) void kernel_batch(const Job *__restrict__ jobs,
-                                                                 const Unit *__restrict__ units, Queues q) {
+                                                                 const Unit *__restrict__ units,
+                                                                 const int *__restrict__ bounds) {
     __shared__ __attribute__((aligned(16))) uint8_t lds[2 * stage<TS>()];
-    __shared__ int next;
-    drain_queues(units, q, &next, [&](const Unit &un) {
-        const Job job = jobs[un.item];
-        unit<TS>(job, un.channel, un.bi, un.bj, lds);
-    });
+    const int u = batch_unit(bounds, blockIdx.x);
+    if (u < 0) return;
+    const Unit un = units[u];
+    const Job job = jobs[un.item];
+    unit<TS>(job, un.channel, un.bi, un.bj, lds);
 }
 
 }  // namespace mfma16
@@ -334,22 +335,14 @@ hipError_t launch_mfma16(const Plan &plan, const Job &job, hipStream_t stream) {
     return hipGetLastError();
 }
 
-hipError_t launch_mfma16_batch(const Plan &plan, const Job *jobs, const Unit *units, Queues q, int grid,
+hipError_t launch_mfma16_batch(const Plan &plan, const Job *jobs, const Unit *units, const int *bounds, int grid,
                                hipStream_t stream) {
     if (plan.time_split == 2) {
-        hipLaunchKernelGGL(mfma16::kernel_batch<2>, dim3(grid), dim3(512), 0, stream, jobs, units, q);
+        hipLaunchKernelGGL(mfma16::kernel_batch<2>, dim3(grid), dim3(512), 0, stream, jobs, units, bounds);
     } else {
-        hipLaunchKernelGGL(mfma16::kernel_batch<1>, dim3(grid), dim3(256), 0, stream, jobs, units, q);
+        hipLaunchKernelGGL(mfma16::kernel_batch<1>, dim3(grid), dim3(256), 0, stream, jobs, units, bounds);
     }
     return hipGetLastError();
-}
-
-int occupancy_mfma16_batch(const Plan &plan) {
-    int n = 0;
-    hipError_t e = plan.time_split == 2
-                       ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, mfma16::kernel_batch<2>, 512, 0)
-                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, mfma16::kernel_batch<1>, 256, 0);
-    return (e != hipSuccess || n < 1) ? 1 : n;
 }
 
 }  // namespace xc

@@ -285,14 +285,13 @@ __global__ __launch_bounds__(256, 2) void kernel(Job job, int nwork) {
 
 template <int KIND, typename OUT>
 __global__ __launch_bounds__(256, 2) void kernel_batch(const Job *__restrict__ jobs, const Unit *__restrict__ units,
-                                                       Queues q) {
+                                                       const int *__restrict__ bounds) {
     __shared__ __attribute__((aligned(16))) uint8_t lds[LDS_BYTES];
-    // the queue slot lives in the staging area: it is read between barriers
-    // before a unit starts and written after the unit's last barrier
-    drain_queues(units, q, reinterpret_cast<int *>(lds), [&](const Unit &un) {
-        const Job job = jobs[un.item];
-        unit<KIND, OUT>(job, un.channel, un.bi, un.bj, lds);
-    });
+    const int u = batch_unit(bounds, blockIdx.x);
+    if (u < 0) return;
+    const Unit un = units[u];
+    const Job job = jobs[un.item];
+    unit<KIND, OUT>(job, un.channel, un.bi, un.bj, lds);
 }
 
 template <int KIND, typename OUT>
@@ -302,18 +301,10 @@ hipError_t launch_t(const Job &job, hipStream_t stream) {
     return hipGetLastError();
 }
 template <int KIND, typename OUT>
-hipError_t launch_batch_t(const Job *jobs, const Unit *units, Queues q, int grid, hipStream_t stream) {
-    hipLaunchKernelGGL((kernel_batch<KIND, OUT>), dim3(grid), dim3(256), 0, stream, jobs, units, q);
+hipError_t launch_batch_t(const Job *jobs, const Unit *units, const int *bounds, int grid, hipStream_t stream) {
+    hipLaunchKernelGGL((kernel_batch<KIND, OUT>), dim3(grid), dim3(256), 0, stream, jobs, units, bounds);
     return hipGetLastError();
 }
-template <int KIND, typename OUT>
-int occupancy_t() {
-    int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel_batch<KIND, OUT>, 256, 0) != hipSuccess || n < 1)
-        n = 1;
-    return n;
-}
-
 #define XC_DMA_DISPATCH(FN, ...)                                                                      \
     switch (in_type) {                                                                                \
     case XC_IN_CI8:                                                                                   \
@@ -332,16 +323,10 @@ hipError_t launch_mfma_dma(xc_in_type in_type, xc_out_type out_type, const Job &
 }
 
 hipError_t launch_mfma_dma_batch(xc_in_type in_type, xc_out_type out_type, const Job *jobs, const Unit *units,
-                                 Queues q, int grid, hipStream_t stream) {
+                                 const int *bounds, int grid, hipStream_t stream) {
     using namespace dma;
-    XC_DMA_DISPATCH(launch_batch_t, jobs, units, q, grid, stream)
+    XC_DMA_DISPATCH(launch_batch_t, jobs, units, bounds, grid, stream)
     return hipErrorInvalidValue;
-}
-
-int occupancy_mfma_dma_batch(xc_in_type in_type, xc_out_type out_type) {
-    using namespace dma;
-    XC_DMA_DISPATCH(occupancy_t)
-    return 1;
 }
 
 }  // namespace xc

@@ -191,17 +191,16 @@ __global__ __launch_bounds__(64 * TS) void kernel(Job job, int nwork) {
     unit<TS, TC>(job, c, bi, bj, st);
 }
 
-// Persistent form: a fixed grid takes units from a device counter until the
-// list is exhausted.  Every workgroup leaves once the counter passes n_units.
+// Batch form: one workgroup per unit of a batch's unit list.
 template <int TS, int TC>
 __global__ __launch_bounds__(64 * TS) void kernel_batch(const Job *__restrict__ jobs,
-                                                         const Unit *__restrict__ units, Queues q) {
+                                                         const Unit *__restrict__ units, const int *__restrict__ bounds) {
     __shared__ Stage<TC> st;
-    __shared__ int next;
-    drain_queues(units, q, &next, [&](const Unit &un) {
-        const Job job = jobs[un.item];
-        unit<TS, TC>(job, un.channel, un.bi, un.bj, st);
-    });
+    const int u = batch_unit(bounds, blockIdx.x);
+    if (u < 0) return;
+    const Unit un = units[u];
+    const Job job = jobs[un.item];
+    unit<TS, TC>(job, un.channel, un.bi, un.bj, st);
 }
 
 template <int TS, int TC>
@@ -212,31 +211,12 @@ hipError_t launch_t(const Job &job, hipStream_t stream) {
 }
 
 template <int TS, int TC>
-hipError_t launch_batch_t(const Job *jobs, const Unit *units, Queues q, int grid, hipStream_t stream) {
-    hipLaunchKernelGGL((kernel_batch<TS, TC>), dim3(grid), dim3(64 * TS), 0, stream, jobs, units, q);
+hipError_t launch_batch_t(const Job *jobs, const Unit *units, const int *bounds, int grid, hipStream_t stream) {
+    hipLaunchKernelGGL((kernel_batch<TS, TC>), dim3(grid), dim3(64 * TS), 0, stream, jobs, units, bounds);
     return hipGetLastError();
 }
 
-template <int TS, int TC>
-int occupancy_t() {
-    int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel_batch<TS, TC>, 64 * TS, 0) != hipSuccess || n < 1)
-        n = 1;
-    return n;
-}
-
 }  // namespace valu
-
-int occupancy_valu_batch(const Plan &plan) {
-    const int ts = plan.time_split, tc = plan.time_chunk;
-    if (ts == 1 && tc == 16) return valu::occupancy_t<1, 16>();
-    if (ts == 2 && tc == 16) return valu::occupancy_t<2, 16>();
-    if (ts == 4 && tc == 16) return valu::occupancy_t<4, 16>();
-    if (ts == 2 && tc == 32) return valu::occupancy_t<2, 32>();
-    if (ts == 4 && tc == 32) return valu::occupancy_t<4, 32>();
-    if (ts == 8 && tc == 32) return valu::occupancy_t<8, 32>();
-    return 1;
-}
 
 hipError_t launch_valu(const Plan &plan, const Job &job, hipStream_t stream) {
     const int ts = plan.time_split, tc = plan.time_chunk;
@@ -249,15 +229,15 @@ hipError_t launch_valu(const Plan &plan, const Job &job, hipStream_t stream) {
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_valu_batch(const Plan &plan, const Job *jobs, const Unit *units, Queues q, int grid,
+hipError_t launch_valu_batch(const Plan &plan, const Job *jobs, const Unit *units, const int *bounds, int grid,
                              hipStream_t stream) {
     const int ts = plan.time_split, tc = plan.time_chunk;
-    if (ts == 1 && tc == 16) return valu::launch_batch_t<1, 16>(jobs, units, q, grid, stream);
-    if (ts == 2 && tc == 16) return valu::launch_batch_t<2, 16>(jobs, units, q, grid, stream);
-    if (ts == 4 && tc == 16) return valu::launch_batch_t<4, 16>(jobs, units, q, grid, stream);
-    if (ts == 2 && tc == 32) return valu::launch_batch_t<2, 32>(jobs, units, q, grid, stream);
-    if (ts == 4 && tc == 32) return valu::launch_batch_t<4, 32>(jobs, units, q, grid, stream);
-    if (ts == 8 && tc == 32) return valu::launch_batch_t<8, 32>(jobs, units, q, grid, stream);
+    if (ts == 1 && tc == 16) return valu::launch_batch_t<1, 16>(jobs, units, bounds, grid, stream);
+    if (ts == 2 && tc == 16) return valu::launch_batch_t<2, 16>(jobs, units, bounds, grid, stream);
+    if (ts == 4 && tc == 16) return valu::launch_batch_t<4, 16>(jobs, units, bounds, grid, stream);
+    if (ts == 2 && tc == 32) return valu::launch_batch_t<2, 32>(jobs, units, bounds, grid, stream);
+    if (ts == 4 && tc == 32) return valu::launch_batch_t<4, 32>(jobs, units, bounds, grid, stream);
+    if (ts == 8 && tc == 32) return valu::launch_batch_t<8, 32>(jobs, units, bounds, grid, stream);
     return hipErrorInvalidValue;
 }
 

@@ -171,9 +171,9 @@ def test_quantile_nearest_rank():
 
 
 def test_batch_worklist_covers_every_unit_once():
-    shapes = [(24, 3, 768), (130, 2, 1024), (64, 5, 512), (1, 2, 10)]
+    shapes = [(24, 3, 768), (130, 2, 1024), (64, 5, 512), (1, 2, 10), (70, 9, 300)]
     for block in (32, 64):
-        units = xe.batch_worklist(shapes, block)
+        units, bounds = xe.batch_worklist(shapes, block, with_bounds=True)
         expect = set()
         for it, (S, C, T) in enumerate(shapes):
             nb = -(-S // block)
@@ -182,10 +182,24 @@ def test_batch_worklist_covers_every_unit_once():
                     for bi in range(bj + 1):
                         expect.add((it, c, bi, bj))
         assert len(units) == len(expect) and set(units) == expect
-        # longest integrations first
-        Ts = [shapes[u[0]][2] for u in units]
-        assert Ts == sorted(Ts, reverse=True)
-
+        assert bounds[0] == 0 and bounds[-1] == len(units) and bounds == sorted(bounds)
+        work = []
+        for x in range(8):
+            rng = units[bounds[x]:bounds[x + 1]]
+            # longest integrations first within an XCD's range
+            Ts = [shapes[u[0]][2] for u in rng]
+            assert Ts == sorted(Ts, reverse=True)
+            work.append(sum(shapes[u[0]][2] for u in rng))
+        # every channel's block pairs are contiguous, on one XCD
+        for it, (S, C, T) in enumerate(shapes):
+            for c in range(C):
+                pos = [k for k, u in enumerate(units) if u[0] == it and u[1] == c]
+                assert pos == list(range(pos[0], pos[0] + len(pos)))
+                assert sum(bounds[x] <= pos[0] < bounds[x + 1] for x in range(8)) == 1
+                assert bounds[[x for x in range(8) if bounds[x] <= pos[0] < bounds[x + 1]][0] + 1] > pos[-1]
+        # work dealt greedily: no XCD exceeds another by more than one channel's units
+        biggest = max(T * (-(-S // block)) * (-(-S // block) + 1) // 2 for S, C, T in shapes)
+        assert max(work) - min(work) <= biggest
 
 def test_stream_footprint_and_validation():
     lib = _lib.load()
