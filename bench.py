@@ -176,7 +176,7 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (for scaling HBM counters)")
     ap.add_argument("--batch", choices=["none", "ci8", "cf32", "both"], default="ci8",
-                    help="also time the 32-sub-array persistent batch")
+                    help="also time the 32-sub-array batch plan")
     ap.add_argument("--stream-streams", type=int, default=1, help="streams for the streaming run (0: skip)")
     ap.add_argument("--stream-fold", type=int, default=8, help="blocks per fold (deadline = fold x period)")
     ap.add_argument("--stream-blocks", type=int, default=384, help="blocks per stream after one warm-up integration")
@@ -330,8 +330,8 @@ def compare_paths(xe, inputs, torch, dev, stream, steps=10):
 
 def batch_bench(xe, inputs, torch, dev, stream, kind, steps=5):
     """32 sub-arrays of uneven shape (stations uniform in [24, 576], channels
-    uniform in [16, 1024], 768 samples) in one persistent, graph-replayed
-    launch, against one xc_correlate launch per sub-array."""
+    uniform in [16, 1024], 768 samples) as one graph-replayed batch plan,
+    against one xc_correlate launch per sub-array."""
     shapes = inputs.subarray_shapes(32, seed=4)
     xs, outs = [], []
     for k, (S, C, T) in enumerate(shapes):
@@ -359,7 +359,7 @@ def batch_bench(xe, inputs, torch, dev, stream, kind, steps=5):
                         + ("complex int8" if kind == "ci8" else "complex64 CN(0,1)"),
             "units": n_units, "algorithmic_flops": flops, "in_GB": round(in_bytes / 1e9, 2),
             "out_GB": round(out_bytes / 1e9, 2),
-            "persistent_graph_ms": round(ms_plan, 3), "persistent_TFLOP/s": round(flops / ms_plan / 1e9, 1),
+            "batch_graph_ms": round(ms_plan, 3), "batch_TFLOP/s": round(flops / ms_plan / 1e9, 1),
             "per_item_launches_ms": round(ms_each, 3), "per_item_TFLOP/s": round(flops / ms_each / 1e9, 1)}
 
 

@@ -1,4 +1,4 @@
-"""GPU tests of the batch plans (one persistent launch, hipGraph replay), the
+"""GPU tests of the batch plans (one workgroup per unit, hipGraph replay), the
 auto-tuner and the streaming server, against the oracle."""
 import ctypes
 import os
