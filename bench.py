@@ -68,6 +68,23 @@ def load_traffic(key: str, kind: str):
     return ent.get("bytes_per_launch")
 
 
+def executed_flops_mfma16(S, C, T, time_split, product):
+    """Matrix-core flops the 16 x 16 FP32 kernel issues for one launch: per
+    channel, each diagonal 64-station block pair runs 36 of its 8 x 8 tiles of
+    16 x 16 (row, column) pairs and each off-diagonal pair all 64, over the
+    time steps rounded up to whole chunks (32 or 16 off the diagonal, twice
+    that on it, for two or one time groups); a tile costs 2048 flops per time
+    step with four real products (four 16x16x4 MFMAs per four time steps) and
+    1536 with three."""
+    nb = (S + 63) // 64
+    kt_off = 32 if time_split == 2 else 16
+    kt_diag = 2 * kt_off
+    pad = lambda kt: (T + kt - 1) // kt * kt
+    per_t = 1536 if product == 2 else 2048
+    tiles_t = nb * 36 * pad(kt_diag) + nb * (nb - 1) // 2 * 64 * pad(kt_off)
+    return float(C) * tiles_t * per_t
+
+
 def time_launches(fn, steps: int, warmup: int, stream):
     import torch
     for _ in range(warmup):
@@ -180,7 +197,12 @@ def main():
     ap.add_argument("--stream-streams", type=int, default=1, help="streams for the streaming run (0: skip)")
     ap.add_argument("--stream-fold", type=int, default=8, help="blocks per fold (deadline = fold x period)")
     ap.add_argument("--stream-blocks", type=int, default=384, help="blocks per stream after one warm-up integration")
-    ap.add_argument("--stream-only", action="store_true", help="run only the streaming measurement")
+    ap.add_argument("--stream-sweep", default="1,2,4",
+                    help="fold lengths k for extra one-stream runs of --stream-sweep-blocks blocks ('' to skip)")
+    ap.add_argument("--stream-sweep-blocks", type=int, default=192)
+    ap.add_argument("--stream-multi", type=int, default=5,
+                    help="streams requested for the admission/multi-stream run at --stream-fold (0: skip)")
+    ap.add_argument("--stream-only", action="store_true", help="run only the streaming measurements")
     ap.add_argument("--batch-only", action="store_true", help="run only the batch measurement")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -198,8 +220,7 @@ def main():
     dev = "cuda:0"
     stream = torch.cuda.current_stream()
     if args.stream_only:
-        print(json.dumps(stream_bench(xe, inputs, torch, args.stream_streams, args.stream_fold, args.stream_blocks)),
-              flush=True)
+        print(json.dumps(stream_all(xe, inputs, torch, args)), flush=True)
         return
     if args.batch_only:
         print(json.dumps({k: batch_bench(xe, inputs, torch, dev, stream, k)
@@ -255,6 +276,15 @@ def main():
                 "algorithmic_flops_per_launch": flops,
                 "peak_achievable": round(achievable, 1), "frac_of_achievable": round(achieved / achievable, 4),
                 "achievable_probe": peak_probe}
+    if src_kind == "mfma16":
+        # what the matrix cores actually execute (tiles below the diagonal of
+        # diagonal block pairs included; three or four real products)
+        ex = executed_flops_mfma16(S, C, T, resolved["time_split"], resolved["product"])
+        roofline.update({"products": 3 if resolved["product"] == xe.XC_PRODUCT_THREE else 4,
+                         "executed_flops_per_launch": ex,
+                         "executed_TFLOP/s": round(ex / (ms_launch * 1e-3) / 1e12, 2),
+                         "executed_frac": round(ex / (ms_launch * 1e-3) / 1e12 / peak, 4),
+                         "executed_frac_of_achievable": round(ex / (ms_launch * 1e-3) / 1e12 / achievable, 4)})
     dtype = {"cf32": "f32", "ci8": "i8->i32", "cf16": "f16->f32", "cbf16": "bf16->f32"}[kind_in]
     desc = DESCRIPTIONS["lofar64" if args.workload == "lofar64" else "p256"]
     res = {"metric": "visibility TFLOP/s (8 flop/CMAC) + % roofline, FP32 vs MFMA; stream p99",
@@ -273,9 +303,7 @@ def main():
         if args.batch != "none":
             res["batch"] = {k: batch_bench(xe, inputs, torch, dev, stream, k)
                             for k in (["ci8", "cf32"] if args.batch == "both" else [args.batch])}
-        if args.stream_streams > 0:
-            res["stream"] = stream_bench(xe, inputs, torch, args.stream_streams, args.stream_fold,
-                                         args.stream_blocks)
+        res.update(stream_all(xe, inputs, torch, args))
 
     if not args.no_cpu_baseline:
         xh = None
@@ -303,6 +331,8 @@ def compare_paths(xe, inputs, torch, dev, stream, steps=10):
              ("f16_mfma", "cf16", None, "fp16_mfma_TF"),
              ("bf16_mfma", "cbf16", None, "bf16_mfma_TF"),
              ("f32_mfma", "cf32", {"kernel": xe.XC_KERNEL_MFMA}, "fp32_mfma_TF"),
+             ("f32_mfma_4products", "cf32", {"kernel": xe.XC_KERNEL_MFMA, "product": xe.XC_PRODUCT_FOUR},
+              "fp32_mfma_TF"),
              ("f32_valu", "cf32", {"kernel": xe.XC_KERNEL_VALU}, "fp32_valu_TF")]
     for name, kind, cfg, peak_key in cases:
         if kind == "ci8":
@@ -320,6 +350,8 @@ def compare_paths(xe, inputs, torch, dev, stream, steps=10):
         byts = hbm_in[kind] + vis_bytes
         peak = PEAKS[peak_key]
         out[name] = {"workload": "256 stations, 1024 channels, 1024 samples (int8 values)",
+                     "config": xe.resolve_config((xe.in_type_of(x)[0], C, T, S, 2),
+                                                 xe.XC_OUT_CI32 if kind == "ci8" else xe.XC_OUT_CF32, config=cfg),
                      "ms": round(ms, 4), "TFLOP/s": round(tf, 2), "frac_of_compute_peak": round(tf / peak, 4),
                      "algorithmic_GB/s": round(byts / (ms * 1e-3) / 1e9, 1),
                      "frac_of_hbm": round(byts / (ms * 1e-3) / 1e9 / PEAKS["hbm_GBs"], 4)}
@@ -363,6 +395,22 @@ def batch_bench(xe, inputs, torch, dev, stream, kind, steps=5):
             "per_item_launches_ms": round(ms_each, 3), "per_item_TFLOP/s": round(flops / ms_each / 1e9, 1)}
 
 
+def stream_all(xe, inputs, torch, args):
+    """The streaming measurements: the main run (--stream-streams streams,
+    folds of --stream-fold blocks), a sweep of shorter folds on one stream,
+    and a run that asks for more streams than the device memory admits."""
+    out = {}
+    if args.stream_streams > 0:
+        out["stream"] = stream_bench(xe, inputs, torch, args.stream_streams, args.stream_fold, args.stream_blocks)
+    ks = [int(v) for v in args.stream_sweep.split(",") if v.strip()]
+    if ks:
+        out["stream_sweep"] = [stream_bench(xe, inputs, torch, 1, k, args.stream_sweep_blocks) for k in ks]
+    if args.stream_multi > 0:
+        out["stream_multi"] = stream_bench(xe, inputs, torch, args.stream_multi, args.stream_fold,
+                                           args.stream_sweep_blocks)
+    return out
+
+
 def stream_bench(xe, inputs, torch, n_streams, k, n_blocks, S=512, C=4096, bt=256, bpi=192):
     """Streaming: 512 stations, 4096 channels, complex int8 blocks of 256
     samples arriving every P = 256 / 49152 s (192 blocks = one second per
@@ -371,8 +419,10 @@ def stream_bench(xe, inputs, torch, n_streams, k, n_blocks, S=512, C=4096, bt=25
     random blocks and a block 'arrives' at its scheduled host time t0 + n P.
     Block latency = fold completion - block arrival; fold latency = fold
     completion - arrival of its last block, with the real-time deadline k P
-    (each fold finishes before the next fold's blocks are all in)."""
+    (each fold finishes before the next fold's blocks are all in).  Streams
+    that the server refuses for lack of device memory are counted, not run."""
     P = bt / 49152.0
+    torch.cuda.empty_cache()    # the admission budget is a share of the free device memory
     srv = xe.Server()
     desc = xe.Server.desc(S, C, bt, bpi, blocks_per_fold=k, ring_blocks=2 * k, in_type=xe.XC_IN_CI8,
                           acc_type=xe.XC_OUT_CI32, block_period_s=P)
@@ -404,6 +454,7 @@ def stream_bench(xe, inputs, torch, n_streams, k, n_blocks, S=512, C=4096, bt=25
             while time.monotonic_ns() < due:
                 pass
             for sid in sids:
+                waited = False
                 while True:
                     try:
                         srv.acquire(sid)
@@ -411,7 +462,8 @@ def stream_bench(xe, inputs, torch, n_streams, k, n_blocks, S=512, C=4096, bt=25
                     except xe.XengineError as e:
                         if e.status_name != "XC_ERR_BACKPRESSURE":
                             raise
-                        stalls += 1
+                        waited = True
+                stalls += waited    # blocks whose ring slot was still being folded at arrival
                 srv.commit(sid, due)
         return stalls
 
@@ -435,7 +487,8 @@ def stream_bench(xe, inputs, torch, n_streams, k, n_blocks, S=512, C=4096, bt=25
             "fold_p99_ms": [round(p["fold_p99_ms"], 3) for p in per],
             "fold_max_ms": [round(p["fold_max_ms"], 3) for p in per],
             "blocks": [p["blocks"] for p in per], "folds": [p["folds"] for p in per],
-            "fold_misses": [p["misses"] for p in per], "integrations": [p["integrations"] for p in per],
+            "fold_misses": [p["misses"] for p in per], "block_misses": [p["block_misses"] for p in per],
+            "integrations": [p["integrations"] for p in per],
             "sustained_TFLOP/s": [round(p["tflops"], 1) for p in per], "producer_stalls": stalls,
             "realtime_TFLOP/s_needed_per_stream": round(xe.flops(S, C, bt) / P / 1e12, 1)}
 

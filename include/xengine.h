@@ -86,6 +86,23 @@ typedef enum xc_staging {
                                  % 2 == 0 for 16-bit samples                          */
 } xc_staging;
 
+/* How a complex multiply-accumulate is formed from real products.  With the
+ * conjugate on station j (Section 2), Re V = sum ar br + ai bi and
+ * Im V = sum ai br - ar bi: four real products.  The three-product (Gauss)
+ * form accumulates P1 = sum ar br, P2 = sum ai bi and
+ * P3 = sum (ar + ai)(br - bi) and returns Re V = P1 + P2,
+ * Im V = P3 - P1 + P2: a quarter fewer matrix-core instructions, at a
+ * rounding error bounded by the magnitudes of P1, P2 and P3 rather than of
+ * V (still within single-precision accumulation error in practice; the
+ * tests hold it to the same tolerance).  Throughput is still counted at 8
+ * flops per complex multiply-accumulate. */
+typedef enum xc_product {
+    XC_PRODUCT_AUTO = 0,
+    XC_PRODUCT_FOUR = 1,   /* four real products (every kernel)                       */
+    XC_PRODUCT_THREE = 2   /* three real products: complex-float32 on 64-station
+                              matrix-core blocks only                                  */
+} xc_product;
+
 /* Largest integration for which XC_OUT_CI32 is exact for every input:
  * |re|,|im| <= 2 * 127^2 * T <= 2^31 - 1  <=>  T <= 66572. */
 #define XC_CI32_MAX_TIMES 66572
@@ -151,6 +168,8 @@ xc_status xc_correlate(const void *samples, xc_in_type in_type, int32_t n_statio
  *                 stage through registers; int8 and 16-bit samples on
  *                 64-station blocks take either (AUTO: LDS when the station
  *                 count allows it).
+ *   product       xc_product.  AUTO: three products for complex-float32 on
+ *                 64-station matrix-core blocks, four everywhere else.
  */
 typedef struct xc_config {
     int32_t kernel;
@@ -158,6 +177,7 @@ typedef struct xc_config {
     int32_t time_chunk;
     int32_t time_split;
     int32_t staging;
+    int32_t product;
 } xc_config;
 
 /* Checks a configuration against a shape without touching the device.
@@ -293,6 +313,10 @@ typedef struct xc_latency_stats {
     int64_t folds;                  /* folds whose latency was measured             */
     int64_t misses;                 /* folds whose latency exceeded the deadline    */
     int64_t integrations;           /* integrations published                       */
+    int64_t block_misses;           /* blocks whose own latency exceeded deadline_ms
+                                       (the stricter per-block reading: a block's
+                                       fold must end within k block periods of
+                                       that block's arrival)                         */
 } xc_latency_stats;
 
 typedef struct xc_server xc_server;

@@ -21,7 +21,7 @@ import torch
 from . import _lib
 from ._lib import (XC_CI32_MAX_TIMES, XC_IN_CBF16, XC_IN_CF16, XC_IN_CF32, XC_IN_CI8, XC_KERNEL_AUTO,
                    XC_KERNEL_MFMA, XC_KERNEL_VALU, XC_OUT_CF32, XC_OUT_CI32, XC_STAGING_AUTO, XC_STAGING_LDS,
-                   XC_STAGING_REGISTERS, XengineError)
+                   XC_STAGING_REGISTERS, XC_PRODUCT_AUTO, XC_PRODUCT_FOUR, XC_PRODUCT_THREE, XengineError)
 
 __all__ = ["correlate", "correlate_into", "n_baselines", "baseline_index", "tile_cost", "perf_max", "ai_global",
            "flops", "resolve_config", "BatchPlan", "batch_worklist", "autotune", "tune_cache_load", "Server",
@@ -119,12 +119,12 @@ def _config(config):
         return config
     return _lib.XcConfig(int(config.get("kernel", 0)), int(config.get("block", 0)),
                          int(config.get("time_chunk", 0)), int(config.get("time_split", 0)),
-                         int(config.get("staging", 0)))
+                         int(config.get("staging", 0)), int(config.get("product", 0)))
 
 
 def _config_dict(c) -> dict:
     return {"kernel": c.kernel, "block": c.block, "time_chunk": c.time_chunk, "time_split": c.time_split,
-            "staging": c.staging}
+            "staging": c.staging, "product": c.product}
 
 
 def resolve_config(x_shape_type, out_type=XC_OUT_CF32, config=None) -> dict:

@@ -25,11 +25,12 @@ XC_PEAK_F32_MFMA16, XC_PEAK_F32_MFMA32, XC_PEAK_I8_MFMA, XC_PEAK_F16_MFMA, XC_PE
 
 
 XC_STAGING_AUTO, XC_STAGING_REGISTERS, XC_STAGING_LDS = 0, 1, 2
+XC_PRODUCT_AUTO, XC_PRODUCT_FOUR, XC_PRODUCT_THREE = 0, 1, 2
 
 
 class XcConfig(ctypes.Structure):
     _fields_ = [("kernel", c_i32), ("block", c_i32), ("time_chunk", c_i32), ("time_split", c_i32),
-                ("staging", c_i32)]
+                ("staging", c_i32), ("product", c_i32)]
 
 
 class XcSubarray(ctypes.Structure):
@@ -46,7 +47,8 @@ class XcStreamDesc(ctypes.Structure):
 class XcLatencyStats(ctypes.Structure):
     _fields_ = [("p50_ms", c_f64), ("p99_ms", c_f64), ("max_ms", c_f64), ("fold_p50_ms", c_f64),
                 ("fold_p99_ms", c_f64), ("fold_max_ms", c_f64), ("deadline_ms", c_f64), ("tflops", c_f64),
-                ("blocks", c_i64), ("folds", c_i64), ("misses", c_i64), ("integrations", c_i64)]
+                ("blocks", c_i64), ("folds", c_i64), ("misses", c_i64), ("integrations", c_i64),
+                ("block_misses", c_i64)]
 
 
 # name -> (restype, argtypes): every symbol include/xengine.h declares

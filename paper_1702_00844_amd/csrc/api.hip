@@ -100,7 +100,7 @@ xc_status resolve(const xc_config *cfg_in, xc_in_type in_type, xc_out_type out_t
         return set_error(XC_ERR_OVERFLOW_RISK, "n_times = %d > %d: int32 visibilities could overflow", T,
                          XC_CI32_MAX_TIMES);
 
-    xc_config cfg = {0, 0, 0, 0, 0};
+    xc_config cfg = {0, 0, 0, 0, 0, 0};
     if (cfg_in) cfg = *cfg_in;
     if (cfg.kernel == XC_KERNEL_AUTO && !cfg_in) {
         xc_config tuned;
@@ -112,7 +112,10 @@ xc_status resolve(const xc_config *cfg_in, xc_in_type in_type, xc_out_type out_t
         return set_error(XC_ERR_INVALID_ARG, "invalid kernel %d", cfg.kernel);
     if (cfg.staging < XC_STAGING_AUTO || cfg.staging > XC_STAGING_LDS)
         return set_error(XC_ERR_INVALID_ARG, "invalid staging %d", cfg.staging);
+    if (cfg.product < XC_PRODUCT_AUTO || cfg.product > XC_PRODUCT_THREE)
+        return set_error(XC_ERR_INVALID_ARG, "invalid product %d", cfg.product);
     Plan p;
+    p.product = XC_PRODUCT_FOUR;
     p.kernel = kernel;
     if (kernel == XC_KERNEL_VALU) {
         if (in_type != XC_IN_CF32)
@@ -151,6 +154,7 @@ xc_status resolve(const xc_config *cfg_in, xc_in_type in_type, xc_out_type out_t
         if (p.staging == XC_STAGING_REGISTERS && f16tile)
             return set_error(XC_ERR_INVALID_ARG,
                              "complex-float32 on 64-station blocks copies straight into LDS only");
+        if (f16tile) p.product = cfg.product ? cfg.product : kDefaultProductF32;
         p.time_split = cfg.time_split ? cfg.time_split : (f16tile && S <= 64 ? 2 : 1);
         if (!(p.time_split == 1 || (f16tile && p.time_split == 2)))
             return set_error(XC_ERR_INVALID_ARG,
@@ -160,6 +164,9 @@ xc_status resolve(const xc_config *cfg_in, xc_in_type in_type, xc_out_type out_t
         if (p.time_chunk != chunk)
             return set_error(XC_ERR_INVALID_ARG, "MFMA time_chunk for this configuration must be %d", chunk);
     }
+    if (cfg.product == XC_PRODUCT_THREE && p.product != XC_PRODUCT_THREE)
+        return set_error(XC_ERR_INVALID_ARG,
+                         "the three-product form is available for complex-float32 on 64-station MFMA blocks only");
     const int64_t nb = (S + p.block - 1) / p.block;
     const int64_t nwork = (int64_t)C * (nb * (nb + 1) / 2);
     if (nwork > (int64_t)1 << 30)
@@ -280,6 +287,7 @@ xc_status xc_resolve_config(const xc_config *cfg, xc_in_type in_type, xc_out_typ
         resolved->time_chunk = p.time_chunk;
         resolved->time_split = p.time_split;
         resolved->staging = p.staging;
+        resolved->product = p.product;
     }
     return XC_OK;
 }

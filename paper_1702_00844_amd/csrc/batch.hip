@@ -113,7 +113,8 @@ static hipError_t plan_enqueue(xc_batch_plan *p, hipStream_t s) {
 
 static bool same_plan(const Plan &a, const Plan &b) {
     return a.kernel == b.kernel && a.block == b.block && a.time_chunk == b.time_chunk &&
-           a.time_split == b.time_split && a.staging == b.staging;
+           a.time_split == b.time_split && a.staging == b.staging &&
+           a.product == b.product;
 }
 
 extern "C" {
@@ -152,7 +153,7 @@ xc_status xc_batch_plan_create(const xc_subarray *items, int32_t n_items, int32_
     // Without an explicit configuration every item runs one time group per
     // workgroup; items whose configurations still differ (e.g. the staging of
     // int8 samples, which depends on the station count) get one launch each.
-    const xc_config one_group = {XC_KERNEL_AUTO, 0, 0, 1, XC_STAGING_AUTO};
+    const xc_config one_group = {XC_KERNEL_AUTO, 0, 0, 1, XC_STAGING_AUTO, XC_PRODUCT_AUTO};
     if (!cfg) cfg = &one_group;
     std::vector<int32_t> S(n_items), C(n_items), T(n_items);
     std::vector<Plan> plans;                 // distinct configurations, in order of first use

@@ -90,7 +90,10 @@ struct Plan {
     int time_chunk;  // time steps per LDS stage
     int time_split;  // waves sharing one output block over time
     int staging;     // XC_STAGING_REGISTERS or XC_STAGING_LDS
+    int product;     // XC_PRODUCT_FOUR or XC_PRODUCT_THREE
 };
+// Product form that AUTO picks for complex-float32 on 64-station matrix-core blocks.
+constexpr int kDefaultProductF32 = XC_PRODUCT_THREE;
 
 // Launchers (return hipSuccess or the launch error).
 hipError_t launch_valu(const Plan &plan, const Job &job, hipStream_t stream);

@@ -114,8 +114,8 @@ __device__ __forceinline__ void store_tile(const Job &job, int c, const v4f &re,
     }
 }
 
-// One wave's share of a block pair.  G = time group (0 .. TS-1).
-template <bool DIAG, int W, int TS>
+// One wave's share of a block pair.  G3 selects the three-product form.
+template <bool DIAG, int W, int TS, bool G3>
 __device__ __forceinline__ void wave_unit(const Job &job, int c, int bi, int bj, uint8_t *lds, int tid) {
     typedef Sched<DIAG, W> SC;
     constexpr int NT = SC::NT;
@@ -138,11 +138,15 @@ __device__ __forceinline__ void wave_unit(const Job &job, int c, int bi, int bj,
         any |= (I0 * 2 + tr * 16 < 2 * S) && (J0 * 2 + tc * 16 < 2 * S);
     }
 
-    v4f are[NT], aim[NT];
+    // Four-product form: are = Re V, aim = Im V.  Three-product form: are =
+    // P1 = sum ar br, aim = P2 = sum ai bi, a3 = P3 = sum (ar + ai)(br - bi);
+    // then Re V = P1 + P2 and Im V = P3 - P1 + P2.
+    v4f are[NT], aim[NT], a3[G3 ? NT : 1];
 #pragma unroll
     for (int s = 0; s < NT; ++s) {
         are[s] = v4f{0.f, 0.f, 0.f, 0.f};
         aim[s] = v4f{0.f, 0.f, 0.f, 0.f};
+        if constexpr (G3) a3[s] = v4f{0.f, 0.f, 0.f, 0.f};
     }
 
     constexpr int PITCH = pitch<DIAG>();
@@ -218,6 +222,23 @@ __device__ __forceinline__ void wave_unit(const Job &job, int c, int bi, int bj,
             if (i + 1 < NK) frag(grp + (i + 1) * TS, fa[cur ^ 1], fb[cur ^ 1]);
             const float2(&a)[SC::NA] = fa[cur];
             const float2(&b)[SC::NB] = fb[cur];
+            if constexpr (G3) {
+                float sa[SC::NA], db[SC::NB];
+#pragma unroll
+                for (int k = 0; k < SC::NA; ++k) sa[k] = a[k].x + a[k].y;
+#pragma unroll
+                for (int k = 0; k < SC::NB; ++k) db[k] = b[k].x - b[k].y;
+#pragma unroll
+                for (int s = 0; s < NT; ++s)
+                    are[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[SC::a_of(s)].x, b[SC::b_of(s)].x, are[s], 0, 0, 0);
+#pragma unroll
+                for (int s = 0; s < NT; ++s)
+                    aim[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[SC::a_of(s)].y, b[SC::b_of(s)].y, aim[s], 0, 0, 0);
+#pragma unroll
+                for (int s = 0; s < NT; ++s)
+                    a3[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(sa[SC::a_of(s)], db[SC::b_of(s)], a3[s], 0, 0, 0);
+                continue;
+            }
 #pragma unroll
             for (int s = 0; s < NT; ++s)
                 are[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[SC::a_of(s)].x, b[SC::b_of(s)].x, are[s], 0, 0, 0);
@@ -233,6 +254,14 @@ __device__ __forceinline__ void wave_unit(const Job &job, int c, int bi, int bj,
 #pragma unroll
             for (int s = 0; s < NT; ++s)
                 aim[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[SC::a_of(s)].x, nby[SC::b_of(s)], aim[s], 0, 0, 0);
+        }
+    }
+    if constexpr (G3) {
+#pragma unroll
+        for (int s = 0; s < NT; ++s) {
+            const v4f re = are[s] + aim[s];
+            aim[s] = (a3[s] - are[s]) + aim[s];
+            are[s] = re;
         }
     }
     // every wave is done with the stages before they are reused below
@@ -278,29 +307,29 @@ __device__ __forceinline__ void wave_unit(const Job &job, int c, int bi, int bj,
                        J0 * 2 + SC::bcol(SC::b_of(s)) * 16, lane);
 }
 
-template <int TS>
+template <int TS, bool G3>
 __device__ __forceinline__ void unit(const Job &job, int c, int bi, int bj, uint8_t *lds) {
     const int tid = threadIdx.x;
     const int w = __builtin_amdgcn_readfirstlane((tid >> 6) & 3);
     if (bi == bj) {
         switch (w) {
-        case 0: wave_unit<true, 0, TS>(job, c, bi, bj, lds, tid); break;
-        case 1: wave_unit<true, 1, TS>(job, c, bi, bj, lds, tid); break;
-        case 2: wave_unit<true, 2, TS>(job, c, bi, bj, lds, tid); break;
-        default: wave_unit<true, 3, TS>(job, c, bi, bj, lds, tid); break;
+        case 0: wave_unit<true, 0, TS, G3>(job, c, bi, bj, lds, tid); break;
+        case 1: wave_unit<true, 1, TS, G3>(job, c, bi, bj, lds, tid); break;
+        case 2: wave_unit<true, 2, TS, G3>(job, c, bi, bj, lds, tid); break;
+        default: wave_unit<true, 3, TS, G3>(job, c, bi, bj, lds, tid); break;
         }
     } else {
         switch (w) {
-        case 0: wave_unit<false, 0, TS>(job, c, bi, bj, lds, tid); break;
-        case 1: wave_unit<false, 1, TS>(job, c, bi, bj, lds, tid); break;
-        case 2: wave_unit<false, 2, TS>(job, c, bi, bj, lds, tid); break;
-        default: wave_unit<false, 3, TS>(job, c, bi, bj, lds, tid); break;
+        case 0: wave_unit<false, 0, TS, G3>(job, c, bi, bj, lds, tid); break;
+        case 1: wave_unit<false, 1, TS, G3>(job, c, bi, bj, lds, tid); break;
+        case 2: wave_unit<false, 2, TS, G3>(job, c, bi, bj, lds, tid); break;
+        default: wave_unit<false, 3, TS, G3>(job, c, bi, bj, lds, tid); break;
         }
     }
 }
 
 // LDS: two staging buffers (64 or 128 KiB), reused for the time-group reduction.
-template <int TS>
+template <int TS, bool G3>
 __global__ __launch_bounds__(256 * TS, 2 / TS) void kernel(Job job, int nwork) {
     __shared__ __attribute__((aligned(16))) uint8_t lds[2 * stage<TS>()];
     const int w = xcd_remap(blockIdx.x, nwork);
@@ -308,10 +337,10 @@ __global__ __launch_bounds__(256 * TS, 2 / TS) void kernel(Job job, int nwork) {
     const int c = w / job.npairs;
     int bi, bj;
     pair_decode(w - c * job.npairs, bi, bj);
-    unit<TS>(job, c, bi, bj, lds);
+    unit<TS, G3>(job, c, bi, bj, lds);
 }
 
-template <int TS>
+template <int TS, bool G3>
 __global__ __launch_bounds__(256 * TS, 2 / TS) void kernel_batch(const Job *__restrict__ jobs,
                                                                  const Unit *__restrict__ units,
                                                                  const int *__restrict__ bounds) {
@@ -320,29 +349,41 @@ __global__ __launch_bounds__(256 * TS, 2 / TS) void kernel_batch(const Job *__re
     if (u < 0) return;
     const Unit un = units[u];
     const Job job = jobs[un.item];
-    unit<TS>(job, un.channel, un.bi, un.bj, lds);
+    unit<TS, G3>(job, un.channel, un.bi, un.bj, lds);
 }
 
 }  // namespace mfma16
 
-hipError_t launch_mfma16(const Plan &plan, const Job &job, hipStream_t stream) {
+namespace mfma16 {
+template <int TS, bool G3>
+hipError_t launch_t(const Job &job, hipStream_t stream) {
     const int nwork = job.C * job.npairs;
-    if (plan.time_split == 2) {
-        hipLaunchKernelGGL(mfma16::kernel<2>, dim3(xcd_grid(nwork)), dim3(512), 0, stream, job, nwork);
-    } else {
-        hipLaunchKernelGGL(mfma16::kernel<1>, dim3(xcd_grid(nwork)), dim3(256), 0, stream, job, nwork);
-    }
+    hipLaunchKernelGGL((kernel<TS, G3>), dim3(xcd_grid(nwork)), dim3(256 * TS), 0, stream, job, nwork);
     return hipGetLastError();
+}
+template <int TS, bool G3>
+hipError_t launch_batch_t(const Job *jobs, const Unit *units, const int *bounds, int grid, hipStream_t stream) {
+    hipLaunchKernelGGL((kernel_batch<TS, G3>), dim3(grid), dim3(256 * TS), 0, stream, jobs, units, bounds);
+    return hipGetLastError();
+}
+}  // namespace mfma16
+
+hipError_t launch_mfma16(const Plan &plan, const Job &job, hipStream_t stream) {
+    using namespace mfma16;
+    const bool g3 = plan.product == XC_PRODUCT_THREE;
+    if (plan.time_split == 2) return g3 ? launch_t<2, true>(job, stream) : launch_t<2, false>(job, stream);
+    return g3 ? launch_t<1, true>(job, stream) : launch_t<1, false>(job, stream);
 }
 
 hipError_t launch_mfma16_batch(const Plan &plan, const Job *jobs, const Unit *units, const int *bounds, int grid,
                                hipStream_t stream) {
-    if (plan.time_split == 2) {
-        hipLaunchKernelGGL(mfma16::kernel_batch<2>, dim3(grid), dim3(512), 0, stream, jobs, units, bounds);
-    } else {
-        hipLaunchKernelGGL(mfma16::kernel_batch<1>, dim3(grid), dim3(256), 0, stream, jobs, units, bounds);
-    }
-    return hipGetLastError();
+    using namespace mfma16;
+    const bool g3 = plan.product == XC_PRODUCT_THREE;
+    if (plan.time_split == 2)
+        return g3 ? launch_batch_t<2, true>(jobs, units, bounds, grid, stream)
+                  : launch_batch_t<2, false>(jobs, units, bounds, grid, stream);
+    return g3 ? launch_batch_t<1, true>(jobs, units, bounds, grid, stream)
+              : launch_batch_t<1, false>(jobs, units, bounds, grid, stream);
 }
 
 }  // namespace xc

@@ -331,6 +331,8 @@ xc_status xc_stream_stats(xc_server *srv, int32_t id, xc_latency_stats *stats) {
     r.fold_max_ms = flat.empty() ? NAN : *std::max_element(flat.begin(), flat.end());
     for (double v : flat)
         if (deadline > 0 && v > deadline) r.misses++;
+    for (double v : lat)
+        if (deadline > 0 && v > deadline) r.block_misses++;
     const double span = (t_last > t_first && t_first != UINT64_MAX) ? (double)(t_last - t_first) * 1e-9 : 0.0;
     r.tflops = span > 0 ? s->flops_per_fold * (double)s->folds.size() / span * 1e-12 : 0.0;
     r.integrations = s->published_seq + 1;

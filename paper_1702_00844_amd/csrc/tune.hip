@@ -11,16 +11,16 @@ using namespace xc;
 
 static std::vector<xc_config> candidates(xc_in_type in_type) {
     std::vector<xc_config> v;
-    v.push_back(xc_config{XC_KERNEL_MFMA, 32, 0, 0, 0});
-    v.push_back(xc_config{XC_KERNEL_MFMA, 64, 0, 1, 0});
+    v.push_back(xc_config{XC_KERNEL_MFMA, 32, 0, 0, 0, 0});
     if (in_type != XC_IN_CF32) {   // both stagings (straight into LDS needs whole granules)
-        v.push_back(xc_config{XC_KERNEL_MFMA, 64, 0, 1, XC_STAGING_LDS});
-        v.push_back(xc_config{XC_KERNEL_MFMA, 64, 0, 1, XC_STAGING_REGISTERS});
-    }
-    if (in_type == XC_IN_CF32) v.push_back(xc_config{XC_KERNEL_MFMA, 64, 0, 2, 0});
-    if (in_type == XC_IN_CF32) {
+        v.push_back(xc_config{XC_KERNEL_MFMA, 64, 0, 1, XC_STAGING_LDS, 0});
+        v.push_back(xc_config{XC_KERNEL_MFMA, 64, 0, 1, XC_STAGING_REGISTERS, 0});
+    } else {   // one or two time groups, four or three real products
+        for (int ts = 1; ts <= 2; ++ts)
+            for (int pr = XC_PRODUCT_FOUR; pr <= XC_PRODUCT_THREE; ++pr)
+                v.push_back(xc_config{XC_KERNEL_MFMA, 64, 0, ts, 0, pr});
         const int opts[][2] = {{16, 1}, {16, 2}, {16, 4}, {32, 2}, {32, 4}, {32, 8}};
-        for (auto &o : opts) v.push_back(xc_config{XC_KERNEL_VALU, 32, o[0], o[1], 0});
+        for (auto &o : opts) v.push_back(xc_config{XC_KERNEL_VALU, 32, o[0], o[1], 0, 0});
     }
     return v;
 }
@@ -85,9 +85,9 @@ xc_status xc_autotune(const void *samples, xc_in_type in_type, int32_t n_station
         if (f) {
             fprintf(f,
                     "{\"in\": %d, \"out\": %d, \"S\": %d, \"C\": %d, \"T\": %d, \"kernel\": %d, \"block\": %d, "
-                    "\"time_chunk\": %d, \"time_split\": %d, \"staging\": %d, \"ms\": %.6f}\n",
+                    "\"time_chunk\": %d, \"time_split\": %d, \"staging\": %d, \"product\": %d, \"ms\": %.6f}\n",
                     (int)in_type, (int)out_type, n_stations, n_channels, n_times, best_c.kernel, best_c.block,
-                    best_c.time_chunk, best_c.time_split, best_c.staging, best_t);
+                    best_c.time_chunk, best_c.time_split, best_c.staging, best_c.product, best_t);
             fclose(f);
         }
     }
@@ -101,13 +101,13 @@ int64_t xc_tune_cache_load(const char *cache_path) {
     char line[512];
     int64_t n = 0;
     while (fgets(line, sizeof line, f)) {
-        int in, out, S, C, T, k, b, tc, ts, sg;
+        int in, out, S, C, T, k, b, tc, ts, sg, pr;
         double ms;
         if (sscanf(line,
                    " {\"in\": %d, \"out\": %d, \"S\": %d, \"C\": %d, \"T\": %d, \"kernel\": %d, \"block\": %d, "
-                   "\"time_chunk\": %d, \"time_split\": %d, \"staging\": %d, \"ms\": %lf",
-                   &in, &out, &S, &C, &T, &k, &b, &tc, &ts, &sg, &ms) == 11) {
-            xc_config c{k, b, tc, ts, sg};
+                   "\"time_chunk\": %d, \"time_split\": %d, \"staging\": %d, \"product\": %d, \"ms\": %lf",
+                   &in, &out, &S, &C, &T, &k, &b, &tc, &ts, &sg, &pr, &ms) == 12) {
+            xc_config c{k, b, tc, ts, sg, pr};
             xc_config r;
             if (xc_resolve_config(&c, (xc_in_type)in, (xc_out_type)out, S, 2, C, T, &r) == XC_OK) {
                 tune_put(TuneKey{in, out, S, C, T}, r);

@@ -111,15 +111,16 @@ def test_int32_bound_is_exact():
 
 def test_config_resolution():
     R, L = _lib.XC_STAGING_REGISTERS, _lib.XC_STAGING_LDS
+    F4, F3 = _lib.XC_PRODUCT_FOUR, _lib.XC_PRODUCT_THREE
     shp = (_lib.XC_IN_CF32, 256, 768, 64, 2)
     r = xe.resolve_config(shp, config={"kernel": _lib.XC_KERNEL_VALU})
-    assert r == {"kernel": 1, "block": 32, "time_chunk": 16, "time_split": 4, "staging": R}
+    assert r == {"kernel": 1, "block": 32, "time_chunk": 16, "time_split": 4, "staging": R, "product": F4}
     r = xe.resolve_config(shp, config={"kernel": _lib.XC_KERNEL_MFMA})
-    assert r == {"kernel": 2, "block": 64, "time_chunk": 32, "time_split": 2, "staging": L}
+    assert r == {"kernel": 2, "block": 64, "time_chunk": 32, "time_split": 2, "staging": L, "product": F3}
     r = xe.resolve_config((_lib.XC_IN_CF32, 1024, 1024, 256, 2), config={"kernel": _lib.XC_KERNEL_MFMA})
-    assert r == {"kernel": 2, "block": 64, "time_chunk": 16, "time_split": 1, "staging": L}
+    assert r == {"kernel": 2, "block": 64, "time_chunk": 16, "time_split": 1, "staging": L, "product": F3}
     r = xe.resolve_config(shp, config={"kernel": _lib.XC_KERNEL_MFMA, "block": 32})
-    assert r == {"kernel": 2, "block": 32, "time_chunk": 16, "time_split": 1, "staging": R}
+    assert r == {"kernel": 2, "block": 32, "time_chunk": 16, "time_split": 1, "staging": R, "product": F4}
     with pytest.raises(xe.XengineError):     # FP32 on 64-station blocks copies straight into LDS only
         xe.resolve_config(shp, config={"kernel": _lib.XC_KERNEL_MFMA, "staging": R})
     with pytest.raises(xe.XengineError):     # VALU stages through registers only
@@ -131,11 +132,11 @@ def test_config_resolution():
     # int8 and 16-bit on 64-station blocks: straight into LDS when the station
     # count is a whole number of 16-byte granules, else through registers
     r = xe.resolve_config((_lib.XC_IN_CI8, 1024, 1024, 256, 2), _lib.XC_OUT_CI32)
-    assert r == {"kernel": 2, "block": 64, "time_chunk": 64, "time_split": 1, "staging": L}
+    assert r == {"kernel": 2, "block": 64, "time_chunk": 64, "time_split": 1, "staging": L, "product": F4}
     r = xe.resolve_config((_lib.XC_IN_CI8, 8, 64, 70, 2), _lib.XC_OUT_CI32)
-    assert r == {"kernel": 2, "block": 64, "time_chunk": 64, "time_split": 1, "staging": R}
+    assert r == {"kernel": 2, "block": 64, "time_chunk": 64, "time_split": 1, "staging": R, "product": F4}
     r = xe.resolve_config((_lib.XC_IN_CI8, 8, 64, 68, 2), _lib.XC_OUT_CI32, config={"kernel": 2, "staging": R})
-    assert r == {"kernel": 2, "block": 64, "time_chunk": 64, "time_split": 1, "staging": R}
+    assert r == {"kernel": 2, "block": 64, "time_chunk": 64, "time_split": 1, "staging": R, "product": F4}
     with pytest.raises(xe.XengineError):
         xe.resolve_config((_lib.XC_IN_CI8, 8, 64, 70, 2), config={"kernel": 2, "staging": L})
     with pytest.raises(xe.XengineError):
@@ -143,15 +144,28 @@ def test_config_resolution():
     with pytest.raises(xe.XengineError):
         xe.resolve_config((_lib.XC_IN_CI8, 8, 64, 68, 2), config={"kernel": 2, "time_chunk": 32})
     r = xe.resolve_config((_lib.XC_IN_CF16, 1024, 1024, 256, 2))
-    assert r == {"kernel": 2, "block": 64, "time_chunk": 32, "time_split": 1, "staging": L}
+    assert r == {"kernel": 2, "block": 64, "time_chunk": 32, "time_split": 1, "staging": L, "product": F4}
     r = xe.resolve_config((_lib.XC_IN_CBF16, 8, 64, 33, 2))
-    assert r == {"kernel": 2, "block": 64, "time_chunk": 32, "time_split": 1, "staging": R}
+    assert r == {"kernel": 2, "block": 64, "time_chunk": 32, "time_split": 1, "staging": R, "product": F4}
     with pytest.raises(xe.XengineError):
         xe.resolve_config((_lib.XC_IN_CBF16, 8, 64, 33, 2), config={"kernel": 2, "staging": L})
     with pytest.raises(xe.XengineError):
         xe.resolve_config((_lib.XC_IN_CI8, 4, 16, 8, 2), config={"kernel": _lib.XC_KERNEL_VALU})
     with pytest.raises(xe.XengineError):
         xe.resolve_config(shp, config={"kernel": _lib.XC_KERNEL_VALU, "time_split": 3})
+    # the three-product form: complex-float32 on 64-station matrix-core blocks only
+    r = xe.resolve_config(shp, config={"kernel": _lib.XC_KERNEL_MFMA, "product": F4})
+    assert r == {"kernel": 2, "block": 64, "time_chunk": 32, "time_split": 2, "staging": L, "product": F4}
+    r = xe.resolve_config(shp, config={"kernel": _lib.XC_KERNEL_MFMA, "time_split": 1, "product": F3})
+    assert r == {"kernel": 2, "block": 64, "time_chunk": 16, "time_split": 1, "staging": L, "product": F3}
+    for bad in ({"kernel": _lib.XC_KERNEL_VALU, "product": F3}, {"kernel": 2, "block": 32, "product": F3},
+                {"kernel": 2, "product": 3}, {"kernel": 2, "product": -1}):
+        with pytest.raises(xe.XengineError):
+            xe.resolve_config(shp, config=bad)
+    with pytest.raises(xe.XengineError):
+        xe.resolve_config((_lib.XC_IN_CI8, 1024, 1024, 256, 2), _lib.XC_OUT_CI32, config={"product": F3})
+    with pytest.raises(xe.XengineError):
+        xe.resolve_config((_lib.XC_IN_CF16, 1024, 1024, 256, 2), config={"product": F3})
 
 
 def test_status_strings():

@@ -22,9 +22,12 @@ VALU = [dict(kernel=xe.XC_KERNEL_VALU, time_chunk=tc, time_split=ts)
         for tc, ts in [(16, 1), (16, 2), (16, 4), (32, 2), (32, 4), (32, 8)]]
 MFMA = dict(kernel=xe.XC_KERNEL_MFMA)
 # complex-float32 matrix-core variants: 32x32 tiles on 32-station blocks, and
-# 16x16 tiles on 64-station blocks with one or two time groups
+# 16x16 tiles on 64-station blocks with one or two time groups, each with the
+# three-product (default) and the four-product form
 MFMA_F32 = [dict(kernel=xe.XC_KERNEL_MFMA, block=32), dict(kernel=xe.XC_KERNEL_MFMA, block=64, time_split=1),
-            dict(kernel=xe.XC_KERNEL_MFMA, block=64, time_split=2)]
+            dict(kernel=xe.XC_KERNEL_MFMA, block=64, time_split=2),
+            dict(kernel=xe.XC_KERNEL_MFMA, block=64, time_split=1, product=xe.XC_PRODUCT_FOUR),
+            dict(kernel=xe.XC_KERNEL_MFMA, block=64, time_split=2, product=xe.XC_PRODUCT_FOUR)]
 
 # (S, C, T): tiny, ragged station counts across block edges, ragged time tails
 SHAPES = [(1, 2, 1), (3, 1, 5), (8, 3, 17), (33, 2, 100), (64, 2, 64), (70, 1, 300), (130, 1, 77)]
@@ -37,7 +40,8 @@ def _cf32(S, C, T, seed):
 def _cfg_id(c):
     if c["kernel"] == xe.XC_KERNEL_VALU:
         return "valu_tc%d_ts%d" % (c["time_chunk"], c["time_split"])
-    return "mfma_b%d_ts%d" % (c.get("block", 0), c.get("time_split", 0))
+    return "mfma_b%d_ts%d%s" % (c.get("block", 0), c.get("time_split", 0),
+                                "_p4" if c.get("product") == xe.XC_PRODUCT_FOUR else "")
 
 
 @pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "S%d_C%d_T%d" % s)
@@ -150,7 +154,7 @@ def test_half_exact_on_integer_samples(dtype, cfg):
     assert np.array_equal(gpu_vis_numpy(v), ref[..., 0] + 1j * ref[..., 1])
 
 
-@pytest.mark.parametrize("cfg", [VALU[2]] + MFMA_F32, ids=["valu", "mfma_b32", "mfma_b64_ts1", "mfma_b64_ts2"])
+@pytest.mark.parametrize("cfg", [VALU[2]] + MFMA_F32, ids=_cfg_id)
 def test_accumulate_mode(cfg):
     S, C, T = 40, 3, 96
     x1 = _cf32(S, C, T, seed=11)
@@ -160,6 +164,32 @@ def test_accumulate_mode(cfg):
     torch.cuda.synchronize()
     ref = oracle_vis(torch.cat([x1, x2], dim=1))     # additivity over time
     assert rel_err(gpu_vis_numpy(v), ref) <= FP32_TOL
+
+
+@pytest.mark.parametrize("ts", [1, 2])
+def test_three_product_forward_error_bound(ts):
+    """The three-product form on strongly correlated samples (one common
+    signal in every station plus weak noise, so that for most baselines the
+    imaginary part is tiny next to P1, P2 and P3, the case its cancellation
+    hurts most): every element lies within the forward error bounds of
+    single-precision sums of T products, with M = sum_t |a_t| |b_t| and
+    u = 2^-24: |d Re V| <= (T + 4) u M (P1 + P2, where |ar br| + |ai bi| <=
+    |a| |b|) and |d Im V| <= 3 (T + 4) u M (P3 - P1 + P2, where
+    |ar + ai| |br - bi| <= 2 |a| |b|); and the normwise error within the
+    single-precision bar."""
+    S, C, T = 96, 2, 700
+    common = inputs.cn_gaussian(C, T, 1, seed=31, device=DEV)
+    x = (10.0 * common + 0.01 * _cf32(S, C, T, seed=32)).contiguous()
+    cfg = dict(kernel=xe.XC_KERNEL_MFMA, block=64, time_split=ts, product=xe.XC_PRODUCT_THREE)
+    got = gpu_vis_numpy(xe.correlate(x, config=cfg))
+    ref = oracle_vis(x)
+    mag = oracle_vis(x.abs().to(torch.complex64)).real     # sum_t |a_t| |b_t| (|x| rounded to float32)
+    bound = (T + 4) * 2.0 ** -24 * mag * (1 + 1e-6)
+    err_re, err_im = np.abs(got.real - ref.real), np.abs(got.imag - ref.imag)
+    assert np.all(err_re <= bound), float(np.max(err_re / bound))
+    assert np.all(err_im <= 3 * bound), float(np.max(err_im / (3 * bound)))
+    assert rel_err(got, ref) <= FP32_TOL
+    assert_hermitian_autos(got, S)
 
 
 @pytest.mark.parametrize("S", [66, 68])
