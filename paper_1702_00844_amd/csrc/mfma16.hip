@@ -3,7 +3,12 @@
 // Same product as the other MFMA kernels (per channel V = X X^H, computed as
 // Re V = Xr Xr^T + Xi Xi^T and Im V = Xi Xr^T - Xr Xi^T on real matrix cores,
 // with f32 products and accumulation), but on 16 x 16 output tiles so that the
-// triangle of station pairs is covered with little waste:
+// triangle of station pairs is covered with little waste.  Either four real
+// products per tile and time step, or three (Gauss's form for complex
+// multiplication): P1 = Xr Xr^T, P2 = Xi Xi^T and P3 = (Xr + Xi)(Xr - Xi)^T,
+// with Re V = P1 + P2 and Im V = P3 - P1 + P2 formed once at the end.  The
+// sums Xr + Xi and Xr - Xi are two vector adds per fragment; the three-product
+// form issues a quarter fewer MFMAs for 50 % more accumulator registers.
 //
 //  * A workgroup owns one (channel, block pair bi <= bj) of SB = 64 stations,
 //    i.e. a 128 x 128 square of (station, pol) rows split into 8 x 8 tiles.
@@ -110,6 +115,53 @@ __device__ __forceinline__ void store_tile(const Job &job, int c, const v4f &re,
             const size_t e2 = (jbase + i) * 4 + 2;
             if (job.accumulate) w = Out<float2>::add(w, V[e2]);
             V[e2] = w;
+        }
+    }
+}
+
+// Diagonal block pair, two time groups: the unit's triangle of baselines
+// (local j < nj, i <= j, at local index j (j + 1) / 2 + i, 32 bytes each,
+// at most 2080 x 32 = 66 560 bytes) is assembled in LDS as an image of the
+// output: time group 0 writes its sums, then time group 1 adds its own (so
+// each element is group 0's sum plus group 1's, as in the register
+// reduction), and the workgroup copies the image out in 16-byte granules,
+// a wave writing 1 KiB runs of consecutive baselines.  Autocorrelations are
+// written as the other stores do: XX, YY real, YX = conj(XY).
+template <bool ADD>
+__device__ __forceinline__ void image_tile(float2 *__restrict__ img, const v4f &re, const v4f &im, int trow,
+                                           int tcol, int nj, int lane) {
+    const int col = tcol * 16 + (lane & 15);
+    const int jl = col >> 1;
+    const int q = col & 1;
+    if (jl >= nj) return;
+    const int jb = jl * (jl + 1) / 2;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int row = trow * 16 + 4 * (lane >> 4) + r;
+        const int il = row >> 1;
+        const int p = row & 1;
+        if (il > jl) continue;
+        float vr = re[r];
+        float vi = im[r];
+        if (il == jl) {
+            if (p == 1 && q == 0) continue;     // written as conj(XY) by the q = 1 lane
+            if (p == q) vi = 0.f;
+        }
+        const int e = (jb + il) * 4 + p * 2 + q;
+        if (ADD) {
+            const float2 o = img[e];
+            img[e] = make_float2(o.x + vr, o.y + vi);
+        } else {
+            img[e] = make_float2(vr, vi);
+        }
+        if (il == jl && p == 0 && q == 1) {
+            const int e2 = (jb + il) * 4 + 2;
+            if (ADD) {
+                const float2 o = img[e2];
+                img[e2] = make_float2(o.x + vr, o.y - vi);
+            } else {
+                img[e2] = make_float2(vr, -vi);
+            }
         }
     }
 }
@@ -266,6 +318,45 @@ __device__ __forceinline__ void wave_unit(const Job &job, int c, int bi, int bj,
     }
     // every wave is done with the stages before they are reused below
     __syncthreads();
+
+    if constexpr (DIAG && TS == 2) {
+        static_assert(2080 * 32 <= 2 * STAGE, "the triangle image must fit the staging area");
+        float2 *img = reinterpret_cast<float2 *>(lds);
+        const int nj = S - J0 < SB ? S - J0 : SB;
+#pragma unroll
+        for (int ph = 0; ph < 2; ++ph) {
+            if (grp == ph && any) {
+#pragma unroll
+                for (int s = 0; s < NT; ++s) {
+                    if (ph == 0)
+                        image_tile<false>(img, are[s], aim[s], SC::arow(SC::a_of(s)), SC::bcol(SC::b_of(s)), nj, lane);
+                    else
+                        image_tile<true>(img, are[s], aim[s], SC::arow(SC::a_of(s)), SC::bcol(SC::b_of(s)), nj, lane);
+                }
+            }
+            __syncthreads();
+        }
+        const float4 *img4 = reinterpret_cast<const float4 *>(lds);
+        float4 *__restrict__ V4 = reinterpret_cast<float4 *>(static_cast<float2 *>(job.vis) +
+                                                             (size_t)c * ((size_t)S * (S + 1) / 2) * 4);
+        const int ng = nj * (nj + 1);     // 16-byte granules: two per baseline
+        for (int g = tid; g < ng; g += 256 * TS) {
+            const int bl = g >> 1;
+            int jl = (int)((sqrtf(8.f * (float)bl + 1.f) - 1.f) * 0.5f);
+            while ((jl + 1) * (jl + 2) / 2 <= bl) ++jl;
+            while (jl * (jl + 1) / 2 > bl) --jl;
+            const int il = bl - jl * (jl + 1) / 2;
+            const int j = J0 + jl;
+            float4 *dst = V4 + (((size_t)j * (j + 1) / 2 + I0 + il) * 2 + (g & 1));
+            float4 v = img4[g];
+            if (job.accumulate) {
+                const float4 o = *dst;
+                v = make_float4(v.x + o.x, v.y + o.y, v.z + o.z, v.w + o.w);
+            }
+            *dst = v;
+        }
+        return;
+    }
 
     if constexpr (TS > 1) {
         // group 1 hands its partial sums to group 0 through LDS (staging is free now)
