@@ -204,6 +204,8 @@ def main():
                     help="streams requested for the admission/multi-stream run at --stream-fold (0: skip)")
     ap.add_argument("--stream-only", action="store_true", help="run only the streaming measurements")
     ap.add_argument("--batch-only", action="store_true", help="run only the batch measurement")
+    ap.add_argument("--no-ingest", action="store_true", help="skip the host-ingest measurement")
+    ap.add_argument("--ingest-only", action="store_true", help="run only the host-ingest measurement")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this correlator build runs on one GPU; channels would shard across GPUs "
@@ -221,6 +223,9 @@ def main():
     stream = torch.cuda.current_stream()
     if args.stream_only:
         print(json.dumps(stream_all(xe, inputs, torch, args)), flush=True)
+        return
+    if args.ingest_only:
+        print(json.dumps({"ingest": ingest_bench(xe, inputs, torch, dev, stream)}), flush=True)
         return
     if args.batch_only:
         print(json.dumps({k: batch_bench(xe, inputs, torch, dev, stream, k)
@@ -304,6 +309,8 @@ def main():
             res["batch"] = {k: batch_bench(xe, inputs, torch, dev, stream, k)
                             for k in (["ci8", "cf32"] if args.batch == "both" else [args.batch])}
         res.update(stream_all(xe, inputs, torch, args))
+        if not args.no_ingest:
+            res["ingest"] = ingest_bench(xe, inputs, torch, dev, stream)
 
     if not args.no_cpu_baseline:
         xh = None
@@ -393,6 +400,112 @@ def batch_bench(xe, inputs, torch, dev, stream, kind, steps=5):
             "out_GB": round(out_bytes / 1e9, 2),
             "batch_graph_ms": round(ms_plan, 3), "batch_TFLOP/s": round(flops / ms_plan / 1e9, 1),
             "per_item_launches_ms": round(ms_each, 3), "per_item_TFLOP/s": round(flops / ms_each / 1e9, 1)}
+
+
+def ingest_bench(xe, inputs, torch, dev, stream, reps=5):
+    """Host ingest (Sections 3.6 and 4.4): the lofar64 block (complex float32)
+    and the p256 block (complex int8) held in pinned host memory, copied to the
+    device group by group and correlated.  Reports the pinned host-to-device
+    bandwidth, perf_max,global = AI_global x that bandwidth, the end-to-end
+    rate with copies overlapped (async) or in order with the computation
+    (sync), station-major input transposed on the GPU, the transpose's own
+    device bandwidth, and how much a concurrent copy slows the kernel."""
+    out = {}
+
+    def timed(fn, n):
+        fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(n):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / n
+
+    for name, S, C, T, kind in [("lofar64_cf32", 64, 256, 768, "cf32"), ("p256_ci8", 256, 1024, 1024, "ci8")]:
+        if kind == "cf32":
+            x, _ = inputs.point_sources(C, T, S, seed=2, device=dev)
+            in_type, sample = xe.XC_IN_CF32, 16
+        else:
+            x = inputs.ci8_gaussian(C, T, S, seed=3, device=dev)
+            in_type, sample = xe.XC_IN_CI8, 4
+        host_tm = x.cpu().pin_memory()
+        flops = xe.flops(S, C, T)
+        nbytes = C * T * S * sample
+        ai_global = flops / nbytes
+        dev_buf = torch.empty_like(x)
+        h2d_ms = timed(lambda: dev_buf.copy_(host_tm, non_blocking=True), reps)
+        h2d = nbytes / (h2d_ms * 1e-3) / 1e9
+        o = torch.empty(xe.vis_shape(C, S, xe.XC_OUT_CI32 if kind == "ci8" else xe.XC_OUT_CF32),
+                        dtype=torch.int32 if kind == "ci8" else torch.complex64, device=dev)
+        t_settle = time.perf_counter()
+        while time.perf_counter() - t_settle < 0.2:       # steady clock, as for the headline
+            timed(lambda: xe.correlate_into(x, o, stream=stream), 4)
+        kernel_ms = timed(lambda: xe.correlate_into(x, o, stream=stream), 20)
+        r = {"workload": f"{S} stations, {C} channels, {T} samples, {kind} in pinned host memory",
+             "host_bytes": nbytes, "h2d_GB/s": round(h2d, 2), "ai_global_flop_per_B": round(ai_global, 1),
+             "perf_max_global_TFLOP/s": round(ai_global * h2d / 1e3, 2),
+             "device_resident_ms": round(kernel_ms, 4),
+             "device_resident_TFLOP/s": round(flops / kernel_ms / 1e9, 1)}
+        ing = xe.Ingest(in_type, S, C, T, layout=xe.XC_LAYOUT_TIME_MAJOR)
+        r["channels_per_group"] = ing.channels_per_group
+        for tag, ov in (("async", True), ("sync", False)):
+            ms = timed(lambda: ing.run(host_tm, out=o, overlap=ov, stream=stream), reps)
+            r[f"time_major_{tag}_ms"] = round(ms, 3)
+            r[f"time_major_{tag}_TFLOP/s"] = round(flops / ms / 1e9, 2)
+        r["time_major_async_frac_of_perf_max_global"] = round(
+            r["time_major_async_TFLOP/s"] / r["perf_max_global_TFLOP/s"], 3)
+        ing.close()
+        # group size: fewer, larger copies against a longer pipeline fill
+        by_group = {}
+        for mib in (8, 32):
+            g = max(1, min(C, (mib << 20) // (T * S * sample)))
+            ing = xe.Ingest(in_type, S, C, T, layout=xe.XC_LAYOUT_TIME_MAJOR, channels_per_group=g)
+            by_group[f"{g}_channels"] = {
+                "async_ms": round(timed(lambda: ing.run(host_tm, out=o, overlap=True, stream=stream), reps), 3),
+                "sync_ms": round(timed(lambda: ing.run(host_tm, out=o, overlap=False, stream=stream), reps), 3)}
+            ing.close()
+        r["time_major_by_group"] = by_group
+        del host_tm
+        if kind == "cf32":
+            # station-major (natural) host layout, transposed on the GPU
+            x_sm = x.permute(0, 2, 1, 3).contiguous()
+            host_sm = x_sm.cpu().pin_memory()
+            ing = xe.Ingest(in_type, S, C, T, layout=xe.XC_LAYOUT_STATION_MAJOR)
+            ms = timed(lambda: ing.run(host_sm, out=o, overlap=True, stream=stream), reps)
+            r["station_major_async_ms"] = round(ms, 3)
+            r["station_major_async_TFLOP/s"] = round(flops / ms / 1e9, 2)
+            ing.close()
+            del host_sm
+            tr_ms = timed(lambda: xe.transpose_to_time_major(x_sm, out=dev_buf, stream=stream), 20)
+            r["device_transpose_ms"] = round(tr_ms, 4)
+            r["device_transpose_GB/s"] = round(2 * nbytes / (tr_ms * 1e-3) / 1e9, 1)
+            del x_sm
+            # the kernel while a 1 GiB pinned copy runs on another stream
+            big_h = torch.empty(1 << 30, dtype=torch.uint8).pin_memory()
+            big_d = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+            cs = torch.cuda.Stream()
+            torch.cuda.synchronize()
+            with torch.cuda.stream(cs):
+                big_d.copy_(big_h, non_blocking=True)
+            n_k = max(1, int(0.5 * (1 << 30) / max(h2d, 1.0) / 1e6 / kernel_ms))   # kernels within half the copy
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(n_k):
+                xe.correlate_into(x, o, stream=stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            during = e0.elapsed_time(e1) / n_k
+            r["kernel_during_copy_ms"] = round(during, 4)
+            r["kernel_slowdown_during_copy"] = round(during / kernel_ms, 3)
+            del big_h, big_d
+        out[name] = r
+        del x, o, dev_buf
+        torch.cuda.empty_cache()
+    return out
 
 
 def stream_all(xe, inputs, torch, args):

@@ -370,6 +370,67 @@ xc_status xc_stream_close(xc_server *srv, int32_t stream_id);
 double xc_quantile(const double *values, int64_t n, double q);
 
 /* ------------------------------------------------------------------------ */
+/* Host ingest: samples in host memory (Section 3.6's host-to-device bound,    */
+/* Section 4.4's asynchronous copies and memory-layout transpose).            */
+
+typedef enum xc_layout {
+    XC_LAYOUT_TIME_MAJOR = 0,     /* x[C][T][S][P]: all stations of a time step together */
+    XC_LAYOUT_STATION_MAJOR = 1   /* x[C][S][T][P]: each station's time series together,
+                                     the natural order of the preceding pipeline stages */
+} xc_layout;
+
+/*
+ * Out-of-place transpose of device samples from the station-major to the
+ * time-major layout, per channel (Section 4.4's memory-layout transpose):
+ * dst[c][t][s][p] = src[c][s][t][p].  Both buffers device, caller-owned,
+ * C * S * T * 2 complex samples of in_type, aligned to one station's
+ * dual-polarised sample (4, 8 or 16 bytes), not overlapping.  Enqueued on
+ * `stream`; argument errors (null or aligned-wrong pointer, src == dst, bad
+ * type or sizes, n_pol != 2) are returned before anything is enqueued.
+ */
+xc_status xc_transpose_to_time_major(const void *src, void *dst, xc_in_type in_type, int32_t n_stations,
+                                     int32_t n_pol, int32_t n_channels, int32_t n_times, void *stream);
+
+/*
+ * A plan that correlates C channels of samples held in host memory.  The
+ * channels are processed in groups of `channels_per_group` (0: about 128 MiB
+ * of samples per group); two device staging slots of one group each (four
+ * with station-major input: the copy and its transpose) are allocated here
+ * and freed by xc_ingest_destroy, together with a copy stream and events.
+ * Errors: XC_ERR_INVALID_ARG (bad type, sizes, layout or group size),
+ * XC_ERR_UNSUPPORTED (n_pol != 2), XC_ERR_OUT_OF_MEMORY, XC_ERR_HIP.
+ */
+typedef struct xc_ingest xc_ingest;
+xc_status xc_ingest_create(xc_in_type in_type, int32_t n_stations, int32_t n_pol, int32_t n_channels,
+                           int32_t n_times, int32_t layout, int32_t channels_per_group, xc_ingest **out);
+
+/* Group size in channels and device bytes held, of a plan (either output may
+ * be NULL). */
+xc_status xc_ingest_info(const xc_ingest *ingest, int32_t *channels_per_group, int64_t *device_bytes);
+
+/*
+ * Enqueues the correlation of host_samples (C channels in the plan's layout,
+ * host memory; pinned memory, e.g. hipHostMalloc, makes the copies
+ * asynchronous DMA) into vis (device, V[C][B][P][P] of out_type, as for
+ * xc_correlate) on `stream`, one group after another: copy to a staging slot,
+ * transpose (station-major input), correlate into the group's channels of V.
+ * overlap = 1: copies run on the plan's copy stream, each group's copy
+ * overlapping the previous group's correlation; overlap = 0: copies run on
+ * `stream`, in order with the computation (synchronous I/O).  The results are
+ * those of xc_correlate_config(cfg, ...) on the time-major block.  host_samples
+ * must stay valid and unchanged until `stream` has completed the call's work;
+ * calls on one plan may follow each other without waiting (slots are reused
+ * only after their previous correlation).  Argument and configuration errors
+ * are returned before anything is enqueued.  The copies are staged, not
+ * asynchronous, if host_samples is pageable memory.
+ */
+xc_status xc_ingest_run(xc_ingest *ingest, const xc_config *cfg, const void *host_samples, void *vis,
+                        xc_out_type out_type, int32_t accumulate, int32_t overlap, void *stream);
+
+/* Waits for the plan's outstanding work and frees it. */
+void xc_ingest_destroy(xc_ingest *ingest);
+
+/* ------------------------------------------------------------------------ */
 /* Achievable device peaks (for roofline reports).                           */
 
 typedef enum xc_peak {

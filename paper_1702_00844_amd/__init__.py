@@ -21,11 +21,12 @@ import torch
 from . import _lib
 from ._lib import (XC_CI32_MAX_TIMES, XC_IN_CBF16, XC_IN_CF16, XC_IN_CF32, XC_IN_CI8, XC_KERNEL_AUTO,
                    XC_KERNEL_MFMA, XC_KERNEL_VALU, XC_OUT_CF32, XC_OUT_CI32, XC_STAGING_AUTO, XC_STAGING_LDS,
-                   XC_STAGING_REGISTERS, XC_PRODUCT_AUTO, XC_PRODUCT_FOUR, XC_PRODUCT_THREE, XengineError)
+                   XC_STAGING_REGISTERS, XC_PRODUCT_AUTO, XC_PRODUCT_FOUR, XC_PRODUCT_THREE, XC_LAYOUT_TIME_MAJOR,
+                   XC_LAYOUT_STATION_MAJOR, XengineError)
 
 __all__ = ["correlate", "correlate_into", "n_baselines", "baseline_index", "tile_cost", "perf_max", "ai_global",
            "flops", "resolve_config", "BatchPlan", "batch_worklist", "autotune", "tune_cache_load", "Server",
-           "quantile", "XengineError", "in_type_of", "vis_shape"]
+           "quantile", "XengineError", "in_type_of", "vis_shape", "Ingest", "transpose_to_time_major"]
 
 
 def lib():
@@ -172,6 +173,83 @@ def correlate(x: torch.Tensor, out: torch.Tensor | None = None, accumulate: bool
         alloc = torch.zeros if accumulate else torch.empty
         out = alloc(vis_shape(C, S, out_type, P), dtype=dtype, device=x.device)
     return correlate_into(x, out, accumulate=accumulate, stream=stream, config=config)
+
+
+def transpose_to_time_major(x: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Station-major device samples x[C][S][T][P] (complex64 [C, S, T, 2], or
+    int8 / float16 / bfloat16 [C, S, T, 2, 2]) -> time-major [C, T, S, P] on the
+    GPU (Section 4.4's memory-layout transpose)."""
+    in_type, C, S, T, P = in_type_of(x)      # dims 1 and 2 are (S, T) here
+    shape = (C, T, S) + tuple(x.shape[3:])
+    if out is None:
+        out = torch.empty(shape, dtype=x.dtype, device=x.device)
+    if tuple(out.shape) != shape or out.dtype != x.dtype:
+        raise ValueError(f"out must be {x.dtype} of shape {shape}")
+    _require_device(x, out)
+    _lib.check(lib().xc_transpose_to_time_major(ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                                in_type, S, P, C, T, _stream_ptr(stream)))
+    return out
+
+
+class Ingest:
+    """Correlation of samples held in host memory: channel groups are copied to
+    the device (pinned host memory: asynchronous DMA on a copy stream,
+    overlapping the previous group's correlation), transposed on the GPU when
+    the host layout is station-major, and correlated into their channels of V
+    by the same kernels as device-resident input (Sections 3.6 and 4.4)."""
+
+    def __init__(self, in_type: int, n_stations: int, n_channels: int, n_times: int,
+                 layout: int = XC_LAYOUT_TIME_MAJOR, channels_per_group: int = 0):
+        h = ctypes.c_void_p()
+        _lib.check(lib().xc_ingest_create(in_type, n_stations, 2, n_channels, n_times, layout, channels_per_group,
+                                          ctypes.byref(h)))
+        self._h = h
+        self.in_type, self.layout = in_type, layout
+        self.S, self.C, self.T = n_stations, n_channels, n_times
+        g, b = ctypes.c_int32(), ctypes.c_int64()
+        _lib.check(lib().xc_ingest_info(h, ctypes.byref(g), ctypes.byref(b)))
+        self.channels_per_group, self.device_bytes = g.value, b.value
+
+    def host_shape(self):
+        mid = (self.T, self.S) if self.layout == XC_LAYOUT_TIME_MAJOR else (self.S, self.T)
+        return (self.C,) + mid + ((2,) if self.in_type == XC_IN_CF32 else (2, 2))
+
+    def run(self, x_host: torch.Tensor, out: torch.Tensor | None = None, accumulate: bool = False,
+            overlap: bool = True, config=None, stream=None, out_type: int | None = None) -> torch.Tensor:
+        """out (+)= correlation of the host samples; enqueued on `stream`.  x_host
+        must stay alive and unchanged until the stream has finished the work."""
+        dtypes = {XC_IN_CF32: torch.complex64, XC_IN_CI8: torch.int8, XC_IN_CF16: torch.float16,
+                  XC_IN_CBF16: torch.bfloat16}
+        if x_host.is_cuda or x_host.dtype != dtypes[self.in_type] or tuple(x_host.shape) != self.host_shape():
+            raise ValueError(f"x_host must be a host tensor of {dtypes[self.in_type]} {self.host_shape()}")
+        if not x_host.is_contiguous():
+            raise ValueError("tensors must be contiguous")
+        if out is None:
+            if out_type is None:
+                out_type = XC_OUT_CI32 if self.in_type == XC_IN_CI8 else XC_OUT_CF32
+            alloc = torch.zeros if accumulate else torch.empty
+            out = alloc(vis_shape(self.C, self.S, out_type), dtype=torch.int32 if out_type == XC_OUT_CI32
+                        else torch.complex64, device="cuda")
+        out_type = XC_OUT_CI32 if out.dtype == torch.int32 else XC_OUT_CF32
+        if tuple(out.shape) != vis_shape(self.C, self.S, out_type):
+            raise ValueError(f"out has shape {tuple(out.shape)}, expected {vis_shape(self.C, self.S, out_type)}")
+        _require_device(out)
+        cfg = _config(config)
+        _lib.check(lib().xc_ingest_run(self._h, ctypes.byref(cfg) if cfg else None, ctypes.c_void_p(x_host.data_ptr()),
+                                       ctypes.c_void_p(out.data_ptr()), out_type, 1 if accumulate else 0,
+                                       1 if overlap else 0, _stream_ptr(stream)))
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().xc_ingest_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def batch_worklist(shapes, block: int, with_bounds: bool = False):

@@ -26,6 +26,7 @@ XC_PEAK_F32_MFMA16, XC_PEAK_F32_MFMA32, XC_PEAK_I8_MFMA, XC_PEAK_F16_MFMA, XC_PE
 
 XC_STAGING_AUTO, XC_STAGING_REGISTERS, XC_STAGING_LDS = 0, 1, 2
 XC_PRODUCT_AUTO, XC_PRODUCT_FOUR, XC_PRODUCT_THREE = 0, 1, 2
+XC_LAYOUT_TIME_MAJOR, XC_LAYOUT_STATION_MAJOR = 0, 1
 
 
 class XcConfig(ctypes.Structure):
@@ -89,6 +90,11 @@ SIGNATURES = {
     "xc_stream_close": (c_i32, [c_vp, c_i32]),
     "xc_stream_reset_stats": (c_i32, [c_vp, c_i32]),
     "xc_quantile": (c_f64, [ctypes.POINTER(c_f64), c_i64, c_f64]),
+    "xc_transpose_to_time_major": (c_i32, [c_vp, c_vp, c_i32, c_i32, c_i32, c_i32, c_i32, c_vp]),
+    "xc_ingest_create": (c_i32, [c_i32, c_i32, c_i32, c_i32, c_i32, c_i32, c_i32, ctypes.POINTER(c_vp)]),
+    "xc_ingest_info": (c_i32, [c_vp, ctypes.POINTER(c_i32), ctypes.POINTER(c_i64)]),
+    "xc_ingest_run": (c_i32, [c_vp, ctypes.POINTER(XcConfig), c_vp, c_vp, c_i32, c_i32, c_i32, c_vp]),
+    "xc_ingest_destroy": (None, [c_vp]),
     "xc_measure_peak": (c_i32, [c_i32, ctypes.POINTER(c_f64)]),
     "xc_status_string": (c_char_p, [c_i32]),
     "xc_last_error": (c_char_p, []),

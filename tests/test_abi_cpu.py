@@ -234,3 +234,28 @@ def test_stream_footprint_and_validation():
     over = xe.Server.desc(4, 2, 256, 261, blocks_per_fold=1, ring_blocks=2)      # 66816 samples > int32 bound
     assert lib.xc_stream_open(h, ctypes.byref(over), ctypes.byref(sid)) == 4
     lib.xc_server_destroy(h)
+
+
+def test_ingest_and_transpose_validation():
+    """Argument errors of the host-ingest plan and the layout transpose come
+    back before any device memory is touched."""
+    lib = _lib.load()
+    h = ctypes.c_void_p()
+    TM, SM = _lib.XC_LAYOUT_TIME_MAJOR, _lib.XC_LAYOUT_STATION_MAJOR
+    ok = dict(in_type=_lib.XC_IN_CF32, S=8, P=2, C=4, T=16, layout=TM, group=0)
+    for bad, status in [(dict(layout=2), 1), (dict(layout=-1), 1), (dict(in_type=4), 1), (dict(P=1), 2),
+                        (dict(S=0), 1), (dict(C=0), 1), (dict(T=0), 1), (dict(group=-1), 1)]:
+        a = {**ok, **bad}
+        assert lib.xc_ingest_create(a["in_type"], a["S"], a["P"], a["C"], a["T"], a["layout"], a["group"],
+                                    ctypes.byref(h)) == status, bad
+        assert not h.value
+    assert lib.xc_ingest_create(0, 8, 2, 4, 16, SM, 0, None) == 1
+    assert lib.xc_ingest_run(None, None, VP(16), VP(16), 0, 0, 1, None) == 1
+    assert lib.xc_ingest_info(None, None, None) == 1
+    lib.xc_ingest_destroy(None)
+    # transpose: null or equal pointers, misalignment, bad type or shape
+    for args, status in [((None, VP(64), 0, 8, 2, 1, 4), 1), ((VP(64), None, 0, 8, 2, 1, 4), 1),
+                         ((VP(64), VP(64), 0, 8, 2, 1, 4), 1), ((VP(72), VP(64), 0, 8, 2, 1, 4), 1),
+                         ((VP(66), VP(64), 1, 8, 2, 1, 4), 1), ((VP(64), VP(128), 5, 8, 2, 1, 4), 1),
+                         ((VP(64), VP(128), 0, 8, 3, 1, 4), 2), ((VP(64), VP(128), 0, 8, 2, 1, 0), 1)]:
+        assert lib.xc_transpose_to_time_major(*args, None) == status, args
