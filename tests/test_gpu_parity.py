@@ -273,3 +273,42 @@ def test_config3_sampled_channels():
         vf = xe.correlate(xf, config=cfg)
         assert rel_err(gpu_vis_numpy(vf, chans), refc) <= FP32_TOL
         del vf
+
+
+@pytest.mark.parametrize("kind", ["cf32_mfma_p3", "cf32_mfma_p4", "cf32_valu", "ci8", "ci8_regs", "cf16", "cbf16"])
+def test_large_ragged_station_count(kind):
+    """520 stations (eight full 64-station blocks and a ragged ninth: 45 block
+    pairs per channel, diagonal and off-diagonal), ragged time: every output."""
+    S, C, T = 520, 2, 37
+    if kind.startswith("cf32"):
+        x = _cf32(S, C, T, seed=520)
+        cfg = {"cf32_mfma_p3": dict(kernel=xe.XC_KERNEL_MFMA, product=xe.XC_PRODUCT_THREE),
+               "cf32_mfma_p4": dict(kernel=xe.XC_KERNEL_MFMA, product=xe.XC_PRODUCT_FOUR),
+               "cf32_valu": dict(kernel=xe.XC_KERNEL_VALU)}[kind]
+        got, ref = gpu_vis_numpy(xe.correlate(x, config=cfg)), oracle_vis(x)
+        assert rel_err(got, ref) <= FP32_TOL
+        assert_hermitian_autos(got, S)
+        return
+    xi = inputs.ci8_gaussian(C, T, S, seed=521, device=DEV)
+    ref = oracle_vis(xi)
+    if kind.startswith("ci8"):
+        cfg = None if kind == "ci8" else dict(kernel=xe.XC_KERNEL_MFMA, block=64, staging=xe.XC_STAGING_REGISTERS)
+        assert np.array_equal(gpu_vis_numpy(xe.correlate(xi, config=cfg)), ref)
+        return
+    x = xi.to(torch.float16 if kind == "cf16" else torch.bfloat16)     # exact: integer samples
+    assert np.array_equal(gpu_vis_numpy(xe.correlate(x)), ref[..., 0] + 1j * ref[..., 1])
+
+
+def test_int32_bound_at_the_longest_integration():
+    """T = 66572, the longest integration int32 holds exactly: all samples
+    (127, -127) give 2 * 127^2 * T = 2147450408 in every XX/YY/XY/YX real
+    part, through the int8 kernels (direct-to-LDS and register-staged)."""
+    S, C, T = 8, 1, 66572
+    x = torch.empty((C, T, S, 2, 2), dtype=torch.int8, device=DEV)
+    x[..., 0] = 127
+    x[..., 1] = -127
+    for cfg in (None, dict(kernel=xe.XC_KERNEL_MFMA, block=64, staging=xe.XC_STAGING_REGISTERS),
+                dict(kernel=xe.XC_KERNEL_MFMA, block=32)):
+        got = gpu_vis_numpy(xe.correlate(x, config=cfg))
+        assert np.all(got[..., 0] == 2 * 127 * 127 * T) and np.all(got[..., 1] == 0)
+    assert 2 * 127 * 127 * T <= 2 ** 31 - 1
