@@ -81,9 +81,10 @@ typedef enum xc_kernel {
 typedef enum xc_staging {
     XC_STAGING_AUTO = 0,
     XC_STAGING_REGISTERS = 1, /* loaded into registers, corner-turned and stored to LDS */
-    XC_STAGING_LDS = 2        /* copied straight into LDS (global_load_lds); needs whole
-                                 16-byte granules: n_stations % 4 == 0 for int8,
-                                 % 2 == 0 for 16-bit samples                          */
+    XC_STAGING_LDS = 2        /* copied straight into LDS (global_load_lds): 16-byte
+                                 granules when n_stations % 4 == 0 for int8 or
+                                 % 2 == 0 for 16-bit samples, 4-byte granules
+                                 (four times as many copies) otherwise                */
 } xc_staging;
 
 /* How a complex multiply-accumulate is formed from real products.  With the
@@ -166,8 +167,7 @@ xc_status xc_correlate(const void *samples, xc_in_type in_type, int32_t n_statio
  *   staging       xc_staging.  Complex-float32 on 64-station blocks always
  *                 copies straight into LDS; VALU and 32-station blocks always
  *                 stage through registers; int8 and 16-bit samples on
- *                 64-station blocks take either (AUTO: LDS when the station
- *                 count allows it).
+ *                 64-station blocks take either (AUTO: LDS).
  *   product       xc_product.  AUTO: three products for complex-float32 on
  *                 64-station matrix-core blocks, four everywhere else.
  */

@@ -139,18 +139,13 @@ xc_status resolve(const xc_config *cfg_in, xc_in_type in_type, xc_out_type out_t
         // complex-float32 on 64-station blocks uses the 16x16 tile kernel, which
         // copies straight into LDS and can split time over two wave groups;
         // int8 and 16-bit samples on 64-station blocks take either staging
-        // (straight into LDS needs whole 16-byte granules); the rest stage
-        // through registers
+        // (AUTO: straight into LDS); the rest stage through registers
         const bool f16tile = in_type == XC_IN_CF32 && p.block == 64;
         const bool either = in_type != XC_IN_CF32 && p.block == 64;
-        const bool lds_ok = f16tile || (either && S % dma_granule(in_type) == 0);
+        const bool lds_ok = f16tile || either;
         p.staging = cfg.staging ? cfg.staging : (lds_ok ? XC_STAGING_LDS : XC_STAGING_REGISTERS);
-        if (p.staging == XC_STAGING_LDS && !lds_ok) {
-            if (either)
-                return set_error(XC_ERR_INVALID_ARG, "staging straight into LDS needs n_stations %% %d == 0 (got %d)",
-                                 dma_granule(in_type), S);
+        if (p.staging == XC_STAGING_LDS && !lds_ok)
             return set_error(XC_ERR_INVALID_ARG, "this configuration stages through registers only");
-        }
         if (p.staging == XC_STAGING_REGISTERS && f16tile)
             return set_error(XC_ERR_INVALID_ARG,
                              "complex-float32 on 64-station blocks copies straight into LDS only");

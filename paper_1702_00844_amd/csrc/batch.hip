@@ -64,6 +64,7 @@ using namespace xc;
 // One launch: the items that resolved to the same configuration.
 struct Segment {
     Plan plan;
+    bool g4;             // direct-to-LDS kernel with 4-byte granules (station count not a granule multiple)
     int64_t n_units;
     int grid;            // kNumXcd x the longest XCD range
     Unit *d_units;
@@ -103,7 +104,7 @@ static hipError_t plan_enqueue(xc_batch_plan *p, hipStream_t s) {
         else if (p->in_type == XC_IN_CF32 && g.plan.block == 64)
             e = launch_mfma16_batch(g.plan, p->d_jobs, g.d_units, g.d_bounds, g.grid, s);
         else if (plan_is_dma(g.plan, p->in_type))
-            e = launch_mfma_dma_batch(p->in_type, p->out_type, p->d_jobs, g.d_units, g.d_bounds, g.grid, s);
+            e = launch_mfma_dma_batch(p->in_type, p->out_type, p->d_jobs, g.d_units, g.d_bounds, g.grid, g.g4, s);
         else
             e = launch_mfma_batch(g.plan, p->in_type, p->out_type, p->d_jobs, g.d_units, g.d_bounds, g.grid, s);
         if (e != hipSuccess) return e;
@@ -158,6 +159,7 @@ xc_status xc_batch_plan_create(const xc_subarray *items, int32_t n_items, int32_
     std::vector<int32_t> S(n_items), C(n_items), T(n_items);
     std::vector<Plan> plans;                 // distinct configurations, in order of first use
     std::vector<std::vector<int>> members;   // their items
+    std::vector<bool> plan_g4;               // their copy granule (direct-to-LDS kernel)
     std::vector<int> item_seg(n_items);
     for (int i = 0; i < n_items; ++i) {
         Plan pi;
@@ -167,10 +169,13 @@ xc_status xc_batch_plan_create(const xc_subarray *items, int32_t n_items, int32_
         if (!items[i].samples || !items[i].vis) return set_error(XC_ERR_INVALID_ARG, "item %d: null pointer", i);
         if (((uintptr_t)items[i].samples & 15u) || ((uintptr_t)items[i].vis & 15u))
             return set_error(XC_ERR_INVALID_ARG, "item %d: pointers must be 16-byte aligned", i);
+        // the direct-to-LDS kernel copies 16- or 4-byte granules by station count: one launch each
+        const bool g4 = plan_is_dma(pi, in_type) && items[i].n_stations % dma_granule(in_type) != 0;
         size_t g = 0;
-        while (g < plans.size() && !same_plan(plans[g], pi)) ++g;
+        while (g < plans.size() && !(same_plan(plans[g], pi) && plan_g4[g] == g4)) ++g;
         if (g == plans.size()) {
             plans.push_back(pi);
+            plan_g4.push_back(g4);
             members.emplace_back();
         }
         members[g].push_back(i);
@@ -193,6 +198,7 @@ xc_status xc_batch_plan_create(const xc_subarray *items, int32_t n_items, int32_
     for (size_t g = 0; g < plans.size() && e == hipSuccess; ++g) {
         Segment seg{};
         seg.plan = plans[g];
+        seg.g4 = plan_g4[g];
         std::vector<Unit> units;
         int bounds[kNumXcd + 1];
         seg.n_units = build_units(members[g], S.data(), C.data(), T.data(), seg.plan.block, &units, bounds);

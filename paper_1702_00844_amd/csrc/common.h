@@ -101,11 +101,14 @@ hipError_t launch_mfma(const Plan &plan, xc_in_type in_type, xc_out_type out_typ
                        const Job &job, hipStream_t stream);
 
 // int8 and 16-bit samples on 64-station blocks staged straight from HBM to
-// LDS (whole granules: n_stations % 4 == 0 for int8, % 2 == 0 for 16-bit).
+// LDS (16-byte granules when n_stations is a multiple of 4 for int8 or of 2
+// for 16-bit samples, 4-byte granules otherwise).
 hipError_t launch_mfma_dma(xc_in_type in_type, xc_out_type out_type, const Job &job, hipStream_t stream);
+// g4: the items' station counts are not multiples of dma_granule (4-byte copies).
 hipError_t launch_mfma_dma_batch(xc_in_type in_type, xc_out_type out_type, const Job *jobs, const Unit *units,
-                                 const int *bounds, int grid, hipStream_t stream);
-// Station-count granule the direct-to-LDS int8/16-bit kernel needs.
+                                 const int *bounds, int grid, bool g4, hipStream_t stream);
+// Stations per 16-byte granule of the direct-to-LDS int8/16-bit kernel; other
+// station counts are copied in 4-byte granules.
 inline int dma_granule(xc_in_type in_type) { return in_type == XC_IN_CI8 ? 4 : 2; }
 // True when the plan runs the direct-to-LDS int8/16-bit kernel.
 inline bool plan_is_dma(const Plan &p, xc_in_type in_type) {

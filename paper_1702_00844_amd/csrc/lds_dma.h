@@ -1,4 +1,5 @@
-// Direct global-to-LDS copies on gfx950 (global_load_lds_dwordx4), shared by
+// Direct global-to-LDS copies on gfx950 (global_load_lds_dwordx4 and
+// global_load_lds_dword), shared by
 // the kernels that stage samples without passing them through registers.
 //
 // The copies are issued from inline assembly so that the compiler does not
@@ -23,6 +24,11 @@ static __device__ __attribute__((aligned(16))) uint32_t g_zero16[4] = {0u, 0u, 0
 #pragma clang diagnostic ignored "-Winline-asm"
 __device__ __forceinline__ void dma16(const void *src, uint32_t lds) {
     asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off" ::"v"(src), "s"(lds)
+                 : "memory", "m0");
+}
+// The same with 4-byte granules: lane L's dword at src goes to lds + 4 L.
+__device__ __forceinline__ void dma4(const void *src, uint32_t lds) {
+    asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dword %0, off" ::"v"(src), "s"(lds)
                  : "memory", "m0");
 }
 #pragma clang diagnostic pop

@@ -31,8 +31,8 @@
 //    (the four rows of a transpose group), 16-bit granule g at
 //    g ^ 8 ((t / 4) mod 2) (the two row sets of a wave's 4-byte reads).
 //
-// Requires whole granules: n_stations % 4 == 0 (int8) or % 2 == 0 (16-bit);
-// other station counts use the register-staged kernels.
+// Station counts that are not whole 16-byte granules (n_stations % 4 != 0 for
+// int8, odd for 16-bit) are copied in 4-byte granules (G4 below).
 #include "common.h"
 
 #include "lds_dma.h"
@@ -141,7 +141,15 @@ __device__ __forceinline__ ACC mma(const v4i &a, const v4i &b, const ACC &c) {
                                                        0, 0);
 }
 
-template <int KIND, typename OUT>
+// G4: 4-byte granules.  With n_stations a multiple of the 16-byte granule
+// (4 int8 or 2 16-bit stations) a copy moves 16 bytes per lane; otherwise a
+// time row does not start on a 16-byte boundary, and each lane copies one
+// 4-byte word (global_load_lds_dword) instead: a copy then fills 256 bytes of
+// one time row (a whole int8 row, half a 16-bit one), four times as many
+// copies for the same LDS image.  The swizzle is applied on the source side:
+// the word landing at byte 4 L of the row is the one the 16-byte-granule copy
+// would have put there.
+template <int KIND, typename OUT, bool G4>
 __device__ __forceinline__ void unit(const Job &job, int c, int bi, int bj, uint8_t *lds_generic) {
     typedef Geo<KIND> G;
     typedef typename Acc<KIND>::type acc_t;
@@ -174,10 +182,51 @@ __device__ __forceinline__ void unit(const Job &job, int c, int bi, int bj, uint
     }
     const uint32_t dst0 = lds_base + blk * G::BLK + rbase * G::ROWB;
 
+    // 4-byte granules: copy i fills bytes 256 h .. 256 h + 255 of time row
+    // rbase + i / IPR (h = i % IPR); the word of lane L there belongs to the
+    // station and word picked by the row's swizzle phase and h, one of four
+    // combinations per lane (rbase is a multiple of 8, so the phase of copy i
+    // is i % 4 for int8 and (i / 8) % 2 for 16-bit samples).
+    constexpr int IPR = G::ROWB / 256;                  // copies per time row: 1 or 2
+    constexpr int NC4 = G::KT / 2 * IPR;                // copies per wave and chunk (half on the diagonal)
+    const int nload4 = diag ? NC4 / 2 : NC4;
+    uint32_t woff[4];     // byte offset of the lane's word within a time row, per combination
+    if constexpr (G4) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int t = G::I8 ? v : 4 * (v >> 1);     // a time row of that swizzle phase
+            const int h = G::I8 ? 0 : (v & 1);
+            const int gl = G::swz(16 * h + lane / 4, t);   // logical granule at the lane's bytes
+            const int st = (blk ? J0 : I0) + G::GS * gl + (G::I8 ? lane % 4 : (lane % 4) / 2);
+            const int stw = st < S ? st : S - 1;
+            woff[v] = (uint32_t)(stw * G::SAMPLE + (G::I8 ? 0 : 4 * (lane & 1)));
+        }
+    }
+    auto combo = [&](int i) { return G::I8 ? (i & 3) : (((i >> 3) & 1) * 2 + (i & 1)); };
+
     auto issue = [&](int ch) {
         const int t0 = ch * G::KT;
         const uint32_t dst = dst0 + (ch % NSTAGE) * STAGE;
-        if (t0 + G::KT <= T && rows_contiguous(job, t0, G::KT)) {
+        if constexpr (G4) {
+            if (t0 + G::KT <= T && rows_contiguous(job, t0, G::KT)) {
+                const uint8_t *src = x + (row_offset(job, c, t0) + (size_t)rbase * S) * G::SAMPLE;
+#pragma unroll
+                for (int i = 0; i < NC4; ++i)
+                    if (i < nload4)
+                        dma4(src + (size_t)(i / IPR) * S * G::SAMPLE + woff[combo(i)],
+                             dst + (i / IPR) * G::ROWB + (i % IPR) * 256);
+            } else {
+#pragma unroll
+                for (int i = 0; i < NC4; ++i) {
+                    if (i >= nload4) break;
+                    const int t = t0 + rbase + i / IPR;
+                    const void *src = t < T ? static_cast<const void *>(x + row_offset(job, c, t) * G::SAMPLE +
+                                                                        woff[combo(i)])
+                                            : static_cast<const void *>(g_zero16);
+                    dma4(src, dst + (i / IPR) * G::ROWB + (i % IPR) * 256);
+                }
+            }
+        } else if (t0 + G::KT <= T && rows_contiguous(job, t0, G::KT)) {
             const uint8_t *src = x + row_offset(job, c, t0) * G::SAMPLE;
 #pragma unroll
             for (int i = 0; i < NC; ++i)
@@ -193,6 +242,7 @@ __device__ __forceinline__ void unit(const Job &job, int c, int bi, int bj, uint
             }
         }
     };
+    const int npend = G4 ? nload4 : nload;    // copies per wave and chunk
 
     // -- tiles of this wave (as in the register-staged kernels)
     bool run[2][2];
@@ -230,7 +280,7 @@ __device__ __forceinline__ void unit(const Job &job, int c, int bi, int bj, uint
         // this wave's copies of chunk ch are done once only those of the
         // (at most NSTAGE - 2) chunks issued after it may be pending
         const int later = min(nchunk - 1 - ch, NSTAGE - 2);
-        wait_vm_n(later * nload);
+        wait_vm_n(later * npend);
         barrier_lds();
         // every wave is past chunk ch - 1: its stage takes chunk ch + NSTAGE - 1
         if (ch + NSTAGE - 1 < nchunk) issue(ch + NSTAGE - 1);
@@ -276,7 +326,7 @@ __device__ __forceinline__ void unit(const Job &job, int c, int bi, int bj, uint
             }
 }
 
-template <int KIND, typename OUT>
+template <int KIND, typename OUT, bool G4>
 __global__ __launch_bounds__(256, 2) void kernel(Job job, int nwork) {
     __shared__ __attribute__((aligned(16))) uint8_t lds[LDS_BYTES];
     const int w = xcd_remap(blockIdx.x, nwork);
@@ -284,10 +334,10 @@ __global__ __launch_bounds__(256, 2) void kernel(Job job, int nwork) {
     const int c = w / job.npairs;
     int bi, bj;
     pair_decode(w - c * job.npairs, bi, bj);
-    unit<KIND, OUT>(job, c, bi, bj, lds);
+    unit<KIND, OUT, G4>(job, c, bi, bj, lds);
 }
 
-template <int KIND, typename OUT>
+template <int KIND, typename OUT, bool G4>
 __global__ __launch_bounds__(256, 2) void kernel_batch(const Job *__restrict__ jobs, const Unit *__restrict__ units,
                                                        const int *__restrict__ bounds) {
     __shared__ __attribute__((aligned(16))) uint8_t lds[LDS_BYTES];
@@ -295,18 +345,25 @@ __global__ __launch_bounds__(256, 2) void kernel_batch(const Job *__restrict__ j
     if (u < 0) return;
     const Unit un = units[u];
     const Job job = jobs[un.item];
-    unit<KIND, OUT>(job, un.channel, un.bi, un.bj, lds);
+    unit<KIND, OUT, G4>(job, un.channel, un.bi, un.bj, lds);
 }
 
 template <int KIND, typename OUT>
 hipError_t launch_t(const Job &job, hipStream_t stream) {
     const int nwork = job.C * job.npairs;
-    hipLaunchKernelGGL((kernel<KIND, OUT>), dim3(xcd_grid(nwork)), dim3(256), 0, stream, job, nwork);
+    if (job.S % Geo<KIND>::GS)
+        hipLaunchKernelGGL((kernel<KIND, OUT, true>), dim3(xcd_grid(nwork)), dim3(256), 0, stream, job, nwork);
+    else
+        hipLaunchKernelGGL((kernel<KIND, OUT, false>), dim3(xcd_grid(nwork)), dim3(256), 0, stream, job, nwork);
     return hipGetLastError();
 }
 template <int KIND, typename OUT>
-hipError_t launch_batch_t(const Job *jobs, const Unit *units, const int *bounds, int grid, hipStream_t stream) {
-    hipLaunchKernelGGL((kernel_batch<KIND, OUT>), dim3(grid), dim3(256), 0, stream, jobs, units, bounds);
+hipError_t launch_batch_t(const Job *jobs, const Unit *units, const int *bounds, int grid, bool g4,
+                          hipStream_t stream) {
+    if (g4)
+        hipLaunchKernelGGL((kernel_batch<KIND, OUT, true>), dim3(grid), dim3(256), 0, stream, jobs, units, bounds);
+    else
+        hipLaunchKernelGGL((kernel_batch<KIND, OUT, false>), dim3(grid), dim3(256), 0, stream, jobs, units, bounds);
     return hipGetLastError();
 }
 #define XC_DMA_DISPATCH(FN, ...)                                                                      \
@@ -327,9 +384,9 @@ hipError_t launch_mfma_dma(xc_in_type in_type, xc_out_type out_type, const Job &
 }
 
 hipError_t launch_mfma_dma_batch(xc_in_type in_type, xc_out_type out_type, const Job *jobs, const Unit *units,
-                                 const int *bounds, int grid, hipStream_t stream) {
+                                 const int *bounds, int grid, bool g4, hipStream_t stream) {
     using namespace dma;
-    XC_DMA_DISPATCH(launch_batch_t, jobs, units, bounds, grid, stream)
+    XC_DMA_DISPATCH(launch_batch_t, jobs, units, bounds, grid, g4, stream)
     return hipErrorInvalidValue;
 }
 

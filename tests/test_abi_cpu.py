@@ -129,16 +129,14 @@ def test_config_resolution():
         xe.resolve_config(shp, config={"kernel": _lib.XC_KERNEL_MFMA, "staging": 3})
     with pytest.raises(xe.XengineError):
         xe.resolve_config((_lib.XC_IN_CI8, 4, 16, 8, 2), _lib.XC_OUT_CI32, config={"kernel": 2, "time_split": 2})
-    # int8 and 16-bit on 64-station blocks: straight into LDS when the station
-    # count is a whole number of 16-byte granules, else through registers
+    # int8 and 16-bit on 64-station blocks: straight into LDS for every station
+    # count (16- or 4-byte granules), through registers on request
     r = xe.resolve_config((_lib.XC_IN_CI8, 1024, 1024, 256, 2), _lib.XC_OUT_CI32)
     assert r == {"kernel": 2, "block": 64, "time_chunk": 64, "time_split": 1, "staging": L, "product": F4}
     r = xe.resolve_config((_lib.XC_IN_CI8, 8, 64, 70, 2), _lib.XC_OUT_CI32)
-    assert r == {"kernel": 2, "block": 64, "time_chunk": 64, "time_split": 1, "staging": R, "product": F4}
+    assert r == {"kernel": 2, "block": 64, "time_chunk": 64, "time_split": 1, "staging": L, "product": F4}
     r = xe.resolve_config((_lib.XC_IN_CI8, 8, 64, 68, 2), _lib.XC_OUT_CI32, config={"kernel": 2, "staging": R})
     assert r == {"kernel": 2, "block": 64, "time_chunk": 64, "time_split": 1, "staging": R, "product": F4}
-    with pytest.raises(xe.XengineError):
-        xe.resolve_config((_lib.XC_IN_CI8, 8, 64, 70, 2), config={"kernel": 2, "staging": L})
     with pytest.raises(xe.XengineError):
         xe.resolve_config((_lib.XC_IN_CI8, 8, 64, 68, 2), config={"kernel": 2, "block": 32, "staging": L})
     with pytest.raises(xe.XengineError):
@@ -146,9 +144,9 @@ def test_config_resolution():
     r = xe.resolve_config((_lib.XC_IN_CF16, 1024, 1024, 256, 2))
     assert r == {"kernel": 2, "block": 64, "time_chunk": 32, "time_split": 1, "staging": L, "product": F4}
     r = xe.resolve_config((_lib.XC_IN_CBF16, 8, 64, 33, 2))
+    assert r == {"kernel": 2, "block": 64, "time_chunk": 32, "time_split": 1, "staging": L, "product": F4}
+    r = xe.resolve_config((_lib.XC_IN_CBF16, 8, 64, 33, 2), config={"kernel": 2, "staging": R})
     assert r == {"kernel": 2, "block": 64, "time_chunk": 32, "time_split": 1, "staging": R, "product": F4}
-    with pytest.raises(xe.XengineError):
-        xe.resolve_config((_lib.XC_IN_CBF16, 8, 64, 33, 2), config={"kernel": 2, "staging": L})
     with pytest.raises(xe.XengineError):
         xe.resolve_config((_lib.XC_IN_CI8, 4, 16, 8, 2), config={"kernel": _lib.XC_KERNEL_VALU})
     with pytest.raises(xe.XengineError):
