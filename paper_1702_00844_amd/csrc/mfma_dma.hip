@@ -286,6 +286,10 @@ __device__ __forceinline__ void unit(const Job &job, int c, int bi, int bj, uint
         if (ch + NSTAGE - 1 < nchunk) issue(ch + NSTAGE - 1);
         if (!any) continue;
         const lds_u8 *sb = lds + (ch % NSTAGE) * STAGE;
+        // (The compiler reads two k-steps' fragments, then issues their
+        // MFMAs.  Reading k-step ks + 1 before the MFMAs of ks, held in place
+        // by scheduling fences, measured no faster: the other wave of the
+        // SIMD covers the LDS latency.)
 #pragma unroll
         for (int ks = 0; ks < G::KT / G::STEP_T; ++ks) {
             v4i a[2], b[2], bn[2];
