@@ -398,7 +398,8 @@ xc_status xc_transpose_to_time_major(const void *src, void *dst, xc_in_type in_t
  * with station-major input: the copy and its transpose) are allocated here
  * and freed by xc_ingest_destroy, together with a copy stream and events.
  * Errors: XC_ERR_INVALID_ARG (bad type, sizes, layout or group size),
- * XC_ERR_UNSUPPORTED (n_pol != 2), XC_ERR_OUT_OF_MEMORY, XC_ERR_HIP.
+ * XC_ERR_UNSUPPORTED (n_pol != 2), XC_ERR_OUT_OF_MEMORY, XC_ERR_HIP.  A plan
+ * keeps the state of its staging slots: use it from one thread at a time.
  */
 typedef struct xc_ingest xc_ingest;
 xc_status xc_ingest_create(xc_in_type in_type, int32_t n_stations, int32_t n_pol, int32_t n_channels,
