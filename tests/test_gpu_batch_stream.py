@@ -56,8 +56,12 @@ def _check(kind, xs, outs, base=None):
     ("cf32", {"kernel": xe.XC_KERNEL_MFMA, "block": 64, "time_split": 2}, SHAPES),
     ("cf32", {"kernel": xe.XC_KERNEL_VALU, "time_chunk": 32, "time_split": 8}, SHAPES),
     ("cf32", {"kernel": xe.XC_KERNEL_VALU, "time_chunk": 16, "time_split": 1}, SHAPES),
+    ("cf32", {"kernel": xe.XC_KERNEL_MFMA, "block": 64, "time_split": 2, "product": xe.XC_PRODUCT_FOUR}, SHAPES),
+    ("ci8", {"kernel": xe.XC_KERNEL_MFMA, "block": 64, "staging": xe.XC_STAGING_REGISTERS}, SHAPES),
+    ("ci8", {"kernel": xe.XC_KERNEL_MFMA, "block": 32}, SHAPES4),
+    ("cf16", {"kernel": xe.XC_KERNEL_MFMA, "block": 64, "staging": xe.XC_STAGING_REGISTERS}, SHAPES4),
 ], ids=["ci8_lds", "ci8_mixed", "cf16_lds", "cf16_mixed", "cbf16", "f32mfma32", "f32mfma64ts1", "f32mfma64ts2", "valu_ts8",
-        "valu_ts1"])
+        "valu_ts1", "f32mfma64ts2_p4", "ci8_regs", "ci8_b32", "cf16_regs"])
 @pytest.mark.parametrize("use_graph", [True, False], ids=["graph", "direct"])
 def test_batch_matches_oracle(kind, config, shapes, use_graph):
     xs = _make(kind, shapes)
