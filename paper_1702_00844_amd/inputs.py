@@ -121,3 +121,24 @@ def subarray_shapes(n_items: int = 32, seed: int = 4, s_range=(24, 576),
     S = rng.integers(s_range[0], s_range[1] + 1, size=n_items)
     C = rng.integers(c_range[0], c_range[1] + 1, size=n_items)
     return [(int(s), int(c), int(n_times)) for s, c in zip(S, C)]
+
+
+def station_streams(S: int, n_in: int, P: int = 2, seed: int = 6, device="cpu",
+                    sigma: float = 1.0) -> torch.Tensor:
+    """Station sample streams before channelisation: complex64 [S, P, n_in],
+    CN(0, sigma^2) noise (the F-engine's input, station-major)."""
+    g = _gen(device, seed)
+    ri = torch.randn((S, P, n_in, 2), generator=g, device=device, dtype=torch.float32)
+    ri.mul_(sigma / math.sqrt(2.0))
+    return torch.view_as_complex(ri)
+
+
+def pfb_taps(n_channels: int, n_taps: int) -> np.ndarray:
+    """Prototype filter of an N-channel, M-tap polyphase filter bank: a sinc of
+    N samples per lobe under a Hann window, M N coefficients (float32).  A
+    data recipe, not part of the filter bank's arithmetic: the filter bank
+    takes any real taps."""
+    N, M = int(n_channels), int(n_taps)
+    k = np.arange(M * N, dtype=np.float64) + 0.5
+    h = np.sinc((k - M * N / 2.0) / N) * (0.5 - 0.5 * np.cos(2.0 * np.pi * k / (M * N)))
+    return h.astype(np.float32)
