@@ -432,6 +432,46 @@ xc_status xc_ingest_run(xc_ingest *ingest, const xc_config *cfg, const void *hos
 void xc_ingest_destroy(xc_ingest *ingest);
 
 /* ------------------------------------------------------------------------ */
+/* F-engine: polyphase filter bank into the correlator's input (Section 2:    */
+/* station data are filtered into frequency channels before correlation).    */
+
+/*
+ * The filter bank, for N channels and M taps per channel (the paper fixes no
+ * filter design; this is the reading taken):
+ *     u[t][n] = sum_{m<M} h[m N + n] z[(t + m) N + n]
+ *     y[t][k] = sum_{n<N} u[t][n] exp(-2 pi i k n / N)
+ *     x[k][t][s][p] = w[s][p][k] y_{s,p}[t][k]     (w optional)
+ * for the T = floor(n_in / N) - M + 1 frames whose window lies in the input.
+ * x is the correlator's input layout ([C][T][S][P] with C = N), so it can be
+ * passed to xc_correlate as it is.
+ *
+ * xc_pfb_create: N = 256 or 512, 1 <= M <= 16, 1 <= S <= 16384, n_pol = 2,
+ * M N <= n_in < 2^31.  Allocates an intermediate of S P T N complex64 and a
+ * twiddle table (freed by xc_pfb_destroy).  Errors: XC_ERR_INVALID_ARG,
+ * XC_ERR_UNSUPPORTED (other N or n_pol), XC_ERR_OUT_OF_MEMORY, XC_ERR_HIP.
+ */
+typedef struct xc_pfb xc_pfb;
+xc_status xc_pfb_create(int32_t n_stations, int32_t n_pol, int32_t n_channels, int32_t n_taps, int64_t n_in,
+                        xc_pfb **out);
+
+/* Frames T and device bytes held, of a filter bank (either output may be NULL). */
+xc_status xc_pfb_info(const xc_pfb *pfb, int32_t *n_frames, int64_t *device_bytes);
+
+/*
+ * Enqueues the filter bank on `stream`.  All pointers device memory, owned by
+ * the caller: z complex64 [S][P][n_in] (each station's and polarisation's
+ * sample stream, 8-byte aligned), taps float32 [M N] (the prototype filter
+ * h), weights complex64 [S][P][N] or NULL (all ones), x complex64 [N][T][S][P]
+ * (written completely, not overlapping z).  Argument errors are returned
+ * before anything is enqueued.  Calls on one filter bank share its
+ * intermediate buffer: calls on different streams must not overlap.
+ */
+xc_status xc_pfb_run(xc_pfb *pfb, const void *z, const float *taps, const void *weights, void *x, void *stream);
+
+/* Frees a filter bank (its enqueued work must be complete). */
+void xc_pfb_destroy(xc_pfb *pfb);
+
+/* ------------------------------------------------------------------------ */
 /* Achievable device peaks (for roofline reports).                           */
 
 typedef enum xc_peak {

@@ -26,7 +26,7 @@ from ._lib import (XC_CI32_MAX_TIMES, XC_IN_CBF16, XC_IN_CF16, XC_IN_CF32, XC_IN
 
 __all__ = ["correlate", "correlate_into", "n_baselines", "baseline_index", "tile_cost", "perf_max", "ai_global",
            "flops", "resolve_config", "BatchPlan", "batch_worklist", "autotune", "tune_cache_load", "Server",
-           "quantile", "XengineError", "in_type_of", "vis_shape", "Ingest", "transpose_to_time_major"]
+           "quantile", "XengineError", "in_type_of", "vis_shape", "Ingest", "transpose_to_time_major", "Pfb"]
 
 
 def lib():
@@ -243,6 +243,59 @@ class Ingest:
     def close(self):
         if getattr(self, "_h", None):
             lib().xc_ingest_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Pfb:
+    """F-engine: polyphase filter bank of N channels and M taps over each
+    station's and polarisation's sample stream z[S][2][n_in] (complex64),
+    producing the correlator's input x[N][T][S][2] (complex64), optionally
+    weighted per (station, polarisation, channel) for delay or gain
+    correction.  ``run`` returns x, which ``correlate`` takes as it is."""
+
+    def __init__(self, n_stations: int, n_channels: int, n_taps: int, n_in: int):
+        h = ctypes.c_void_p()
+        _lib.check(lib().xc_pfb_create(n_stations, 2, n_channels, n_taps, n_in, ctypes.byref(h)))
+        self._h = h
+        self.S, self.N, self.M, self.n_in = n_stations, n_channels, n_taps, n_in
+        t, b = ctypes.c_int32(), ctypes.c_int64()
+        _lib.check(lib().xc_pfb_info(h, ctypes.byref(t), ctypes.byref(b)))
+        self.n_frames, self.device_bytes = t.value, b.value
+
+    def out_shape(self):
+        return (self.N, self.n_frames, self.S, 2)
+
+    def run(self, z: torch.Tensor, taps: torch.Tensor, weights: torch.Tensor | None = None,
+            out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        if z.dtype != torch.complex64 or tuple(z.shape) != (self.S, 2, self.n_in):
+            raise ValueError(f"z must be complex64 of shape {(self.S, 2, self.n_in)}")
+        if taps.dtype != torch.float32 or taps.numel() != self.M * self.N:
+            raise ValueError(f"taps must be float32 with {self.M * self.N} values")
+        if weights is not None and (weights.dtype != torch.complex64 or tuple(weights.shape) != (self.S, 2, self.N)):
+            raise ValueError(f"weights must be complex64 of shape {(self.S, 2, self.N)}")
+        if out is None:
+            out = torch.empty(self.out_shape(), dtype=torch.complex64, device=z.device)
+        if out.dtype != torch.complex64 or tuple(out.shape) != self.out_shape():
+            raise ValueError(f"out must be complex64 of shape {self.out_shape()}")
+        tensors = [z, taps, out] + ([weights] if weights is not None else [])
+        _require_device(*tensors)
+        for t in tensors:
+            if not t.is_contiguous():
+                raise ValueError("tensors must be contiguous")
+        _lib.check(lib().xc_pfb_run(self._h, ctypes.c_void_p(z.data_ptr()), ctypes.c_void_p(taps.data_ptr()),
+                                    ctypes.c_void_p(weights.data_ptr()) if weights is not None else None,
+                                    ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().xc_pfb_destroy(self._h)
             self._h = None
 
     def __del__(self):

@@ -95,6 +95,10 @@ SIGNATURES = {
     "xc_ingest_info": (c_i32, [c_vp, ctypes.POINTER(c_i32), ctypes.POINTER(c_i64)]),
     "xc_ingest_run": (c_i32, [c_vp, ctypes.POINTER(XcConfig), c_vp, c_vp, c_i32, c_i32, c_i32, c_vp]),
     "xc_ingest_destroy": (None, [c_vp]),
+    "xc_pfb_create": (c_i32, [c_i32, c_i32, c_i32, c_i32, c_i64, ctypes.POINTER(c_vp)]),
+    "xc_pfb_info": (c_i32, [c_vp, ctypes.POINTER(c_i32), ctypes.POINTER(c_i64)]),
+    "xc_pfb_run": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
+    "xc_pfb_destroy": (None, [c_vp]),
     "xc_measure_peak": (c_i32, [c_i32, ctypes.POINTER(c_f64)]),
     "xc_status_string": (c_char_p, [c_i32]),
     "xc_last_error": (c_char_p, []),

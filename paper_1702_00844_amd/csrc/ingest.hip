@@ -22,6 +22,7 @@
 #include <cstdint>
 
 #include "common.h"
+#include "transpose.h"
 
 namespace xc {
 xc_status resolve(const xc_config *cfg, xc_in_type in_type, xc_out_type out_type, int32_t S, int32_t P, int32_t C,
@@ -44,56 +45,11 @@ int station_sample_bytes(xc_in_type t) {
 bool valid_in_type(int t) { return t >= XC_IN_CF32 && t <= XC_IN_CBF16; }
 
 // Transpose of each channel's S x T matrix of station samples (E = 4, 8 or 16
-// bytes) from x[c][s][t] to x[c][t][s], through a 32 x 32 LDS tile padded by
-// one element per row: reads run along t and writes along s, 32 consecutive
-// elements per 32 lanes.
-constexpr int TT = 32;
-
-template <typename E>
-__global__ __launch_bounds__(256) void transpose_kernel(const E *__restrict__ src, E *__restrict__ dst, int S,
-                                                        int T, int c0) {
-    __shared__ E tile[TT][TT + 1];
-    const int c = c0 + blockIdx.z;
-    const int t0 = blockIdx.x * TT, s0 = blockIdx.y * TT;
-    const int tx = threadIdx.x & (TT - 1), ty = threadIdx.x / TT;
-    const E *in = src + (size_t)c * S * T;
-    E *out = dst + (size_t)c * S * T;
-#pragma unroll
-    for (int r = 0; r < TT; r += 256 / TT) {
-        const int s = s0 + ty + r, t = t0 + tx;
-        if (s < S && t < T) tile[ty + r][tx] = in[(size_t)s * T + t];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < TT; r += 256 / TT) {
-        const int t = t0 + ty + r, s = s0 + tx;
-        if (s < S && t < T) out[(size_t)t * S + s] = tile[tx][ty + r];
-    }
-}
-
+// bytes) from x[c][s][t] to x[c][t][s].
 hipError_t launch_transpose(const void *src, void *dst, xc_in_type in_type, int S, int C, int T,
                             hipStream_t stream) {
-    const dim3 block(256);
-    for (int c0 = 0; c0 < C; c0 += 65535) {
-        const dim3 grid((T + TT - 1) / TT, (S + TT - 1) / TT, std::min(C - c0, 65535));
-        switch (station_sample_bytes(in_type)) {
-        case 16:
-            hipLaunchKernelGGL(transpose_kernel<uint4>, grid, block, 0, stream, static_cast<const uint4 *>(src),
-                               static_cast<uint4 *>(dst), S, T, c0);
-            break;
-        case 8:
-            hipLaunchKernelGGL(transpose_kernel<uint2>, grid, block, 0, stream, static_cast<const uint2 *>(src),
-                               static_cast<uint2 *>(dst), S, T, c0);
-            break;
-        default:
-            hipLaunchKernelGGL(transpose_kernel<uint32_t>, grid, block, 0, stream,
-                               static_cast<const uint32_t *>(src), static_cast<uint32_t *>(dst), S, T, c0);
-            break;
-        }
-        const hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
+    const int64_t st = (int64_t)S * T;
+    return launch_transpose_tiles(src, dst, station_sample_bytes(in_type), S, T, T, S, st, st, C, stream);
 }
 
 xc_status check_shape(xc_in_type in_type, int32_t S, int32_t P, int32_t C, int32_t T) {

@@ -257,3 +257,19 @@ def test_ingest_and_transpose_validation():
                          ((VP(66), VP(64), 1, 8, 2, 1, 4), 1), ((VP(64), VP(128), 5, 8, 2, 1, 4), 1),
                          ((VP(64), VP(128), 0, 8, 3, 1, 4), 2), ((VP(64), VP(128), 0, 8, 2, 1, 0), 1)]:
         assert lib.xc_transpose_to_time_major(*args, None) == status, args
+
+
+def test_pfb_validation():
+    """Filter-bank plans reject bad shapes before touching the device."""
+    lib = _lib.load()
+    h = ctypes.c_void_p()
+    ok = dict(S=4, P=2, N=256, M=4, n_in=4 * 256)
+    for bad, status in [(dict(N=128), 2), (dict(N=1024), 2), (dict(P=1), 2), (dict(M=0), 1), (dict(M=17), 1),
+                        (dict(S=0), 1), (dict(S=16385), 1), (dict(n_in=4 * 256 - 1), 1), (dict(n_in=1 << 31), 1)]:
+        a = {**ok, **bad}
+        assert lib.xc_pfb_create(a["S"], a["P"], a["N"], a["M"], a["n_in"], ctypes.byref(h)) == status, bad
+        assert not h.value
+    assert lib.xc_pfb_create(4, 2, 256, 4, 1024, None) == 1
+    assert lib.xc_pfb_run(None, VP(64), VP(64), None, VP(128), None) == 1
+    assert lib.xc_pfb_info(None, None, None) == 1
+    lib.xc_pfb_destroy(None)
