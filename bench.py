@@ -21,6 +21,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -206,6 +207,7 @@ def main():
     ap.add_argument("--batch-only", action="store_true", help="run only the batch measurement")
     ap.add_argument("--no-ingest", action="store_true", help="skip the host-ingest measurement")
     ap.add_argument("--ingest-only", action="store_true", help="run only the host-ingest measurement")
+    ap.add_argument("--fengine-only", action="store_true", help="run only the filter-bank measurement")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this correlator build runs on one GPU; channels would shard across GPUs "
@@ -223,6 +225,9 @@ def main():
     stream = torch.cuda.current_stream()
     if args.stream_only:
         print(json.dumps(stream_all(xe, inputs, torch, args)), flush=True)
+        return
+    if args.fengine_only:
+        print(json.dumps({"fengine": fengine_bench(xe, inputs, torch, dev, stream)}), flush=True)
         return
     if args.ingest_only:
         print(json.dumps({"ingest": ingest_bench(xe, inputs, torch, dev, stream)}), flush=True)
@@ -311,6 +316,7 @@ def main():
         res.update(stream_all(xe, inputs, torch, args))
         if not args.no_ingest:
             res["ingest"] = ingest_bench(xe, inputs, torch, dev, stream)
+        res["fengine"] = fengine_bench(xe, inputs, torch, dev, stream)
 
     if not args.no_cpu_baseline:
         xh = None
@@ -506,6 +512,47 @@ def ingest_bench(xe, inputs, torch, dev, stream, reps=5):
         del x, o, dev_buf
         torch.cuda.empty_cache()
     return out
+
+
+def fengine_bench(xe, inputs, torch, dev, stream, steps=20):
+    """F-engine: 64 stations x 2 pol of CN(0,1) sample streams through a
+    256-channel, 16-tap polyphase filter bank into 768 frames (the lofar64
+    block: 256 channels x 768 samples x 64 stations), then correlated.  The
+    filter bank is HBM-bound: algorithmic bytes = samples in + channels out
+    (8 bytes each); the two kernels also write and read an intermediate of the
+    output's size.  Flops per output sample: 4 per tap (complex x real) plus
+    5 log2 N for the FFT."""
+    S, N, M, T = 64, 256, 16, 768
+    n_in = (T + M - 1) * N
+    z = inputs.station_streams(S, n_in, seed=6, device=dev)
+    taps = torch.from_numpy(inputs.pfb_taps(N, M)).to(dev)
+    fb = xe.Pfb(S, N, M, n_in)
+    x = torch.empty(fb.out_shape(), dtype=torch.complex64, device=dev)
+    o = torch.empty(xe.vis_shape(N, S, xe.XC_OUT_CF32), dtype=torch.complex64, device=dev)
+    ms_f = time_launches(lambda: fb.run(z, taps, out=x, stream=stream), steps, 3, stream)
+    ms_x = time_launches(lambda: xe.correlate_into(x, o, stream=stream), steps, 3, stream)
+
+    def fx():
+        fb.run(z, taps, out=x, stream=stream)
+        xe.correlate_into(x, o, stream=stream)
+    ms_fx = time_launches(fx, steps, 3, stream)
+    alg = (z.numel() + x.numel()) * 8
+    moved = alg + 2 * x.numel() * 8
+    flops_f = x.numel() * (4 * M + 5 * math.log2(N))
+    flops_x = xe.flops(S, N, T)
+    fb.close()
+    r = {"workload": f"{S} stations x 2 pol, {n_in} samples per stream -> {N} channels x {T} frames, {M} taps",
+         "filter_bank_ms": round(ms_f, 4),
+         "filter_bank_Gsamples/s": round(z.numel() / (ms_f * 1e-3) / 1e9, 1),
+         "roofline": {"bound": "hbm", "achieved": round(alg / (ms_f * 1e-3) / 1e9, 1), "peak": PEAKS["hbm_GBs"],
+                      "unit": "GB/s", "frac": round(alg / (ms_f * 1e-3) / 1e9 / PEAKS["hbm_GBs"], 4),
+                      "traffic": None, "bytes_moved_incl_intermediate_GB/s": round(moved / (ms_f * 1e-3) / 1e9, 1)},
+         "filter_bank_TFLOP/s": round(flops_f / (ms_f * 1e-3) / 1e12, 2),
+         "correlator_ms": round(ms_x, 4), "f_then_x_ms": round(ms_fx, 4),
+         "f_then_x_correlator_TFLOP/s": round(flops_x / (ms_fx * 1e-3) / 1e12, 1)}
+    del z, x, o
+    torch.cuda.empty_cache()
+    return r
 
 
 def stream_all(xe, inputs, torch, args):

@@ -14,8 +14,9 @@
 // Two HBM-bound kernels:
 //  * filter_fft: one workgroup per (station-polarisation stream, block of
 //    frames); thread n owns polyphase branch n (and n + 256): its M taps and
-//    a sliding window of its last M input samples stay in registers, so each
-//    input sample is read once, coalesced (a frame is N consecutive samples);
+//    the samples of the block's frames (plus the M - 1 frames after them)
+//    are loaded into registers at once, coalesced (a frame is N consecutive
+//    samples), so that the block waits for memory once;
 //    the branch outputs of the block's frames go to LDS and are transformed
 //    there by a radix-2 Stockham FFT (two ping-pong buffers, twiddles from a
 //    table computed on the host in double precision), then weighted and
@@ -58,40 +59,41 @@ __global__ __launch_bounds__(THREADS) void filter_fft(const float2 *__restrict__
     for (int i = tid; i < N / 2; i += THREADS) tw[i] = twiddle[i];
 
     const float2 *zs = z + (size_t)stream * n_in;
+    // every input sample of the block's frames (frames f0 .. f0 + nf + M - 2 of
+    // the stream) is loaded at once, so that the block waits for memory once;
+    // the loads are unconditional (frame indices clamped to the last frame of
+    // the input, taps past M zeroed) so that the compiler issues them together
+    constexpr int NZ = G::FB + MAX_TAPS - 1;
+    const int last = T + M - 2;
     float h[MAX_TAPS][G::BR];
-    float2 win[MAX_TAPS][G::BR];
+    float2 zin[NZ][G::BR];
 #pragma unroll
     for (int m = 0; m < MAX_TAPS; ++m)
 #pragma unroll
         for (int b = 0; b < G::BR; ++b) {
-            h[m][b] = m < M ? taps[m * N + tid + b * THREADS] : 0.f;
-            // the window of the block's first frame, but for its last sample
-            win[m][b] = (m < M - 1) ? zs[(size_t)(f0 + m) * N + tid + b * THREADS] : make_float2(0.f, 0.f);
+            const float v = taps[(m < M ? m : M - 1) * N + tid + b * THREADS];
+            h[m][b] = m < M ? v : 0.f;
         }
-    // filter: frame f needs samples of frames f .. f + M - 1 of the stream
-    for (int f = 0; f < nf; ++f) {
+#pragma unroll
+    for (int i = 0; i < NZ; ++i)
 #pragma unroll
         for (int b = 0; b < G::BR; ++b) {
-            const int n = tid + b * THREADS;
-            // newest sample of the window: frame f0 + f + M - 1 (always < T + M - 1)
-            float2 v = zs[(size_t)(f0 + f + M - 1) * N + n];
+            const int fi = f0 + i < last ? f0 + i : last;
+            zin[i][b] = zs[(size_t)fi * N + tid + b * THREADS];
+        }
+    // filter: frame f0 + f sums taps m over the samples of frames f0 + f + m
 #pragma unroll
-            for (int m = 0; m < MAX_TAPS; ++m)
-                if (m == M - 1) win[m][b] = v;
+    for (int f = 0; f < G::FB; ++f)
+#pragma unroll
+        for (int b = 0; b < G::BR; ++b) {
             float ur = 0.f, ui = 0.f;
 #pragma unroll
             for (int m = 0; m < MAX_TAPS; ++m) {
-                if (m < M) {
-                    ur += h[m][b] * win[m][b].x;
-                    ui += h[m][b] * win[m][b].y;
-                }
+                ur += h[m][b] * zin[f + m][b].x;
+                ui += h[m][b] * zin[f + m][b].y;
             }
-            buf[0][f * N + n] = make_float2(ur, ui);
-            // slide the window by one frame
-#pragma unroll
-            for (int m = 0; m + 1 < MAX_TAPS; ++m) win[m][b] = win[m + 1][b];
+            if (f < nf) buf[0][f * N + tid + b * THREADS] = make_float2(ur, ui);
         }
-    }
     __syncthreads();
 
     // Stockham radix-2 FFT of the nf frames: sub-transform size ns doubles each
@@ -131,12 +133,152 @@ __global__ __launch_bounds__(THREADS) void filter_fft(const float2 *__restrict__
     }
 }
 
+// ---- 256 channels: the FFT as 16 x 16 (four-step), 16-point DFTs in registers
+//
+// With n = 16 n1 + n2 and k = k1 + 16 k2:
+//   X[k1 + 16 k2] = sum_n2 W16^(n2 k2) W256^(n2 k1) sum_n1 W16^(n1 k1) u[16 n1 + n2].
+// Pass 1: thread (frame, n2) takes the 16-point DFT over n1, multiplies by
+// W256^(n2 k1) and writes the results back over its own inputs; pass 2:
+// thread (frame, k1) takes the 16-point DFT over n2 and writes its channels
+// k1 + 16 k2 (16 consecutive channels per 16 lanes).  LDS rows of 16
+// elements are padded by one element so that both passes are free of bank
+// conflicts.  Two barriers instead of eight LDS passes.
+
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// exp(-2 pi i m / 16)
+__constant__ float2 W16[16] = {
+    {1.000000000f, -0.000000000f},
+    {0.923879533f, -0.382683432f},
+    {0.707106781f, -0.707106781f},
+    {0.382683432f, -0.923879533f},
+    {0.000000000f, -1.000000000f},
+    {-0.382683432f, -0.923879533f},
+    {-0.707106781f, -0.707106781f},
+    {-0.923879533f, -0.382683432f},
+    {-1.000000000f, -0.000000000f},
+    {-0.923879533f, 0.382683432f},
+    {-0.707106781f, 0.707106781f},
+    {-0.382683432f, 0.923879533f},
+    {-0.000000000f, 1.000000000f},
+    {0.382683432f, 0.923879533f},
+    {0.707106781f, 0.707106781f},
+    {0.923879533f, 0.382683432f}
+};
+
+// In-place forward 4-point DFT: (a, b, c, d) -> (X0, X1, X2, X3).
+__device__ __forceinline__ void dft4(float2 &a, float2 &b, float2 &c, float2 &d) {
+    const float2 s0 = make_float2(a.x + c.x, a.y + c.y), s1 = make_float2(a.x - c.x, a.y - c.y);
+    const float2 s2 = make_float2(b.x + d.x, b.y + d.y), s3 = make_float2(b.x - d.x, b.y - d.y);
+    a = make_float2(s0.x + s2.x, s0.y + s2.y);
+    c = make_float2(s0.x - s2.x, s0.y - s2.y);
+    b = make_float2(s1.x + s3.y, s1.y - s3.x);    // s1 - i s3
+    d = make_float2(s1.x - s3.y, s1.y + s3.x);    // s1 + i s3
+}
+
+// In-place forward 16-point DFT, natural order in and out (4 x 4 steps).
+__device__ __forceinline__ void dft16(float2 (&x)[16]) {
+    float2 t[16];
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) {
+        float2 a = x[n2], b = x[4 + n2], c = x[8 + n2], d = x[12 + n2];
+        dft4(a, b, c, d);
+        t[4 * n2 + 0] = a;
+        t[4 * n2 + 1] = cmul(b, W16[n2]);
+        t[4 * n2 + 2] = cmul(c, W16[2 * n2]);
+        t[4 * n2 + 3] = cmul(d, W16[3 * n2]);
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+        float2 a = t[k1], b = t[4 + k1], c = t[8 + k1], d = t[12 + k1];
+        dft4(a, b, c, d);
+        x[k1] = a;
+        x[k1 + 4] = b;
+        x[k1 + 8] = c;
+        x[k1 + 12] = d;
+    }
+}
+
+__global__ __launch_bounds__(THREADS) void filter_fft256(const float2 *__restrict__ z, const float *__restrict__ taps,
+                                                         const float2 *__restrict__ weights,
+                                                         const float2 *__restrict__ twiddle, float2 *__restrict__ y,
+                                                         int M, int n_in, int T) {
+    constexpr int N = 256, FB = 16, PAD = 17, FROW = 16 * PAD;
+    __shared__ __attribute__((aligned(16))) float2 buf[FB * FROW];
+    __shared__ float2 tw[N / 2];
+    const int tid = threadIdx.x;
+    const int stream = blockIdx.y;
+    const int f0 = blockIdx.x * FB;
+    const int nf = T - f0 < FB ? T - f0 : FB;
+    for (int i = tid; i < N / 2; i += THREADS) tw[i] = twiddle[i];
+
+    // filter, as in the general kernel: all inputs of the block loaded at once
+    const float2 *zs = z + (size_t)stream * n_in;
+    constexpr int NZ = FB + MAX_TAPS - 1;
+    const int last = T + M - 2;
+    float h[MAX_TAPS];
+    float2 zin[NZ];
+#pragma unroll
+    for (int m = 0; m < MAX_TAPS; ++m) {
+        const float v = taps[(m < M ? m : M - 1) * N + tid];
+        h[m] = m < M ? v : 0.f;
+    }
+#pragma unroll
+    for (int i = 0; i < NZ; ++i) zin[i] = zs[(size_t)(f0 + i < last ? f0 + i : last) * N + tid];
+#pragma unroll
+    for (int f = 0; f < FB; ++f) {
+        float ur = 0.f, ui = 0.f;
+#pragma unroll
+        for (int m = 0; m < MAX_TAPS; ++m) {
+            ur += h[m] * zin[f + m].x;
+            ui += h[m] * zin[f + m].y;
+        }
+        if (f < nf) buf[f * FROW + tid + (tid >> 4)] = make_float2(ur, ui);
+    }
+    __syncthreads();
+
+    const int f = tid >> 4, q = tid & 15;
+    float2 a[16];
+    if (f < nf) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) a[i] = buf[f * FROW + PAD * i + q];       // u[16 i + q]
+        dft16(a);
+#pragma unroll
+        for (int k1 = 0; k1 < 16; ++k1) {
+            const int j = q * k1;                                              // W256^j, j <= 225
+            const float2 w = j < N / 2 ? tw[j] : make_float2(-tw[j - N / 2].x, -tw[j - N / 2].y);
+            buf[f * FROW + PAD * k1 + q] = cmul(a[k1], w);
+        }
+    }
+    __syncthreads();
+    if (f < nf) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) a[i] = buf[f * FROW + PAD * q + i];       // pass-1 output n2 = i, k1 = q
+        dft16(a);
+        float2 *yr = y + ((size_t)stream * T + f0 + f) * N;
+        const float2 *ws = weights ? weights + (size_t)stream * N : nullptr;
+#pragma unroll
+        for (int k2 = 0; k2 < 16; ++k2) {
+            const int k = q + 16 * k2;
+            yr[k] = ws ? cmul(a[k2], ws[k]) : a[k2];
+        }
+    }
+}
+
 template <int N>
 hipError_t launch_filter_fft(const void *z, const float *taps, const void *weights, const float2 *twiddle, void *y,
                              int streams, int M, int n_in, int T, hipStream_t stream) {
-    const dim3 grid((T + Geo<N>::FB - 1) / Geo<N>::FB, streams);
-    hipLaunchKernelGGL(filter_fft<N>, grid, dim3(THREADS), 0, stream, static_cast<const float2 *>(z), taps,
-                       static_cast<const float2 *>(weights), twiddle, static_cast<float2 *>(y), M, n_in, T);
+    if constexpr (N == 256) {
+        const dim3 grid((T + 15) / 16, streams);
+        hipLaunchKernelGGL(filter_fft256, grid, dim3(THREADS), 0, stream, static_cast<const float2 *>(z), taps,
+                           static_cast<const float2 *>(weights), twiddle, static_cast<float2 *>(y), M, n_in, T);
+    } else {
+        const dim3 grid((T + Geo<N>::FB - 1) / Geo<N>::FB, streams);
+        hipLaunchKernelGGL(filter_fft<N>, grid, dim3(THREADS), 0, stream, static_cast<const float2 *>(z), taps,
+                           static_cast<const float2 *>(weights), twiddle, static_cast<float2 *>(y), M, n_in, T);
+    }
     return hipGetLastError();
 }
 
