@@ -227,7 +227,8 @@ def main():
         print(json.dumps(stream_all(xe, inputs, torch, args)), flush=True)
         return
     if args.fengine_only:
-        print(json.dumps({"fengine": fengine_bench(xe, inputs, torch, dev, stream)}), flush=True)
+        print(json.dumps({"fengine": fengine_bench(xe, inputs, torch, dev, stream),
+                          "small_launch": small_launch_bench(xe, inputs, torch, dev, stream)}), flush=True)
         return
     if args.ingest_only:
         print(json.dumps({"ingest": ingest_bench(xe, inputs, torch, dev, stream)}), flush=True)
@@ -317,6 +318,7 @@ def main():
         if not args.no_ingest:
             res["ingest"] = ingest_bench(xe, inputs, torch, dev, stream)
         res["fengine"] = fengine_bench(xe, inputs, torch, dev, stream)
+        res["small_launch"] = small_launch_bench(xe, inputs, torch, dev, stream)
 
     if not args.no_cpu_baseline:
         xh = None
@@ -512,6 +514,34 @@ def ingest_bench(xe, inputs, torch, dev, stream, reps=5):
         del x, o, dev_buf
         torch.cuda.empty_cache()
     return out
+
+
+def small_launch_bench(xe, inputs, torch, dev, stream, n=1000):
+    """The 8-station workload (8 stations, 16 channels, 256 samples; 4.7e6
+    flop): bound by launch latency, timed as n back-to-back launches and as
+    the same n launches captured in one HIP graph and replayed."""
+    S, C, T = 8, 16, 256
+    x = inputs.cn_gaussian(C, T, S, seed=1, device=dev)
+    o = torch.empty(xe.vis_shape(C, S, xe.XC_OUT_CF32), dtype=torch.complex64, device=dev)
+    eager = time_launches(lambda: xe.correlate_into(x, o, stream=stream), n, 50, stream)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        for _ in range(3):
+            xe.correlate_into(x, o, stream=side)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=side):
+        for _ in range(n):
+            xe.correlate_into(x, o, stream=side)
+    torch.cuda.synchronize()
+    replay = time_launches(lambda: g.replay(), 5, 2, torch.cuda.current_stream()) / n
+    flops = xe.flops(S, C, T)
+    return {"workload": f"{S} stations, {C} channels, {T} samples, complex64 CN(0,1)",
+            "eager_us_per_launch": round(eager * 1e3, 2), "graph_us_per_launch": round(replay * 1e3, 2),
+            "eager_TFLOP/s": round(flops / (eager * 1e-3) / 1e12, 3),
+            "graph_TFLOP/s": round(flops / (replay * 1e-3) / 1e12, 3)}
 
 
 def fengine_bench(xe, inputs, torch, dev, stream, steps=20):

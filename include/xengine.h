@@ -154,7 +154,8 @@ xc_status xc_correlate(const void *samples, xc_in_type in_type, int32_t n_statio
  * Kernel configuration.  Zero fields mean "default for this shape".
  *   kernel        xc_kernel
  *   block         stations per block of the triangle's block grid (Section 4.5
- *                 splits large triangles into blocks).  VALU: 32.  MFMA: 32 or 64.
+ *                 splits large triangles into blocks).  VALU: 32.  MFMA: 32 or 64
+ *                 (AUTO: 32 for complex-float32 on at most 48 stations, else 64).
  *   time_chunk    time steps staged in LDS per pipeline stage (fixed by the
  *                 other fields except for VALU: 16 or 32; complex-float32 on
  *                 64-station blocks reports its off-diagonal chunk, diagonal

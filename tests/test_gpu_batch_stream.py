@@ -195,3 +195,29 @@ def test_stream_state_errors_and_admission():
     srv.close_stream(b)
     srv.close_stream(c)
     srv.close()
+
+
+def test_correlate_captured_in_a_graph():
+    """xc_correlate launches captured in a HIP graph (as the launch-latency
+    measurement does): every replay, with eager work in between, gives the
+    eager result exactly (same kernel, same inputs)."""
+    S, C, T = 8, 16, 256
+    x = inputs.cn_gaussian(C, T, S, seed=1, device=DEV)
+    ref = xe.correlate(x)
+    out = torch.zeros_like(ref)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        xe.correlate_into(x, out, stream=side)          # warm-up outside the capture
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=side):
+        for _ in range(4):
+            xe.correlate_into(x, out, stream=side)
+    for _ in range(3):
+        out.zero_()                                      # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref)
