@@ -44,6 +44,7 @@ KERNEL_SOURCES = {
     "mfma": [_CSRC + "mfma.hip", _CSRC + "mfma_parts.h", _CSRC + "common.h"],
     "mfma16": [_CSRC + "mfma16.hip", _CSRC + "lds_dma.h", _CSRC + "common.h"],
     "dma": [_CSRC + "mfma_dma.hip", _CSRC + "lds_dma.h", _CSRC + "mfma_parts.h", _CSRC + "common.h"],
+    "pfb": [_CSRC + "pfb.hip", _CSRC + "transpose.h", _CSRC + "common.h"],
 }
 
 
@@ -571,12 +572,15 @@ def fengine_bench(xe, inputs, torch, dev, stream, steps=20):
     flops_f = x.numel() * (4 * M + 5 * math.log2(N))
     flops_x = xe.flops(S, N, T)
     fb.close()
+    # HBM bytes of one filter-bank run (both kernels) from the committed counter summary
+    tf, tt = load_traffic("fengine_filter_fft", "pfb"), load_traffic("fengine_corner_turn", "pfb")
+    traffic = tf + tt if tf is not None and tt is not None else None
     r = {"workload": f"{S} stations x 2 pol, {n_in} samples per stream -> {N} channels x {T} frames, {M} taps",
          "filter_bank_ms": round(ms_f, 4),
          "filter_bank_Gsamples/s": round(z.numel() / (ms_f * 1e-3) / 1e9, 1),
          "roofline": {"bound": "hbm", "achieved": round(alg / (ms_f * 1e-3) / 1e9, 1), "peak": PEAKS["hbm_GBs"],
                       "unit": "GB/s", "frac": round(alg / (ms_f * 1e-3) / 1e9 / PEAKS["hbm_GBs"], 4),
-                      "traffic": None, "bytes_moved_incl_intermediate_GB/s": round(moved / (ms_f * 1e-3) / 1e9, 1)},
+                      "traffic": traffic, "bytes_moved_incl_intermediate_GB/s": round(moved / (ms_f * 1e-3) / 1e9, 1)},
          "filter_bank_TFLOP/s": round(flops_f / (ms_f * 1e-3) / 1e12, 2),
          "correlator_ms": round(ms_x, 4), "f_then_x_ms": round(ms_fx, 4),
          "f_then_x_correlator_TFLOP/s": round(flops_x / (ms_fx * 1e-3) / 1e12, 1)}

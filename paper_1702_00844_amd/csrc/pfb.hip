@@ -204,13 +204,17 @@ __device__ __forceinline__ void dft16(float2 (&x)[16]) {
 __global__ __launch_bounds__(THREADS) void filter_fft256(const float2 *__restrict__ z, const float *__restrict__ taps,
                                                          const float2 *__restrict__ weights,
                                                          const float2 *__restrict__ twiddle, float2 *__restrict__ y,
-                                                         int M, int n_in, int T) {
+                                                         int M, int n_in, int T, int nfb, int nwork) {
     constexpr int N = 256, FB = 16, PAD = 17, FROW = 16 * PAD;
     __shared__ __attribute__((aligned(16))) float2 buf[FB * FROW];
     __shared__ float2 tw[N / 2];
     const int tid = threadIdx.x;
-    const int stream = blockIdx.y;
-    const int f0 = blockIdx.x * FB;
+    // consecutive frame blocks of a stream on one XCD: the M - 1 frames a block
+    // shares with the next one are then read from that XCD's L2
+    const int w = xcd_remap(blockIdx.x, nwork);
+    if (w < 0) return;
+    const int stream = w / nfb;
+    const int f0 = (w - stream * nfb) * FB;
     const int nf = T - f0 < FB ? T - f0 : FB;
     for (int i = tid; i < N / 2; i += THREADS) tw[i] = twiddle[i];
 
@@ -271,9 +275,12 @@ template <int N>
 hipError_t launch_filter_fft(const void *z, const float *taps, const void *weights, const float2 *twiddle, void *y,
                              int streams, int M, int n_in, int T, hipStream_t stream) {
     if constexpr (N == 256) {
-        const dim3 grid((T + 15) / 16, streams);
-        hipLaunchKernelGGL(filter_fft256, grid, dim3(THREADS), 0, stream, static_cast<const float2 *>(z), taps,
-                           static_cast<const float2 *>(weights), twiddle, static_cast<float2 *>(y), M, n_in, T);
+        const int nfb = (T + 15) / 16;
+        const int64_t nwork = (int64_t)nfb * streams;
+        if (nwork > ((int64_t)1 << 31) - kNumXcd) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(filter_fft256, dim3(xcd_grid((int)nwork)), dim3(THREADS), 0, stream,
+                           static_cast<const float2 *>(z), taps, static_cast<const float2 *>(weights), twiddle,
+                           static_cast<float2 *>(y), M, n_in, T, nfb, (int)nwork);
     } else {
         const dim3 grid((T + Geo<N>::FB - 1) / Geo<N>::FB, streams);
         hipLaunchKernelGGL(filter_fft<N>, grid, dim3(THREADS), 0, stream, static_cast<const float2 *>(z), taps,
@@ -316,6 +323,11 @@ xc_status xc_pfb_create(int32_t n_stations, int32_t n_pol, int32_t n_channels, i
     if (n_in < (int64_t)n_taps * n_channels || n_in > ((int64_t)1 << 31) - 1)
         return set_error(XC_ERR_INVALID_ARG, "n_in = %lld: need n_taps * n_channels .. 2^31 - 1 samples",
                          (long long)n_in);
+    {
+        const int64_t T = n_in / n_channels - n_taps + 1;
+        if ((T + 15) / 16 * 2 * (int64_t)n_stations > ((int64_t)1 << 31) - 1024)
+            return set_error(XC_ERR_UNSUPPORTED, "too many (stream, frame block) work units");
+    }
     xc_pfb *p = new xc_pfb;
     p->S = n_stations;
     p->P = n_pol;
