@@ -539,10 +539,25 @@ def small_launch_bench(xe, inputs, torch, dev, stream, n=1000):
     torch.cuda.synchronize()
     replay = time_launches(lambda: g.replay(), 5, 2, torch.cuda.current_stream()) / n
     flops = xe.flops(S, C, T)
+    # the integration split over workgroups (partial sums added in a fixed order)
+    split = {}
+    for k in (4, 16, 64):
+        ms = time_launches(lambda: xe.correlate_into(x, o, stream=stream, split=k), n // 4, 20, stream)
+        split[str(k)] = round(ms * 1e3, 2)
+    best = min(split, key=lambda k: split[k])
+    gs = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(gs, stream=side):
+        for _ in range(n):
+            xe.correlate_into(x, o, stream=side, split=int(best))
+    torch.cuda.synchronize()
+    replay_split = time_launches(lambda: gs.replay(), 5, 2, torch.cuda.current_stream()) / n
     return {"workload": f"{S} stations, {C} channels, {T} samples, complex64 CN(0,1)",
             "eager_us_per_launch": round(eager * 1e3, 2), "graph_us_per_launch": round(replay * 1e3, 2),
             "eager_TFLOP/s": round(flops / (eager * 1e-3) / 1e12, 3),
-            "graph_TFLOP/s": round(flops / (replay * 1e-3) / 1e12, 3)}
+            "graph_TFLOP/s": round(flops / (replay * 1e-3) / 1e12, 3),
+            "split_eager_us_per_launch": split, "split_best": int(best),
+            "split_graph_us_per_launch": round(replay_split * 1e3, 2),
+            "split_graph_TFLOP/s": round(flops / (replay_split * 1e-3) / 1e12, 3)}
 
 
 def fengine_bench(xe, inputs, torch, dev, stream, steps=20):

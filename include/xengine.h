@@ -151,6 +151,23 @@ xc_status xc_correlate(const void *samples, xc_in_type in_type, int32_t n_statio
                        xc_out_type out_type, int32_t accumulate, void *stream);
 
 /*
+ * The same correlation with the integration split over workgroups, for
+ * workloads with few (channel, block pair) units, such as few channels and
+ * stations (Section 4.5 splits long integrations the same way): the T time
+ * steps are cut into pieces of ceil(T / n_split) steps (K pieces, K <= n_split,
+ * none empty), each piece's partial sums are written to `work` (device,
+ * caller-owned, at least xc_correlate_split_bytes bytes, 16-byte aligned),
+ * then vis (+)= the sum over pieces 0 .. K-1 in that order: the reduction
+ * order is fixed, so results are reproducible for a given n_split (int32:
+ * exact; float: may differ from the unsplit kernel by rounding).  Allocates
+ * nothing.  n_split = 1 (or T = 1) is xc_correlate_config.  Errors as
+ * xc_correlate_config, and XC_ERR_INVALID_ARG for n_split < 1, a null or
+ * misaligned work pointer or too small a work_bytes.
+ */
+int64_t xc_correlate_split_bytes(int32_t n_stations, int32_t n_pol, int32_t n_channels, int32_t n_times,
+                                 int32_t n_split);
+
+/*
  * Kernel configuration.  Zero fields mean "default for this shape".
  *   kernel        xc_kernel
  *   block         stations per block of the triangle's block grid (Section 4.5
@@ -193,6 +210,11 @@ xc_status xc_correlate_config(const xc_config *cfg, const void *samples, xc_in_t
                               int32_t n_stations, int32_t n_pol, int32_t n_channels,
                               int32_t n_times, void *vis, xc_out_type out_type,
                               int32_t accumulate, void *stream);
+
+/* See xc_correlate_split_bytes above. */
+xc_status xc_correlate_split(const xc_config *cfg, const void *samples, xc_in_type in_type, int32_t n_stations,
+                             int32_t n_pol, int32_t n_channels, int32_t n_times, void *vis, xc_out_type out_type,
+                             int32_t accumulate, int32_t n_split, void *work, int64_t work_bytes, void *stream);
 
 /* ------------------------------------------------------------------------ */
 /* Cost model (Section 2, Table 1; Section 3.6 bound-and-bottleneck).        */

@@ -139,8 +139,12 @@ def resolve_config(x_shape_type, out_type=XC_OUT_CF32, config=None) -> dict:
 
 
 def correlate_into(x: torch.Tensor, out: torch.Tensor, accumulate: bool = False, stream=None,
-                   config=None) -> torch.Tensor:
-    """out (+)= correlation of x; out dtype complex64 (XC_OUT_CF32) or int32 (XC_OUT_CI32)."""
+                   config=None, split: int = 1) -> torch.Tensor:
+    """out (+)= correlation of x; out dtype complex64 (XC_OUT_CF32) or int32 (XC_OUT_CI32).
+    split > 1 cuts the integration into that many pieces, one set of
+    workgroups each, and adds their partial sums in a fixed order (for
+    workloads with few channels and stations); the workspace is a torch
+    allocation on the device."""
     in_type, C, T, S, P = in_type_of(x)
     out_type = XC_OUT_CI32 if out.dtype == torch.int32 else XC_OUT_CF32
     if out.dtype not in (torch.int32, torch.complex64):
@@ -149,6 +153,18 @@ def correlate_into(x: torch.Tensor, out: torch.Tensor, accumulate: bool = False,
         raise ValueError(f"out has shape {tuple(out.shape)}, expected {vis_shape(C, S, out_type, P)}")
     _require_device(x, out)
     cfg = _config(config)
+    if split > 1:
+        nbytes = lib().xc_correlate_split_bytes(S, P, C, T, split)
+        if nbytes < 0:
+            raise ValueError("invalid split correlation shape")
+        work = torch.empty(max(int(nbytes), 16), dtype=torch.uint8, device=x.device)
+        if stream is not None:
+            work.record_stream(stream)
+        st = lib().xc_correlate_split(ctypes.byref(cfg) if cfg else None, ctypes.c_void_p(x.data_ptr()), in_type, S,
+                                      P, C, T, ctypes.c_void_p(out.data_ptr()), out_type, 1 if accumulate else 0,
+                                      int(split), ctypes.c_void_p(work.data_ptr()), work.numel(), _stream_ptr(stream))
+        _lib.check(st)
+        return out
     st = lib().xc_correlate_config(ctypes.byref(cfg) if cfg else None, ctypes.c_void_p(x.data_ptr()), in_type, S, P,
                                    C, T, ctypes.c_void_p(out.data_ptr()), out_type, 1 if accumulate else 0,
                                    _stream_ptr(stream))
@@ -157,7 +173,7 @@ def correlate_into(x: torch.Tensor, out: torch.Tensor, accumulate: bool = False,
 
 
 def correlate(x: torch.Tensor, out: torch.Tensor | None = None, accumulate: bool = False, stream=None,
-              config=None, out_type: int | None = None) -> torch.Tensor:
+              config=None, out_type: int | None = None, split: int = 1) -> torch.Tensor:
     """Visibilities of samples x.
 
     x: complex64 [C, T, S, 2], or int8 / float16 / bfloat16 [C, T, S, 2, 2]
@@ -172,7 +188,7 @@ def correlate(x: torch.Tensor, out: torch.Tensor | None = None, accumulate: bool
         dtype = torch.int32 if out_type == XC_OUT_CI32 else torch.complex64
         alloc = torch.zeros if accumulate else torch.empty
         out = alloc(vis_shape(C, S, out_type, P), dtype=dtype, device=x.device)
-    return correlate_into(x, out, accumulate=accumulate, stream=stream, config=config)
+    return correlate_into(x, out, accumulate=accumulate, stream=stream, config=config, split=split)
 
 
 def transpose_to_time_major(x: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:

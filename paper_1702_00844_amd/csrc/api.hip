@@ -1,4 +1,5 @@
 // C ABI: argument validation, configuration resolution, dispatch, cost model.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -183,6 +184,29 @@ static int in_bytes(xc_in_type t) {
 
 static bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
 
+// Pieces an integration of T steps is split into when n_split are asked for:
+// pieces of ceil(T / n_split) steps, none empty.
+static int32_t split_pieces(int32_t T, int32_t n_split) {
+    const int32_t k = std::min(n_split, T);
+    const int32_t len = (T + k - 1) / k;
+    return (T + len - 1) / len;
+}
+
+// vis[e] (+)= sum over pieces k = 0 .. K-1, in that order, of part[k][e]: the
+// time reduction of an integration split over workgroups, in a fixed order.
+template <typename E>
+__global__ void add_pieces(const E *__restrict__ part, E *__restrict__ vis, int64_t n, int K, int accumulate) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        E a = accumulate ? vis[e] : E{};
+        for (int k = 0; k < K; ++k) {
+            const E v = part[(int64_t)k * n + e];
+            a.x += v.x;
+            a.y += v.y;
+        }
+        vis[e] = a;
+    }
+}
+
 // -- optional scan of int8 input for -128 (XC_CHECK=1) --
 __global__ void scan_m128(const int8_t *x, size_t n, int *flag) {
     size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -227,6 +251,11 @@ Job make_job(const void *samples, void *vis, int S, int C, int T, int block, int
     j.accumulate = accumulate ? 1 : 0;
     j.tblk = T;
     j.bstride = 0;
+    j.cstride = (int64_t)T * S;
+    j.tsplit = 1;
+    j.tpiece = T;
+    j.xpiece = 0;
+    j.vpiece = 0;
     return j;
 }
 
@@ -307,6 +336,54 @@ xc_status xc_correlate_config(const xc_config *cfg, const void *samples, xc_in_t
     }
     const Job job = make_job(samples, vis, n_stations, n_channels, n_times, plan.block, accumulate);
     return launch_plan(plan, in_type, out_type, job, s);
+}
+
+int64_t xc_correlate_split_bytes(int32_t n_stations, int32_t n_pol, int32_t n_channels, int32_t n_times,
+                                 int32_t n_split) {
+    if (n_stations < 1 || n_pol != 2 || n_channels < 1 || n_times < 1 || n_split < 1) return -1;
+    const int32_t K = split_pieces(n_times, n_split);
+    return (int64_t)K * xc_vis_elems(n_stations, n_pol, n_channels) * 8;
+}
+
+xc_status xc_correlate_split(const xc_config *cfg, const void *samples, xc_in_type in_type, int32_t n_stations,
+                             int32_t n_pol, int32_t n_channels, int32_t n_times, void *vis, xc_out_type out_type,
+                             int32_t accumulate, int32_t n_split, void *work, int64_t work_bytes, void *stream) {
+    if (n_split < 1) return set_error(XC_ERR_INVALID_ARG, "n_split must be >= 1");
+    const int32_t K = n_times >= 1 ? split_pieces(n_times, n_split) : 1;
+    if (K == 1)
+        return xc_correlate_config(cfg, samples, in_type, n_stations, n_pol, n_channels, n_times, vis, out_type,
+                                   accumulate, stream);
+    Plan plan;
+    xc_status st = resolve(cfg, in_type, out_type, n_stations, n_pol, n_channels, n_times, &plan);
+    if (st != XC_OK) return st;
+    if (!samples || !vis || !work) return set_error(XC_ERR_INVALID_ARG, "null samples, vis or work pointer");
+    if (!aligned16(samples) || !aligned16(vis) || !aligned16(work))
+        return set_error(XC_ERR_INVALID_ARG, "samples, vis and work must be 16-byte aligned");
+    if (accumulate != 0 && accumulate != 1) return set_error(XC_ERR_INVALID_ARG, "accumulate must be 0 or 1");
+    const int64_t elems = xc_vis_elems(n_stations, n_pol, n_channels);
+    if (work_bytes < (int64_t)K * elems * 8)
+        return set_error(XC_ERR_INVALID_ARG, "work holds %lld bytes, %lld needed", (long long)work_bytes,
+                         (long long)K * elems * 8);
+    Job job = make_job(samples, work, n_stations, n_channels, n_times, plan.block, 0);
+    job.tsplit = K;
+    job.tpiece = (n_times + K - 1) / K;
+    job.xpiece = (int64_t)job.tpiece * n_stations * 2 * in_bytes(in_type);
+    job.vpiece = elems * 8;
+    if ((int64_t)job.C * job.npairs * K > ((int64_t)1 << 30))
+        return set_error(XC_ERR_UNSUPPORTED, "too many work units");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    st = launch_plan(plan, in_type, out_type, job, s);
+    if (st != XC_OK) return st;
+    const int blocks = (int)std::min<int64_t>((elems + 255) / 256, 65536);
+    if (out_type == XC_OUT_CI32)
+        hipLaunchKernelGGL(add_pieces<int2>, dim3(blocks), dim3(256), 0, s, static_cast<const int2 *>(work),
+                           static_cast<int2 *>(vis), elems, K, accumulate);
+    else
+        hipLaunchKernelGGL(add_pieces<float2>, dim3(blocks), dim3(256), 0, s, static_cast<const float2 *>(work),
+                           static_cast<float2 *>(vis), elems, K, accumulate);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_error(e, "piece-sum launch");
+    return XC_OK;
 }
 
 xc_status xc_correlate(const void *samples, xc_in_type in_type, int32_t n_stations, int32_t n_pol,

@@ -26,12 +26,23 @@ struct Job {
     // station-samples apart.  Unblocked input has tblk = T and bstride = 0.
     int32_t tblk;
     int64_t bstride;
+    // Unblocked input: station-samples from one channel to the next (T S for
+    // a whole block; larger when the job views a sub-range of time).
+    int64_t cstride;
+    // Integration split over workgroups: unit w of the launch is piece
+    // w % tsplit of unit w / tsplit; piece k integrates time steps
+    // k tpiece .. k tpiece + tpiece - 1 into its own partial sums, xpiece
+    // bytes further into the samples and vpiece bytes further into vis.
+    int32_t tsplit;
+    int32_t tpiece;
+    int64_t xpiece;
+    int64_t vpiece;
 };
 
 // Index (in station-samples, i.e. units of one station's dual-pol sample) of
 // the first station of time step t of channel c.
 __host__ __device__ inline size_t row_offset(const Job &job, int c, int t) {
-    if (job.bstride == 0) return ((size_t)c * job.T + t) * job.S;
+    if (job.bstride == 0) return (size_t)c * job.cstride + (size_t)t * job.S;
     const int blk = t / job.tblk;
     return (size_t)blk * job.bstride + ((size_t)c * job.tblk + (t - blk * job.tblk)) * job.S;
 }
@@ -77,6 +88,25 @@ __device__ inline int xcd_remap(int phys, int nwork) {
     const int logical = (phys % kNumXcd) * per + phys / kNumXcd;
     return logical < nwork ? logical : -1;
 }
+
+// Work unit w of a flat launch -> channel and block pair; when the
+// integration is split over workgroups, the job is narrowed to the unit's
+// piece of time (its samples, its length and its partial sums).
+__device__ inline void unit_decode(Job &job, int w, int &c, int &bi, int &bj) {
+    if (job.tsplit > 1) {
+        const int piece = w % job.tsplit;
+        w /= job.tsplit;
+        job.x = static_cast<const uint8_t *>(job.x) + piece * job.xpiece;
+        job.vis = static_cast<uint8_t *>(job.vis) + piece * job.vpiece;
+        const int rest = job.T - piece * job.tpiece;
+        job.T = rest < job.tpiece ? rest : job.tpiece;
+    }
+    c = w / job.npairs;
+    pair_decode(w - c * job.npairs, bi, bj);
+}
+
+// Work units of a flat launch of a job.
+inline int job_units(const Job &job) { return job.C * job.npairs * job.tsplit; }
 
 inline int xcd_grid(int nwork) {
     const int per = (nwork + kNumXcd - 1) / kNumXcd;

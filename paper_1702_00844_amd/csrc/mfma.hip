@@ -160,9 +160,8 @@ __global__ __launch_bounds__(256, 2) void kernel(Job job, int nwork) {
     __shared__ __attribute__((aligned(16))) uint8_t lds[2 * Geo<KIND, SB>::STAGE_BYTES];
     const int w = xcd_remap(blockIdx.x, nwork);
     if (w < 0) return;
-    const int c = w / job.npairs;
-    int bi, bj;
-    pair_decode(w - c * job.npairs, bi, bj);
+    int c, bi, bj;
+    unit_decode(job, w, c, bi, bj);
     unit<KIND, SB, OUT>(job, c, bi, bj, lds);
 }
 
@@ -179,7 +178,7 @@ __global__ __launch_bounds__(256, 2) void kernel_batch(const Job *__restrict__ j
 
 template <int KIND, int SB, typename OUT>
 hipError_t launch_t(const Job &job, hipStream_t stream) {
-    const int nwork = job.C * job.npairs;
+    const int nwork = job_units(job);
     hipLaunchKernelGGL((kernel<KIND, SB, OUT>), dim3(xcd_grid(nwork)), dim3(256), 0, stream, job, nwork);
     return hipGetLastError();
 }

@@ -425,9 +425,8 @@ __global__ __launch_bounds__(256 * TS, 2 / TS) void kernel(Job job, int nwork) {
     __shared__ __attribute__((aligned(16))) uint8_t lds[2 * stage<TS>()];
     const int w = xcd_remap(blockIdx.x, nwork);
     if (w < 0) return;
-    const int c = w / job.npairs;
-    int bi, bj;
-    pair_decode(w - c * job.npairs, bi, bj);
+    int c, bi, bj;
+    unit_decode(job, w, c, bi, bj);
     unit<TS, G3>(job, c, bi, bj, lds);
 }
 
@@ -448,7 +447,7 @@ __global__ __launch_bounds__(256 * TS, 2 / TS) void kernel_batch(const Job *__re
 namespace mfma16 {
 template <int TS, bool G3>
 hipError_t launch_t(const Job &job, hipStream_t stream) {
-    const int nwork = job.C * job.npairs;
+    const int nwork = job_units(job);
     hipLaunchKernelGGL((kernel<TS, G3>), dim3(xcd_grid(nwork)), dim3(256 * TS), 0, stream, job, nwork);
     return hipGetLastError();
 }

@@ -185,9 +185,8 @@ __global__ __launch_bounds__(64 * TS) void kernel(Job job, int nwork) {
     __shared__ Stage<TC> st;
     const int w = xcd_remap(blockIdx.x, nwork);
     if (w < 0) return;
-    const int c = w / job.npairs;
-    int bi, bj;
-    pair_decode(w - c * job.npairs, bi, bj);
+    int c, bi, bj;
+    unit_decode(job, w, c, bi, bj);
     unit<TS, TC>(job, c, bi, bj, st);
 }
 
@@ -205,7 +204,7 @@ __global__ __launch_bounds__(64 * TS) void kernel_batch(const Job *__restrict__ 
 
 template <int TS, int TC>
 hipError_t launch_t(const Job &job, hipStream_t stream) {
-    const int nwork = job.C * job.npairs;
+    const int nwork = job_units(job);
     hipLaunchKernelGGL((kernel<TS, TC>), dim3(xcd_grid(nwork)), dim3(64 * TS), 0, stream, job, nwork);
     return hipGetLastError();
 }

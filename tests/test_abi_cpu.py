@@ -273,3 +273,19 @@ def test_pfb_validation():
     assert lib.xc_pfb_run(None, VP(64), VP(64), None, VP(128), None) == 1
     assert lib.xc_pfb_info(None, None, None) == 1
     lib.xc_pfb_destroy(None)
+
+
+def test_split_workspace_and_validation():
+    """Pieces of ceil(T / n_split) steps, none empty; errors before any launch."""
+    lib = _lib.load()
+    elems = 16 * (8 * 9 // 2) * 4
+    for T, n, pieces in [(10, 4, 4), (10, 6, 5), (10, 1, 1), (10, 50, 10), (1, 8, 1), (256, 16, 16), (100, 7, 7)]:
+        assert lib.xc_correlate_split_bytes(8, 2, 16, T, n) == pieces * elems * 8, (T, n)
+    assert lib.xc_correlate_split_bytes(8, 2, 16, 10, 0) == -1
+    assert lib.xc_correlate_split_bytes(8, 3, 16, 10, 2) == -1
+    # n_split < 1, null work, too small a workspace, misaligned work: rejected before anything is enqueued
+    args = (None, VP(1 << 20), 0, 8, 2, 16, 10, VP(2 << 20))
+    assert lib.xc_correlate_split(*args, 0, 0, 0, VP(4 << 20), 1 << 20, None) == 1
+    assert lib.xc_correlate_split(*args, 0, 0, 4, None, 1 << 20, None) == 1
+    assert lib.xc_correlate_split(*args, 0, 0, 4, VP(4 << 20), 16, None) == 1
+    assert lib.xc_correlate_split(*args, 0, 0, 4, VP((4 << 20) + 8), 1 << 20, None) == 1

@@ -312,3 +312,41 @@ def test_int32_bound_at_the_longest_integration():
         got = gpu_vis_numpy(xe.correlate(x, config=cfg))
         assert np.all(got[..., 0] == 2 * 127 * 127 * T) and np.all(got[..., 1] == 0)
     assert 2 * 127 * 127 * T <= 2 ** 31 - 1
+
+
+SPLIT_CFGS = [("cf32", dict(kernel=xe.XC_KERNEL_MFMA, block=64, time_split=2)),
+              ("cf32", dict(kernel=xe.XC_KERNEL_MFMA, block=64, time_split=1, product=xe.XC_PRODUCT_FOUR)),
+              ("cf32", dict(kernel=xe.XC_KERNEL_MFMA, block=32)),
+              ("cf32", dict(kernel=xe.XC_KERNEL_VALU)),
+              ("ci8", None),
+              ("ci8", dict(kernel=xe.XC_KERNEL_MFMA, block=64, staging=xe.XC_STAGING_REGISTERS)),
+              ("ci8", dict(kernel=xe.XC_KERNEL_MFMA, block=32)),
+              ("cf16", None)]
+
+
+@pytest.mark.parametrize("kind,cfg", SPLIT_CFGS, ids=["f32_b64ts2", "f32_b64ts1p4", "f32_b32", "f32_valu", "i8_lds",
+                                                      "i8_regs", "i8_b32", "f16_lds"])
+@pytest.mark.parametrize("split", [2, 7, 1000])
+def test_split_integration(kind, cfg, split):
+    """The integration cut into pieces over workgroups, partial sums added in
+    a fixed order: int8 bit-exact, 16-bit exact on integer samples, FP32
+    within 1e-5; accumulation adds over time exactly as without the split."""
+    S, C, T = 70, 3, 101
+    if kind == "cf32":
+        x1, x2 = _cf32(S, C, T, seed=61), _cf32(S, C, T, seed=62)
+    else:
+        x1 = inputs.ci8_gaussian(C, T, S, seed=61, device=DEV)
+        x2 = inputs.ci8_gaussian(C, T, S, seed=62, device=DEV)
+        if kind == "cf16":
+            x1, x2 = x1.to(torch.float16), x2.to(torch.float16)
+    v = xe.correlate(x1, config=cfg, split=split)
+    xe.correlate(x2, out=v, accumulate=True, config=cfg, split=split)
+    torch.cuda.synchronize()
+    src = torch.cat([x1, x2], dim=1)
+    got = gpu_vis_numpy(v)
+    if kind == "cf32":
+        assert rel_err(got, oracle_vis(src)) <= FP32_TOL
+        assert_hermitian_autos(got, S)
+    else:
+        ref = oracle_vis(src.to(torch.int8) if kind == "cf16" else src)
+        assert np.array_equal(got, ref if kind == "ci8" else ref[..., 0] + 1j * ref[..., 1])
