@@ -415,7 +415,7 @@ class _DevicePointer:
 def device_tensor(ptr: int, shape, dtype: torch.dtype, device="cuda") -> torch.Tensor:
     """A torch view of library-owned device memory (stream ring slots, resident
     integrations); the memory stays owned by the library."""
-    typestr = {torch.int8: "|i1", torch.int32: "<i4", torch.float32: "<f4", torch.float16: "<f2",
+    typestr = {torch.int8: "|i1", torch.int16: "<i2", torch.int32: "<i4", torch.float32: "<f4", torch.float16: "<f2",
                torch.complex64: "<c8"}[dtype]
     return torch.as_tensor(_DevicePointer(ptr, shape, typestr), device=device)
 

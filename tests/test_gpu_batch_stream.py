@@ -114,20 +114,26 @@ def test_autotune_and_cache(tmp_path):
 
 
 # block_times 24: the int8 kernel's 32-step chunks straddle the ring slots of a fold
-@pytest.mark.parametrize("kind,bt", [("ci8", 32), ("ci8", 24), ("cf32", 32)])
+@pytest.mark.parametrize("kind,bt", [("ci8", 32), ("ci8", 24), ("cf32", 32), ("cf16", 32), ("cbf16", 24)])
 def test_stream_integrations_match_oracle(kind, bt):
     S, C, bpi, k = 20, 3, 6, 2
     n_int = 2
     srv = xe.Server()
-    in_type = xe.XC_IN_CI8 if kind == "ci8" else xe.XC_IN_CF32
+    in_type = {"ci8": xe.XC_IN_CI8, "cf32": xe.XC_IN_CF32, "cf16": xe.XC_IN_CF16, "cbf16": xe.XC_IN_CBF16}[kind]
     acc = xe.XC_OUT_CI32 if kind == "ci8" else xe.XC_OUT_CF32
     d = xe.Server.desc(S, C, bt, bpi, blocks_per_fold=k, ring_blocks=4, in_type=in_type, acc_type=acc,
                        block_period_s=0.001)
     sid = srv.open(d)
     blocks = []
     for b in range(bpi * n_int):
-        blk = (inputs.ci8_gaussian(C, bt, S, seed=500 + b, device=DEV) if kind == "ci8"
-               else inputs.cn_gaussian(C, bt, S, seed=500 + b, device=DEV))
+        if kind == "cf32":
+            blk = inputs.cn_gaussian(C, bt, S, seed=500 + b, device=DEV)
+        else:
+            # 16-bit samples hold the int8 values exactly, and every partial sum
+            # (at most 192 x 2 x 127^2 < 2^24) is exact in float32
+            blk = inputs.ci8_gaussian(C, bt, S, seed=500 + b, device=DEV)
+            if kind != "ci8":
+                blk = blk.to(torch.float16 if kind == "cf16" else torch.bfloat16)
         blocks.append(blk)
         while True:
             try:
@@ -137,8 +143,10 @@ def test_stream_integrations_match_oracle(kind, bt):
                 assert e.status_name == "XC_ERR_BACKPRESSURE"
                 time.sleep(0.001)
         if kind == "ci8":
-            slot = xe.device_tensor(ptr, (C, bt, S, 2, 2), torch.int8)
-            slot.copy_(blk)
+            xe.device_tensor(ptr, (C, bt, S, 2, 2), torch.int8).copy_(blk)
+        elif kind != "cf32":
+            # 16-bit samples copied bit for bit (there is no bfloat16 array-interface type)
+            xe.device_tensor(ptr, (C, bt, S, 2, 2), torch.int16).copy_(blk.view(torch.int16))
         else:
             slot = xe.device_tensor(ptr, (C, bt, S, 2 * 2), torch.float32)
             slot.copy_(torch.view_as_real(blk).reshape(C, bt, S, 4))
@@ -150,9 +158,12 @@ def test_stream_integrations_match_oracle(kind, bt):
             assert seq == (b + 1) // bpi - 1
             shape = xe.vis_shape(C, S, acc)
             got = xe.device_tensor(vptr, shape, torch.int32 if kind == "ci8" else torch.complex64)
-            ref = oracle_vis(torch.cat(blocks[b + 1 - bpi:b + 1], dim=1))
+            window = torch.cat(blocks[b + 1 - bpi:b + 1], dim=1)
+            ref = oracle_vis(window.to(torch.int8) if kind in ("cf16", "cbf16") else window)
             if kind == "ci8":
                 assert np.array_equal(gpu_vis_numpy(got), ref)
+            elif kind in ("cf16", "cbf16"):
+                assert np.array_equal(gpu_vis_numpy(got), ref[..., 0] + 1j * ref[..., 1])
             else:
                 assert rel_err(gpu_vis_numpy(got), ref) <= 1e-5
     st = srv.stats(sid)
