@@ -143,8 +143,9 @@ int64_t xc_vis_bytes(xc_out_type out_type, int32_t n_stations, int32_t n_pol,
  *   XC_ERR_OVERFLOW_RISK XC_OUT_CI32 and n_times > XC_CI32_MAX_TIMES;
  *   XC_ERR_HIP          launch failure.
  * If the environment variable XC_CHECK=1 is set, XC_IN_CI8 input is scanned
- * for the value -128 first (synchronously) and rejected with
- * XC_ERR_INVALID_ARG.
+ * for the value -128 first and rejected with XC_ERR_INVALID_ARG; that debug
+ * scan synchronises the stream and allocates (and frees) a 4-byte device
+ * flag.  Otherwise the call allocates nothing and returns without waiting.
  */
 xc_status xc_correlate(const void *samples, xc_in_type in_type, int32_t n_stations,
                        int32_t n_pol, int32_t n_channels, int32_t n_times, void *vis,
