@@ -378,7 +378,12 @@ xc_status xc_stream_commit(xc_server *srv, int32_t stream_id, uint64_t arrival_n
 xc_status xc_stream_latest(xc_server *srv, int32_t stream_id, const void **vis,
                            int64_t *sequence);
 
-/* Waits for all enqueued folds of the stream, then fills *stats. */
+/* Waits for all enqueued folds of the stream, then fills *stats.  The wait
+ * holds the server's lock, so calls on the server's other streams wait for
+ * it too.  Every committed block leaves a latency record (its arrival time,
+ * and one completion record per fold) that is kept until
+ * xc_stream_reset_stats or xc_stream_close: a stream that runs for long
+ * should read and reset its statistics periodically. */
 xc_status xc_stream_stats(xc_server *srv, int32_t stream_id, xc_latency_stats *stats);
 
 /* Waits for all enqueued folds of the stream, then forgets their latency
