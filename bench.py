@@ -491,6 +491,10 @@ def ingest_bench(xe, inputs, torch, dev, stream, reps=5):
             tr_ms = timed(lambda: xe.transpose_to_time_major(x_sm, out=dev_buf, stream=stream), 20)
             r["device_transpose_ms"] = round(tr_ms, 4)
             r["device_transpose_GB/s"] = round(2 * nbytes / (tr_ms * 1e-3) / 1e9, 1)
+            # device-resident station-major block correlated directly (corner turn in the LDS copies)
+            sm_ms = timed(lambda: xe.correlate_into(x_sm, o, stream=stream, layout=xe.XC_LAYOUT_STATION_MAJOR), 20)
+            r["station_major_kernel_ms"] = round(sm_ms, 4)
+            r["station_major_kernel_TFLOP/s"] = round(flops / sm_ms / 1e9, 1)
             del x_sm
             # the kernel while a 1 GiB pinned copy runs on another stream
             big_h = torch.empty(1 << 30, dtype=torch.uint8).pin_memory()

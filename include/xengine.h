@@ -217,6 +217,24 @@ xc_status xc_correlate_split(const xc_config *cfg, const void *samples, xc_in_ty
                              int32_t n_pol, int32_t n_channels, int32_t n_times, void *vis, xc_out_type out_type,
                              int32_t accumulate, int32_t n_split, void *work, int64_t work_bytes, void *stream);
 
+/*
+ * The same correlation from station-major samples, samples[C][S][T][P]
+ * (device; each station's time series contiguous, the layout a station's
+ * receiver produces; Section 4.4 discusses both layouts).  The corner turn to
+ * time-major order happens in the copies into LDS, so there is no transposed
+ * copy in device memory: the kernel's LDS image, and hence the result bit for
+ * bit, are those of xc_correlate_config on the time-major block.  Complex
+ * float32 samples, on the 64-station matrix-core kernel (kernel AUTO or
+ * XC_KERNEL_MFMA, block 0 or 64; cfg may set its time split and product form)
+ * or on the vector-ALU kernel (XC_KERNEL_VALU, whose loads into registers do
+ * the corner turn the same way).  Errors as for xc_correlate_config, and
+ * XC_ERR_UNSUPPORTED for another sample type or the 32-station matrix-core
+ * kernel.  Allocates nothing.
+ */
+xc_status xc_correlate_station_major(const xc_config *cfg, const void *samples, xc_in_type in_type,
+                                     int32_t n_stations, int32_t n_pol, int32_t n_channels, int32_t n_times,
+                                     void *vis, xc_out_type out_type, int32_t accumulate, void *stream);
+
 /* ------------------------------------------------------------------------ */
 /* Cost model (Section 2, Table 1; Section 3.6 bound-and-bottleneck).        */
 

@@ -139,12 +139,30 @@ def resolve_config(x_shape_type, out_type=XC_OUT_CF32, config=None) -> dict:
 
 
 def correlate_into(x: torch.Tensor, out: torch.Tensor, accumulate: bool = False, stream=None,
-                   config=None, split: int = 1) -> torch.Tensor:
+                   config=None, split: int = 1, layout: int = XC_LAYOUT_TIME_MAJOR) -> torch.Tensor:
     """out (+)= correlation of x; out dtype complex64 (XC_OUT_CF32) or int32 (XC_OUT_CI32).
     split > 1 cuts the integration into that many pieces, one set of
     workgroups each, and adds their partial sums in a fixed order (for
     workloads with few channels and stations); the workspace is a torch
-    allocation on the device."""
+    allocation on the device.  layout = XC_LAYOUT_STATION_MAJOR takes
+    complex64 x[C, S, T, 2] (each station's series contiguous) and corner-turns
+    it in the kernel's copies into LDS (64-station matrix-core kernel)."""
+    if layout == XC_LAYOUT_STATION_MAJOR:
+        in_type, C, S, T, P = in_type_of(x)      # dims 1 and 2 are (S, T) here
+        if split > 1:
+            raise ValueError("station-major input is not combined with a split integration")
+        out_type = XC_OUT_CI32 if out.dtype == torch.int32 else XC_OUT_CF32
+        if tuple(out.shape) != vis_shape(C, S, out_type, P):
+            raise ValueError(f"out has shape {tuple(out.shape)}, expected {vis_shape(C, S, out_type, P)}")
+        _require_device(x, out)
+        cfg = _config(config)
+        st = lib().xc_correlate_station_major(ctypes.byref(cfg) if cfg else None, ctypes.c_void_p(x.data_ptr()),
+                                              in_type, S, P, C, T, ctypes.c_void_p(out.data_ptr()), out_type,
+                                              1 if accumulate else 0, _stream_ptr(stream))
+        _lib.check(st)
+        return out
+    if layout != XC_LAYOUT_TIME_MAJOR:
+        raise ValueError(f"unknown layout {layout}")
     in_type, C, T, S, P = in_type_of(x)
     out_type = XC_OUT_CI32 if out.dtype == torch.int32 else XC_OUT_CF32
     if out.dtype not in (torch.int32, torch.complex64):
@@ -173,22 +191,26 @@ def correlate_into(x: torch.Tensor, out: torch.Tensor, accumulate: bool = False,
 
 
 def correlate(x: torch.Tensor, out: torch.Tensor | None = None, accumulate: bool = False, stream=None,
-              config=None, out_type: int | None = None, split: int = 1) -> torch.Tensor:
+              config=None, out_type: int | None = None, split: int = 1,
+              layout: int = XC_LAYOUT_TIME_MAJOR) -> torch.Tensor:
     """Visibilities of samples x.
 
     x: complex64 [C, T, S, 2], or int8 / float16 / bfloat16 [C, T, S, 2, 2]
+    (layout = XC_LAYOUT_STATION_MAJOR: complex64 [C, S, T, 2])
     returns complex64 [C, B, 2, 2] (int8 input: int32 [C, B, 2, 2, 2] unless
     out_type = XC_OUT_CF32).  The paper's correlation[b][c][p][q] order is
     ``out.permute(1, 0, 2, 3)``.
     """
     in_type, C, T, S, P = in_type_of(x)
+    if layout == XC_LAYOUT_STATION_MAJOR:
+        S, T = T, S
     if out is None:
         if out_type is None:
             out_type = XC_OUT_CI32 if in_type == XC_IN_CI8 else XC_OUT_CF32
         dtype = torch.int32 if out_type == XC_OUT_CI32 else torch.complex64
         alloc = torch.zeros if accumulate else torch.empty
         out = alloc(vis_shape(C, S, out_type, P), dtype=dtype, device=x.device)
-    return correlate_into(x, out, accumulate=accumulate, stream=stream, config=config, split=split)
+    return correlate_into(x, out, accumulate=accumulate, stream=stream, config=config, split=split, layout=layout)
 
 
 def transpose_to_time_major(x: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:

@@ -67,6 +67,8 @@ SIGNATURES = {
     "xc_correlate_split_bytes": (c_i64, [c_i32, c_i32, c_i32, c_i32, c_i32]),
     "xc_correlate_split": (c_i32, [ctypes.POINTER(XcConfig), c_vp, c_i32, c_i32, c_i32, c_i32, c_i32, c_vp, c_i32,
                                    c_i32, c_i32, c_vp, c_i64, c_vp]),
+    "xc_correlate_station_major": (c_i32, [ctypes.POINTER(XcConfig), c_vp, c_i32, c_i32, c_i32, c_i32, c_i32,
+                                           c_vp, c_i32, c_i32, c_vp]),
     "xc_tile_cost": (c_i32, [c_i32, c_i32, ctypes.POINTER(c_i64), ctypes.POINTER(c_i64),
                              ctypes.POINTER(c_i64)]),
     "xc_perf_max": (c_f64, [c_f64, c_f64, c_f64]),

@@ -256,6 +256,7 @@ Job make_job(const void *samples, void *vis, int S, int C, int T, int block, int
     j.tpiece = T;
     j.xpiece = 0;
     j.vpiece = 0;
+    j.sstride = 0;
     return j;
 }
 
@@ -384,6 +385,32 @@ xc_status xc_correlate_split(const xc_config *cfg, const void *samples, xc_in_ty
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_error(e, "piece-sum launch");
     return XC_OK;
+}
+
+xc_status xc_correlate_station_major(const xc_config *cfg, const void *samples, xc_in_type in_type,
+                                     int32_t n_stations, int32_t n_pol, int32_t n_channels, int32_t n_times,
+                                     void *vis, xc_out_type out_type, int32_t accumulate, void *stream) {
+    if (in_type != XC_IN_CF32)
+        return set_error(XC_ERR_UNSUPPORTED, "station-major input: complex float32 samples only");
+    // the kernels whose sample loads take either layout: the 64-station
+    // matrix-core kernel (copies into LDS) and the vector-ALU kernel
+    xc_config c = cfg ? *cfg : xc_config{};
+    if (c.kernel == XC_KERNEL_AUTO) c.kernel = XC_KERNEL_MFMA;
+    if (c.kernel == XC_KERNEL_MFMA && c.block != 0 && c.block != 64)
+        return set_error(XC_ERR_UNSUPPORTED, "station-major input: the matrix-core kernel on 64-station blocks only");
+    if (c.kernel == XC_KERNEL_MFMA) c.block = 64;
+    Plan plan;
+    xc_status st = resolve(&c, in_type, out_type, n_stations, n_pol, n_channels, n_times, &plan);
+    if (st != XC_OK) return st;
+    if (!(plan.kernel == XC_KERNEL_VALU || (plan.kernel == XC_KERNEL_MFMA && plan.block == 64)))
+        return set_error(XC_ERR_UNSUPPORTED, "station-major input: the matrix-core kernel on 64-station blocks only");
+    if (!samples || !vis) return set_error(XC_ERR_INVALID_ARG, "null samples or vis pointer");
+    if (!aligned16(samples) || !aligned16(vis))
+        return set_error(XC_ERR_INVALID_ARG, "samples and vis must be 16-byte aligned");
+    if (accumulate != 0 && accumulate != 1) return set_error(XC_ERR_INVALID_ARG, "accumulate must be 0 or 1");
+    Job job = make_job(samples, vis, n_stations, n_channels, n_times, plan.block, accumulate);
+    job.sstride = n_times;
+    return launch_plan(plan, in_type, out_type, job, static_cast<hipStream_t>(stream));
 }
 
 xc_status xc_correlate(const void *samples, xc_in_type in_type, int32_t n_stations, int32_t n_pol,

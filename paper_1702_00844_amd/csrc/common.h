@@ -37,6 +37,12 @@ struct Job {
     int32_t tpiece;
     int64_t xpiece;
     int64_t vpiece;
+    // Station-major input (x[C][S][T][2]: each station's time series
+    // contiguous): station-samples from one station's series to the next;
+    // 0 for the time-major layout.  Read by the 16 x 16 complex-float32
+    // matrix-core kernel (its copies into LDS do the corner turn) and the
+    // vector-ALU kernel (its loads into registers do).
+    int64_t sstride;
 };
 
 // Index (in station-samples, i.e. units of one station's dual-pol sample) of

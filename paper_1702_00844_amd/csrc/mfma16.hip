@@ -223,10 +223,23 @@ __device__ __forceinline__ void wave_unit(const Job &job, int c, int bi, int bj,
     const uint32_t dst0 = lds_addr(lds) + trow0 * PITCH + blk * BROW;
     const uint8_t *x8 = static_cast<const uint8_t *>(job.x);
     const int T = job.T;
+    // station-major input: this lane's station series of channel c
+    const uint8_t *srow = x8 + ((size_t)c * job.cstride + (size_t)stc * job.sstride) * 16;
     auto issue = [&](int ch) {
         const int t0 = ch * KT;
         const uint32_t dst = dst0 + (ch & 1) * STAGE;
-        if (t0 + KT <= T && rows_contiguous(job, t0, KT)) {
+        if (job.sstride) {
+            // the corner turn happens here: lane l copies station l's sample
+            // of the time row, so the LDS image is the same as for time-major
+            // input (a 128-byte line of a station's series is shared by the
+            // copies of 8 consecutive time rows)
+#pragma unroll
+            for (int k = 0; k < NCOPY; ++k) {
+                const int t = t0 + trow0 + k * TSTEP;
+                dma16(t < T ? static_cast<const void *>(srow + (size_t)t * 16) : static_cast<const void *>(g_zero16),
+                      dst + k * TSTEP * PITCH);
+            }
+        } else if (t0 + KT <= T && rows_contiguous(job, t0, KT)) {
             const uint8_t *src = x8 + row_offset(job, c, t0) * 16 + off;
 #pragma unroll
             for (int k = 0; k < NCOPY; ++k) dma16(src + k * step, dst + k * TSTEP * PITCH);

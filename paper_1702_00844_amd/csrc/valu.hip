@@ -85,7 +85,11 @@ __device__ __forceinline__ void unit(const Job &job, int c, int bi, int bj, Stag
             const int s = e % (2 * SB);
             const int station = s < SB ? I0 + s : J0 + s - SB;
             const bool ok = (e < NELEM) && (t0 + t < T) && station < S && !(diag && s >= SB);
-            pre[k] = ok ? x[row_offset(job, c, t0 + t) + station] : make_float4(0.f, 0.f, 0.f, 0.f);
+            // time-major: all stations of a time step together; station-major
+            // (sstride != 0): each station's series together
+            const size_t e_x = job.sstride ? (size_t)c * job.cstride + (size_t)station * job.sstride + (t0 + t)
+                                           : row_offset(job, c, t0 + t) + station;
+            pre[k] = ok ? x[e_x] : make_float4(0.f, 0.f, 0.f, 0.f);
         }
     };
     auto lstore = [&](int buf) {

@@ -289,3 +289,32 @@ def test_split_workspace_and_validation():
     assert lib.xc_correlate_split(*args, 0, 0, 4, None, 1 << 20, None) == 1
     assert lib.xc_correlate_split(*args, 0, 0, 4, VP(4 << 20), 16, None) == 1
     assert lib.xc_correlate_split(*args, 0, 0, 4, VP((4 << 20) + 8), 1 << 20, None) == 1
+
+
+def test_station_major_validation():
+    """The station-major entry point takes complex float32 on the 64-station
+    matrix-core kernel or the vector-ALU kernel, and rejects everything else
+    before any launch."""
+    lib = _lib.load()
+    X, V = VP(1 << 20), VP(2 << 20)
+
+    def call(cfg, in_type=0, S=70, P=2, C=3, T=50, x=X, v=V, out_type=0, acc=0):
+        return lib.xc_correlate_station_major(ctypes.byref(cfg) if cfg else None, x, in_type, S, P, C, T, v,
+                                              out_type, acc, None)
+
+    unsupported, invalid = 2, 1
+    assert call(None, in_type=xe.XC_IN_CI8, out_type=xe.XC_OUT_CI32) == unsupported
+    assert call(None, in_type=xe.XC_IN_CF16) == unsupported
+    assert call(_lib.XcConfig(xe.XC_KERNEL_VALU, 0, 0, 0, 0, 0), x=None) == invalid   # VALU takes it
+    assert call(_lib.XcConfig(xe.XC_KERNEL_MFMA, 32, 0, 0, 0, 0)) == unsupported
+    assert call(None, P=3) == unsupported
+    assert call(None, x=None) == invalid
+    assert call(None, v=VP((2 << 20) + 8)) == invalid
+    assert call(None, acc=2) == invalid
+    assert call(None, T=0) == invalid
+    # what it resolves to: the 64-station matrix-core kernel, at any station count
+    for S in (1, 8, 48, 70):
+        r = _lib.XcConfig()
+        assert lib.xc_resolve_config(ctypes.byref(_lib.XcConfig(xe.XC_KERNEL_MFMA, 64, 0, 0, 0, 0)), 0, 0, S, 2, 3,
+                                     50, ctypes.byref(r)) == 0
+        assert (r.kernel, r.block) == (xe.XC_KERNEL_MFMA, 64)

@@ -103,3 +103,42 @@ def test_ingest_rejects_bad_host_tensors():
     with pytest.raises(ValueError):
         ing.run(x.cpu().to(torch.complex128))       # wrong dtype
     ing.close()
+
+
+@pytest.mark.parametrize("shape", [(3, 70, 100), (2, 64, 768), (1, 1, 1), (4, 130, 33), (2, 8, 256), (1, 129, 200)],
+                         ids=["S70_T100", "S64_T768", "S1_T1", "S130_T33", "S8_T256", "S129_T200"])
+@pytest.mark.parametrize("config", [None, {"time_split": 1}, {"time_split": 2, "product": xe.XC_PRODUCT_FOUR},
+                                    {"time_split": 1, "product": xe.XC_PRODUCT_FOUR},
+                                    {"kernel": xe.XC_KERNEL_VALU, "time_chunk": 32, "time_split": 8},
+                                    {"kernel": xe.XC_KERNEL_VALU, "time_chunk": 16, "time_split": 1}],
+                         ids=["auto", "ts1", "ts2_p4", "ts1_p4", "valu_ts8", "valu_ts1"])
+def test_station_major_kernel_matches_time_major(shape, config):
+    """The station-major kernels corner-turn in their sample loads (copies into
+    LDS, or loads into registers): what they stage, and so their results bit
+    for bit, are those of the time-major kernel with the same configuration on
+    the transposed block."""
+    C, S, T = shape
+    x = _samples("cf32", C, T, S, seed=900 + S + T)
+    cfg = dict(config or {})
+    if cfg.get("kernel") != xe.XC_KERNEL_VALU:
+        cfg = {"kernel": xe.XC_KERNEL_MFMA, "block": 64, **cfg}
+    ref = xe.correlate(x, config=cfg)
+    got = xe.correlate(_station_major(x), config=config, layout=SM)
+    assert torch.equal(_bits(got), _bits(ref))
+
+
+def test_station_major_against_oracle_with_accumulation():
+    C, S, T = 3, 70, 300
+    x1 = _samples("cf32", C, T, S, seed=931)
+    x2 = _samples("cf32", C, 77, S, seed=932)
+    out = xe.correlate(_station_major(x1), layout=SM)
+    assert rel_err(gpu_vis_numpy(out), oracle_vis(x1)) <= 1e-5
+    xe.correlate(_station_major(x2), out=out, accumulate=True, layout=SM)
+    assert rel_err(gpu_vis_numpy(out), oracle_vis(torch.cat([x1, x2], dim=1))) <= 1e-5
+
+
+def test_station_major_rejects_other_sample_types():
+    xi = _station_major(_samples("ci8", 2, 40, 12, seed=933))
+    with pytest.raises(xe.XengineError) as e:
+        xe.correlate(xi, layout=SM)
+    assert e.value.status_name == "XC_ERR_UNSUPPORTED"
