@@ -462,6 +462,9 @@ xc_status xc_ingest_info(const xc_ingest *ingest, int32_t *channels_per_group, i
  * asynchronous DMA) into vis (device, V[C][B][P][P] of out_type, as for
  * xc_correlate) on `stream`, one group after another: copy to a staging slot,
  * transpose (station-major input), correlate into the group's channels of V.
+ * Station-major complex float32 on the 64-station matrix-core kernel or the
+ * vector-ALU kernel skips the transpose: those kernels read the staged group
+ * as it is (as xc_correlate_station_major does).
  * overlap = 1: copies run on the plan's copy stream, each group's copy
  * overlapping the previous group's correlation; overlap = 0: copies run on
  * `stream`, in order with the computation (synchronous I/O).  The results are

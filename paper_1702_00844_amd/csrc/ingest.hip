@@ -171,6 +171,11 @@ xc_status xc_ingest_run(xc_ingest *g, const xc_config *cfg, const void *host_sam
     xc_status st = resolve(cfg, g->in_type, out_type, g->S, 2, g->group, g->T, &plan);
     if (st != XC_OK) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
+    // station-major complex float32 on a kernel whose sample loads corner-turn
+    // (64-station matrix cores, vector ALU) is correlated as staged, without
+    // the transpose
+    const bool direct = g->layout == XC_LAYOUT_STATION_MAJOR && g->in_type == XC_IN_CF32 &&
+                        (plan.kernel == XC_KERNEL_VALU || (plan.kernel == XC_KERNEL_MFMA && plan.block == 64));
     const size_t vis_chan = (size_t)g->S * (g->S + 1) / 2 * 4 * 8;   // bytes of one channel's V
     const uint8_t *host = static_cast<const uint8_t *>(host_samples);
     const int ngroups = (g->C + g->group - 1) / g->group;
@@ -190,13 +195,14 @@ xc_status xc_ingest_run(xc_ingest *g, const xc_config *cfg, const void *host_sam
             if (e == hipSuccess) e = hipStreamWaitEvent(s, g->copied[slot], 0);
         }
         const void *src = g->raw[slot];
-        if (e == hipSuccess && g->layout == XC_LAYOUT_STATION_MAJOR) {
+        if (e == hipSuccess && g->layout == XC_LAYOUT_STATION_MAJOR && !direct) {
             e = launch_transpose(g->raw[slot], g->tmaj[slot], g->in_type, g->S, cg, g->T, s);
             src = g->tmaj[slot];
         }
         if (e != hipSuccess) break;
-        const Job job = make_job(src, static_cast<uint8_t *>(vis) + (size_t)c0 * vis_chan, g->S, cg, g->T,
-                                 plan.block, accumulate);
+        Job job = make_job(src, static_cast<uint8_t *>(vis) + (size_t)c0 * vis_chan, g->S, cg, g->T, plan.block,
+                           accumulate);
+        if (direct) job.sstride = g->T;
         st = launch_plan(plan, g->in_type, out_type, job, s);
         if (st != XC_OK) return st;
         e = hipEventRecord(g->consumed[slot], s);
