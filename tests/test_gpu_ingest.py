@@ -60,6 +60,24 @@ def test_ingest_matches_device_path(kind, layout, overlap, group):
     ing.close()
 
 
+@pytest.mark.parametrize("config", [{"kernel": xe.XC_KERNEL_VALU, "time_chunk": 16, "time_split": 4},
+                                    {"kernel": xe.XC_KERNEL_MFMA, "block": 32},
+                                    {"kernel": xe.XC_KERNEL_MFMA, "block": 64, "time_split": 1}],
+                         ids=["valu_direct", "mfma32_transposed", "mfma64_direct"])
+def test_ingest_station_major_fp32_kernels(config):
+    """Station-major complex float32 groups: the kernels that corner-turn in
+    their loads read the staged group directly, the 32-station matrix-core
+    kernel after the GPU transpose; every path gives the device result."""
+    C, T, S = 5, 70, 45
+    x = _samples("cf32", C, T, S, seed=29)
+    ref = gpu_vis_numpy(xe.correlate(x, config=config))
+    ing = xe.Ingest(xe.XC_IN_CF32, S, C, T, layout=SM, channels_per_group=2)
+    got = gpu_vis_numpy(ing.run(_station_major(x).cpu().pin_memory(), config=config))
+    torch.cuda.synchronize()
+    assert np.array_equal(got, ref)
+    ing.close()
+
+
 @pytest.mark.parametrize("layout", [TM, SM], ids=["time_major", "station_major"])
 def test_ingest_fp32_64_stations_against_oracle(layout):
     """The two-time-group FP32 kernel on 64-station blocks, fed group by group
