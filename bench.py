@@ -211,8 +211,8 @@ def main():
     ap.add_argument("--fengine-only", action="store_true", help="run only the filter-bank measurement")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this correlator build runs on one GPU; channels would shard across GPUs "
-                                   "(see the design notes) but no multi-GPU path is built"}))
+        print(json.dumps({"error": "this correlator runs on one GPU: channels would shard across GPUs, "
+                                   "but no multi-GPU path exists"}))
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration(args.steps)
