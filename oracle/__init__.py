@@ -2,10 +2,14 @@
 
 Plain CPU implementation of the correlation of van Nieuwpoort & Romein,
 "Correlating Radio Astronomy Signals with Many-Core Hardware", Section 2
-(correlation equation and the pseudo-code of Figure 2):
+(the correlation equation):
 
     V[c][b(i,j)][p][q] = sum_t x[c][t][i][p] * conj(x[c][t][j][q]),
-    0 <= i <= j < S,  b(i,j) = j(j+1)/2 + i.
+    0 <= i <= j < S,  b(i,j) = j(j+1)/2 + i,
+
+computed per channel as the Hermitian Gram matrix of the time steps' sample
+vectors (one rank-one update per time step, time ascending), whose 2x2
+blocks on and above the block diagonal are then packed into V.
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 ``bench.py`` may import this package.  It shares no code with the GPU library

@@ -1,8 +1,8 @@
 """Pure-Python twin of the oracle for tiny shapes -- TEST INFRASTRUCTURE ONLY.
 
 Follows the correlation equation of Section 2 with Python's own complex and
-integer numbers (no numpy arithmetic), enumerating pairs in the order of the
-pseudo-code of Figure 2.  Used to cross-check the C oracle on inputs of a few
+integer numbers (no numpy arithmetic): one explicit sum over time per
+(channel, station pair, polarisation pair).  Used to cross-check the C oracle on inputs of a few
 stations and times.
 """
 from __future__ import annotations
