@@ -700,7 +700,7 @@ def stream_bench(xe, inputs, torch, n_streams, k, n_blocks, S=512, C=4096, bt=25
             "fold_p99_ms": [round(p["fold_p99_ms"], 3) for p in per],
             "fold_max_ms": [round(p["fold_max_ms"], 3) for p in per],
             "blocks": [p["blocks"] for p in per], "folds": [p["folds"] for p in per],
-            "fold_misses": [p["misses"] for p in per], "block_misses": [p["block_misses"] for p in per],
+            "fold_misses": [p["fold_misses"] for p in per], "block_misses": [p["misses"] for p in per],
             "integrations": [p["integrations"] for p in per],
             "sustained_TFLOP/s": [round(p["tflops"], 1) for p in per], "producer_stalls": stalls,
             "realtime_TFLOP/s_needed_per_stream": round(xe.flops(S, C, bt) / P / 1e12, 1)}

@@ -189,6 +189,11 @@ int64_t xc_correlate_split_bytes(int32_t n_stations, int32_t n_pol, int32_t n_ch
  *                 64-station blocks take either (AUTO: LDS).
  *   product       xc_product.  AUTO: three products for complex-float32 on
  *                 64-station matrix-core blocks, four everywhere else.
+ *   tile_w,       VALU only: the register tile of one lane, tile_w stations of
+ *   tile_h        block I by tile_h stations of block J (Table 1): 4 x 4
+ *                 (default), 8 x 2, 4 x 2 or 2 x 2.  VALU time_split 8 needs a
+ *                 tile of 64 lanes per time group (4 x 4 or 8 x 2).
+ *                 Matrix-core kernels: 0.
  */
 typedef struct xc_config {
     int32_t kernel;
@@ -197,6 +202,8 @@ typedef struct xc_config {
     int32_t time_split;
     int32_t staging;
     int32_t product;
+    int32_t tile_w;
+    int32_t tile_h;
 } xc_config;
 
 /* Checks a configuration against a shape without touching the device.
@@ -257,6 +264,8 @@ double xc_flops(int32_t n_stations, int32_t n_channels, int32_t n_times);
 
 /* ------------------------------------------------------------------------ */
 /* Batches of sub-arrays in one launch per kernel configuration.            */
+/* Channels (and sub-arrays) are independent (Section 2), so uneven         */
+/* workloads combine into one list of work units.                           */
 
 typedef struct xc_subarray {
     const void *samples;   /* device, x[C][T][S][2] of the batch's in_type  */
@@ -269,23 +278,31 @@ typedef struct xc_subarray {
 typedef struct xc_batch_plan xc_batch_plan;
 
 /*
- * Builds a plan for correlating every item of `items`.  Items whose resolved
- * configurations are equal share one launch (with cfg == NULL every item runs
- * one time group per workgroup; the staging of int8 and 16-bit samples still
- * depends on the station count, so a batch has at most two launches).  A
- * launch runs one workgroup per (item, channel, block pair) unit of a device
- * work list cut into one range per XCD: whole channels are dealt to the XCD
- * with the least work so far (items by decreasing integration length), so a
- * channel's block pairs share an L2 and the longest units start first.  If
- * use_graph != 0 the launches are captured into a hipGraph on `stream` and
- * replayed by xc_batch_plan_run.  The plan owns its device work lists;
+ * Builds a plan for correlating every item of `items` (many sub-arrays and
+ * subbands of uneven size; channels are independent, Section 2, so the
+ * batch is one flat list of work units).  Items whose resolved
+ * configurations are equal share one launch.  Configuration: `cfg` for every
+ * item if not NULL; else, with `tune_cache` (a JSON-lines file path, as
+ * xc_autotune writes), each item takes the configuration tuned for its shape
+ * bucket (the tile size must be tuned per platform and shape, Section 2):
+ * the file is loaded first, and every bucket still missing is tuned here on
+ * the first item that falls in it (xc_autotune: timing that overwrites that
+ * item's vis and synchronises `stream`) and appended to the file -- unless
+ * accumulate == 1, in which case missing buckets take the default; with
+ * neither, every item runs the default with one time group per workgroup.
+ * A launch runs one workgroup per (item, channel, block pair) unit of a
+ * device work list cut into one range per XCD: whole channels are dealt to
+ * the XCD with the least work so far (items by decreasing integration
+ * length), so a channel's block pairs share an L2 and the longest units
+ * start first.  If use_graph != 0 the launches are captured into a hipGraph
+ * and replayed by xc_batch_plan_run.  The plan owns its device work lists;
  * xc_batch_plan_destroy frees them.  Pointers in `items` are baked into the
  * plan: they must stay valid while the plan is used.
  * Errors: as xc_correlate for each item; XC_ERR_OUT_OF_MEMORY.
  */
 xc_status xc_batch_plan_create(const xc_subarray *items, int32_t n_items, int32_t n_pol,
                                xc_in_type in_type, xc_out_type out_type, int32_t accumulate,
-                               const xc_config *cfg, int32_t use_graph, void *stream,
+                               const xc_config *cfg, const char *tune_cache, int32_t use_graph, void *stream,
                                xc_batch_plan **out);
 xc_status xc_batch_plan_run(xc_batch_plan *plan, void *stream);
 void xc_batch_plan_destroy(xc_batch_plan *plan);
@@ -305,60 +322,91 @@ int64_t xc_batch_worklist(const int32_t *n_stations, const int32_t *n_channels,
                           int32_t *units, int64_t capacity, int32_t *bounds);
 
 /* ------------------------------------------------------------------------ */
-/* Auto-tuning (tile sizes must be tuned per platform, Section 2).           */
+/* Auto-tuning (the tile size must be tuned per platform, Section 2; Table 1 */
+/* gives each register tile's flops, bytes and minimum registers).          */
 
 /*
- * Times every valid configuration for the shape on `stream` (synchronising),
- * using the caller's samples/vis buffers (vis is overwritten), and writes the
- * fastest to *best and its kernel time to *best_ms.  If cache_path is not
- * NULL the result is stored in that JSON-lines file and xc_correlate (AUTO)
- * uses it for the same shape in this process.
+ * Times every candidate configuration for the shape on `stream`
+ * (synchronising), using the caller's samples/vis buffers (vis is
+ * overwritten), and writes the fastest to *best and its kernel time to
+ * *best_ms.  The candidates (xc_tune_candidates) are the matrix-core block
+ * sizes, stagings, time groups and product forms, and the vector-ALU register
+ * tiles w x h with w, h in {2, 4, 8} (a tile and its mirror image cost the
+ * same; one is built) whose Table 1 register count plus the kernel's staging
+ * and address registers fits 256, each with every time chunk and time-group
+ * count.  The winner is kept for the shape's bucket (xc_tune_bucket), which
+ * xc_correlate (AUTO) and batch plans then use for every shape of that
+ * bucket in this process; if cache_path is not NULL it is also appended to
+ * that JSON-lines file.
  */
 xc_status xc_autotune(const void *samples, xc_in_type in_type, int32_t n_stations,
                       int32_t n_pol, int32_t n_channels, int32_t n_times, void *vis,
                       xc_out_type out_type, const char *cache_path, void *stream,
                       xc_config *best, double *best_ms);
 
-/* Loads a tuning cache written by xc_autotune (entries for other shapes are
- * kept).  Returns the number of entries loaded, or -1 if the file is
- * unreadable. */
+/* The candidate configurations of xc_autotune for a sample type, after the
+ * Table 1 pruning (host only).  Writes at most `capacity` of them to out (if
+ * not NULL); returns their number, or -1 for a bad type. */
+int64_t xc_tune_candidates(xc_in_type in_type, xc_config *out, int64_t capacity);
+
+/* The tuning bucket of a shape (host only): key = {in_type, out_type,
+ * ceil(S / 32), 1 if S fills whole copy granules of the direct-to-LDS kernel
+ * (4 int8 or 2 16-bit stations), ceil(log2 T), min(ceil(log2(C x
+ * 64-station block pairs)), 12)}.  Shapes with equal keys share a tuned
+ * configuration. */
+xc_status xc_tune_bucket(xc_in_type in_type, xc_out_type out_type, int32_t n_stations, int32_t n_channels,
+                         int32_t n_times, int32_t key[6]);
+
+/* Loads a tuning cache written by xc_autotune into the process's bucket
+ * table (entries already there for other buckets are kept; an entry that no
+ * longer resolves is skipped).  Returns the number of entries loaded, or -1
+ * if the file is unreadable. */
 int64_t xc_tune_cache_load(const char *cache_path);
 
 /* ------------------------------------------------------------------------ */
 /* Streaming: blocks arrive, partial integrations stay resident on device.   */
+/* The correlator is a real-time application whose input arrives as a       */
+/* stream (Section 1); an integration spans about one second of samples      */
+/* (Section 2) and is built from sub-intervals whose partial results are      */
+/* accumulated in memory (Section 4.5); copies and computation overlap        */
+/* (Section 4.4).                                                            */
 
 typedef struct xc_stream_desc {
     int32_t n_stations;
     int32_t n_pol;                  /* must be 2 */
     int32_t n_channels;
     int32_t block_times;            /* samples per arriving block                  */
-    int32_t blocks_per_integration; /* blocks folded into one published integration */
-    int32_t blocks_per_fold;        /* k: blocks correlated per fold launch         */
+    int32_t blocks_per_integration; /* blocks folded into one published integration
+                                       (a multiple of blocks_per_fold)             */
+    int32_t blocks_per_fold;        /* k: every channel is folded every k blocks    */
     int32_t ring_blocks;            /* device ring slots (>= 2 * blocks_per_fold)   */
     int32_t in_type;                /* xc_in_type                                    */
     int32_t acc_type;               /* xc_out_type of the resident accumulator       */
-    double block_period_s;          /* arrival period P; deadline = k * P            */
+    int32_t staggered;              /* 0: every k blocks, one fold of all channels;
+                                       1: the channels in k groups, one group folded
+                                       per committed block (its outstanding blocks),
+                                       every group at the end of an integration     */
+    double block_period_s;          /* arrival period P; block deadline = k * P      */
 } xc_stream_desc;
 
 /* Latency accounting.  A block's latency runs from its arrival to the
- * completion of the fold that integrates it; a fold's latency runs from the
- * arrival of its last block (when it can start) to its completion.  The
- * real-time deadline is on folds: a fold must complete before the next fold's
- * blocks have all arrived, i.e. within blocks_per_fold * block_period, so that
- * the stream keeps up with bounded queueing. */
+ * completion of the last fold that integrates it; the real-time deadline is
+ * per block: D = blocks_per_fold * block_period.  A fold's latency runs from
+ * the arrival of the block whose commit enqueued it to its completion, against
+ * the interval between fold launches (block_period when staggered, D
+ * otherwise). */
 typedef struct xc_latency_stats {
-    double p50_ms, p99_ms, max_ms;            /* per block: arrival -> fold completed     */
-    double fold_p50_ms, fold_p99_ms, fold_max_ms;  /* per fold: last arrival -> completed */
-    double deadline_ms;             /* blocks_per_fold * block_period (per fold)    */
+    double p50_ms, p99_ms, max_ms;  /* per block: arrival -> last fold completed    */
+    double deadline_ms;             /* per block: blocks_per_fold * block_period     */
     double tflops;                  /* algorithmic TFLOP/s over the measured span   */
     int64_t blocks;                 /* blocks whose latency was measured            */
+    int64_t misses;                 /* blocks whose latency exceeded deadline_ms    */
+    int64_t pending;                /* committed blocks not yet completely folded   */
+    double fold_p50_ms, fold_p99_ms, fold_max_ms;  /* per fold: trigger -> completed */
+    double fold_deadline_ms;        /* interval between fold launches               */
     int64_t folds;                  /* folds whose latency was measured             */
-    int64_t misses;                 /* folds whose latency exceeded the deadline    */
+    int64_t fold_misses;            /* folds whose latency exceeded fold_deadline_ms */
     int64_t integrations;           /* integrations published                       */
-    int64_t block_misses;           /* blocks whose own latency exceeded deadline_ms
-                                       (the stricter per-block reading: a block's
-                                       fold must end within k block periods of
-                                       that block's arrival)                         */
 } xc_latency_stats;
 
 typedef struct xc_server xc_server;
@@ -366,6 +414,7 @@ typedef struct xc_server xc_server;
 /* Creates a server with a device-memory budget (0 = 90% of the free memory
  * of the current device). */
 xc_status xc_server_create(size_t hbm_budget_bytes, xc_server **out);
+/* Waits for every stream's work and frees everything. */
 void xc_server_destroy(xc_server *srv);
 
 /* Device bytes one stream needs: two resident accumulators (one integrating,
@@ -373,35 +422,73 @@ void xc_server_destroy(xc_server *srv);
 size_t xc_stream_footprint(const xc_stream_desc *desc);
 
 /* Admits a stream if its footprint fits the remaining budget
- * (XC_ERR_ADMISSION otherwise), allocates its buffers and a HIP stream. */
+ * (XC_ERR_ADMISSION otherwise), allocates its buffers, a HIP stream, events
+ * and a 4-byte host-coherent flag.  Errors: XC_ERR_INVALID_ARG (sizes,
+ * blocks_per_integration not a multiple of blocks_per_fold, ring_blocks <
+ * 2 * blocks_per_fold), XC_ERR_OVERFLOW_RISK (XC_OUT_CI32 accumulator over
+ * more than XC_CI32_MAX_TIMES samples), XC_ERR_OUT_OF_MEMORY, XC_ERR_HIP. */
 xc_status xc_stream_open(xc_server *srv, const xc_stream_desc *desc, int32_t *stream_id);
 
 /* Returns the device pointer of the next free ring slot (x[C][block_times][S][2]).
- * XC_ERR_BACKPRESSURE if every slot holds a block that is not yet folded. */
+ * XC_ERR_BACKPRESSURE if that slot holds a block whose folds have not all
+ * completed; XC_ERR_STATE if the previous slot was not committed. */
 xc_status xc_stream_acquire(xc_server *srv, int32_t stream_id, void **block_dev_ptr);
 
-/* Marks the acquired slot as filled; arrival_ns is the block's arrival time
- * on the host clock (CLOCK_MONOTONIC ns).  Every blocks_per_fold committed
- * blocks one fold (accumulate-mode correlation over those blocks) is
- * enqueued; after blocks_per_integration blocks the accumulators swap and the
- * finished integration is published. */
+/* Marks the acquired slot as filled (its contents must be in place: written
+ * by the host or by device work that has completed); arrival_ns is the
+ * block's arrival time on the host clock (CLOCK_MONOTONIC ns).  Enqueues the
+ * folds this block triggers (see staggered) on the stream's HIP stream and
+ * returns without waiting.  After the last block of an integration the
+ * integration is published. */
 xc_status xc_stream_commit(xc_server *srv, int32_t stream_id, uint64_t arrival_ns);
 
-/* Device pointer to the latest published integration (V[C][B][2][2] of
- * acc_type) and its sequence number (-1 and NULL if none yet).  Work that
- * reads it must be ordered after the stream's folds (xc_stream_stats
- * synchronises them).  The buffer is reused, and overwritten, by the first
- * fold of the integration after next, so read it before the next
- * integration has been published. */
+/* The same, for a slot filled by work enqueued on producer_stream (a
+ * hipStream_t): the folds that read it wait for that work (an event recorded
+ * on producer_stream now), and the host need not synchronise. */
+xc_status xc_stream_commit_after(xc_server *srv, int32_t stream_id, uint64_t arrival_ns, void *producer_stream);
+
+/* Integration k (0, 1, ... in arrival order) of the stream: *vis = its device
+ * buffer V[C][B][2][2] of acc_type, *ready = a hipEvent_t recorded after its
+ * last fold (wait on it, e.g. hipStreamWaitEvent, before reading; the event
+ * and buffer are the library's).  Returns without blocking.  The buffer is
+ * reused by integration k + 2 from that integration's first block on:
+ * XC_ERR_STATE if integration k is not yet published or already being
+ * overwritten.  Unless the consumer calls xc_stream_release, its reads must
+ * be done before then. */
+xc_status xc_stream_integration(xc_server *srv, int32_t stream_id, int64_t k, const void **vis, void **ready);
+
+/* Makes work enqueued on `stream` after this call wait for `event` (a
+ * hipEvent_t such as xc_stream_integration's ready event): the host does
+ * not wait. */
+xc_status xc_wait_event(void *event, void *stream);
+
+/* The consumer's reads of integration k are the work enqueued on
+ * consumer_stream (a hipStream_t) before this call: the first fold that
+ * overwrites the buffer (integration k + 2) waits for that work.  Errors as
+ * for xc_stream_integration. */
+xc_status xc_stream_release(xc_server *srv, int32_t stream_id, int64_t k, void *consumer_stream);
+
+/* Device pointer to the latest published integration and its sequence
+ * number (-1 and NULL if none yet): xc_stream_integration of that number,
+ * without the event. */
 xc_status xc_stream_latest(xc_server *srv, int32_t stream_id, const void **vis,
                            int64_t *sequence);
 
-/* Waits for all enqueued folds of the stream, then fills *stats.  The wait
- * holds the server's lock, so calls on the server's other streams wait for
- * it too.  Every committed block leaves a latency record (its arrival time,
- * and one completion record per fold) that is kept until
- * xc_stream_reset_stats or xc_stream_close: a stream that runs for long
- * should read and reset its statistics periodically. */
+/* Holds the stream's folds: work enqueued on the stream after this call
+ * starts only once xc_stream_resume is called or max_wait_s (0 .. 60) has
+ * passed, whichever comes first (a one-lane kernel polls a host-coherent
+ * flag; the time limit bounds the hold whatever the host does).  For starting
+ * streams together and for exercising back-pressure deterministically. */
+xc_status xc_stream_hold(xc_server *srv, int32_t stream_id, double max_wait_s);
+xc_status xc_stream_resume(xc_server *srv, int32_t stream_id);
+
+/* Waits for all folds enqueued on the stream so far, then fills *stats.  The
+ * wait does not hold the server's lock, so the server's other streams go on;
+ * calls on this stream must not overlap its xc_stream_close.  Every committed
+ * block leaves a latency record (its arrival time, and one completion record
+ * per fold) that is kept until xc_stream_reset_stats or xc_stream_close: a
+ * stream that runs for long should read and reset its statistics
+ * periodically. */
 xc_status xc_stream_stats(xc_server *srv, int32_t stream_id, xc_latency_stats *stats);
 
 /* Waits for all enqueued folds of the stream, then forgets their latency
@@ -409,7 +496,7 @@ xc_status xc_stream_stats(xc_server *srv, int32_t stream_id, xc_latency_stats *s
  * call).  Integration state is unchanged. */
 xc_status xc_stream_reset_stats(xc_server *srv, int32_t stream_id);
 
-/* Waits for the stream's work and frees its buffers. */
+/* Waits for the stream's work (ending any hold) and frees its buffers. */
 xc_status xc_stream_close(xc_server *srv, int32_t stream_id);
 
 /* Host-only helpers, exposed for tests. */

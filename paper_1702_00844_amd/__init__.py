@@ -26,7 +26,8 @@ from ._lib import (XC_CI32_MAX_TIMES, XC_IN_CBF16, XC_IN_CF16, XC_IN_CF32, XC_IN
 
 __all__ = ["correlate", "correlate_into", "n_baselines", "baseline_index", "tile_cost", "perf_max", "ai_global",
            "flops", "resolve_config", "BatchPlan", "batch_worklist", "autotune", "tune_cache_load", "Server",
-           "quantile", "XengineError", "in_type_of", "vis_shape", "Ingest", "transpose_to_time_major", "Pfb"]
+           "quantile", "XengineError", "in_type_of", "vis_shape", "Ingest", "transpose_to_time_major", "Pfb",
+           "tune_candidates", "tune_bucket"]
 
 
 def lib():
@@ -120,12 +121,13 @@ def _config(config):
         return config
     return _lib.XcConfig(int(config.get("kernel", 0)), int(config.get("block", 0)),
                          int(config.get("time_chunk", 0)), int(config.get("time_split", 0)),
-                         int(config.get("staging", 0)), int(config.get("product", 0)))
+                         int(config.get("staging", 0)), int(config.get("product", 0)),
+                         int(config.get("tile_w", 0)), int(config.get("tile_h", 0)))
 
 
 def _config_dict(c) -> dict:
     return {"kernel": c.kernel, "block": c.block, "time_chunk": c.time_chunk, "time_split": c.time_split,
-            "staging": c.staging, "product": c.product}
+            "staging": c.staging, "product": c.product, "tile_w": c.tile_w, "tile_h": c.tile_h}
 
 
 def resolve_config(x_shape_type, out_type=XC_OUT_CF32, config=None) -> dict:
@@ -366,7 +368,8 @@ class BatchPlan:
     configuration (one workgroup per unit), replayed from a hipGraph when
     use_graph is true."""
 
-    def __init__(self, samples, outs, accumulate=False, config=None, use_graph=True, stream=None):
+    def __init__(self, samples, outs, accumulate=False, config=None, use_graph=True, stream=None,
+                 tune_cache: str | None = None):
         if len(samples) != len(outs) or not samples:
             raise ValueError("need one output per sample block")
         kinds = {in_type_of(x)[0] for x in samples}
@@ -386,7 +389,8 @@ class BatchPlan:
         handle = ctypes.c_void_p()
         _lib.check(lib().xc_batch_plan_create(items, len(samples), 2, self.in_type, self.out_type,
                                               1 if accumulate else 0, ctypes.byref(cfg) if cfg else None,
-                                              1 if use_graph else 0, _stream_ptr(stream), ctypes.byref(handle)))
+                                              tune_cache.encode() if tune_cache else None, 1 if use_graph else 0,
+                                              _stream_ptr(stream), ctypes.byref(handle)))
         self._h = handle
 
     @property
@@ -426,6 +430,24 @@ def tune_cache_load(path: str) -> int:
     return int(lib().xc_tune_cache_load(path.encode()))
 
 
+def tune_candidates(in_type: int) -> list:
+    """The auto-tuner's candidate configurations for a sample type, after the
+    Table 1 register pruning of the vector-ALU tiles."""
+    n = lib().xc_tune_candidates(in_type, None, 0)
+    if n < 0:
+        raise ValueError(f"invalid in_type {in_type}")
+    buf = (_lib.XcConfig * n)()
+    lib().xc_tune_candidates(in_type, buf, n)
+    return [_config_dict(c) for c in buf]
+
+
+def tune_bucket(in_type: int, out_type: int, n_stations: int, n_channels: int, n_times: int) -> tuple:
+    """The tuning bucket of a shape (shapes with equal buckets share a tuned configuration)."""
+    key = (ctypes.c_int32 * 6)()
+    _lib.check(lib().xc_tune_bucket(in_type, out_type, n_stations, n_channels, n_times, key))
+    return tuple(key)
+
+
 class _DevicePointer:
     """Exposes a raw device allocation of the library to torch (no copy)."""
 
@@ -453,11 +475,14 @@ class Server:
 
     @staticmethod
     def desc(n_stations, n_channels, block_times, blocks_per_integration, blocks_per_fold=1, ring_blocks=0,
-             in_type=XC_IN_CI8, acc_type=XC_OUT_CI32, block_period_s=0.0):
+             in_type=XC_IN_CI8, acc_type=XC_OUT_CI32, block_period_s=0.0, staggered=True):
+        """Stream descriptor; staggered folds one of k channel groups per block
+        (every channel still every k blocks), otherwise all channels every k
+        blocks."""
         if ring_blocks == 0:
             ring_blocks = 2 * blocks_per_fold
         return _lib.XcStreamDesc(n_stations, 2, n_channels, block_times, blocks_per_integration, blocks_per_fold,
-                                 ring_blocks, in_type, acc_type, block_period_s)
+                                 ring_blocks, in_type, acc_type, 1 if staggered else 0, block_period_s)
 
     @staticmethod
     def footprint(desc) -> int:
@@ -473,8 +498,38 @@ class Server:
         _lib.check(lib().xc_stream_acquire(self._h, sid, ctypes.byref(p)))
         return p.value
 
-    def commit(self, sid: int, arrival_ns: int):
-        _lib.check(lib().xc_stream_commit(self._h, sid, arrival_ns))
+    def commit(self, sid: int, arrival_ns: int, producer_stream=None):
+        """Marks the acquired slot filled.  With producer_stream (a torch
+        stream), the folds wait for the work enqueued on it so far instead of
+        the slot having to be complete already."""
+        if producer_stream is None:
+            _lib.check(lib().xc_stream_commit(self._h, sid, arrival_ns))
+        else:
+            _lib.check(lib().xc_stream_commit_after(self._h, sid, arrival_ns, _stream_ptr(producer_stream)))
+
+    def integration(self, sid: int, k: int):
+        """(device pointer, ready event handle) of integration k."""
+        p, ev = ctypes.c_void_p(), ctypes.c_void_p()
+        _lib.check(lib().xc_stream_integration(self._h, sid, k, ctypes.byref(p), ctypes.byref(ev)))
+        return p.value, ev.value
+
+    def wait_integration(self, sid: int, k: int, stream=None) -> int:
+        """Makes `stream` (default: the current torch stream) wait for
+        integration k without blocking the host; returns its device pointer."""
+        p, ev = self.integration(sid, k)
+        _lib.check(lib().xc_wait_event(ctypes.c_void_p(ev), _stream_ptr(stream)))
+        return p
+
+    def release(self, sid: int, k: int, stream=None):
+        """The work enqueued on `stream` so far is the last that reads
+        integration k: the fold that overwrites it waits for that work."""
+        _lib.check(lib().xc_stream_release(self._h, sid, k, _stream_ptr(stream)))
+
+    def hold(self, sid: int, max_wait_s: float):
+        _lib.check(lib().xc_stream_hold(self._h, sid, max_wait_s))
+
+    def resume(self, sid: int):
+        _lib.check(lib().xc_stream_resume(self._h, sid))
 
     def latest(self, sid: int):
         p = ctypes.c_void_p()

@@ -31,7 +31,7 @@ XC_LAYOUT_TIME_MAJOR, XC_LAYOUT_STATION_MAJOR = 0, 1
 
 class XcConfig(ctypes.Structure):
     _fields_ = [("kernel", c_i32), ("block", c_i32), ("time_chunk", c_i32), ("time_split", c_i32),
-                ("staging", c_i32), ("product", c_i32)]
+                ("staging", c_i32), ("product", c_i32), ("tile_w", c_i32), ("tile_h", c_i32)]
 
 
 class XcSubarray(ctypes.Structure):
@@ -42,14 +42,14 @@ class XcSubarray(ctypes.Structure):
 class XcStreamDesc(ctypes.Structure):
     _fields_ = [("n_stations", c_i32), ("n_pol", c_i32), ("n_channels", c_i32), ("block_times", c_i32),
                 ("blocks_per_integration", c_i32), ("blocks_per_fold", c_i32), ("ring_blocks", c_i32),
-                ("in_type", c_i32), ("acc_type", c_i32), ("block_period_s", c_f64)]
+                ("in_type", c_i32), ("acc_type", c_i32), ("staggered", c_i32), ("block_period_s", c_f64)]
 
 
 class XcLatencyStats(ctypes.Structure):
-    _fields_ = [("p50_ms", c_f64), ("p99_ms", c_f64), ("max_ms", c_f64), ("fold_p50_ms", c_f64),
-                ("fold_p99_ms", c_f64), ("fold_max_ms", c_f64), ("deadline_ms", c_f64), ("tflops", c_f64),
-                ("blocks", c_i64), ("folds", c_i64), ("misses", c_i64), ("integrations", c_i64),
-                ("block_misses", c_i64)]
+    _fields_ = [("p50_ms", c_f64), ("p99_ms", c_f64), ("max_ms", c_f64), ("deadline_ms", c_f64), ("tflops", c_f64),
+                ("blocks", c_i64), ("misses", c_i64), ("pending", c_i64), ("fold_p50_ms", c_f64),
+                ("fold_p99_ms", c_f64), ("fold_max_ms", c_f64), ("fold_deadline_ms", c_f64), ("folds", c_i64),
+                ("fold_misses", c_i64), ("integrations", c_i64)]
 
 
 # name -> (restype, argtypes): every symbol include/xengine.h declares
@@ -75,7 +75,7 @@ SIGNATURES = {
     "xc_ai_global": (c_f64, [c_i32]),
     "xc_flops": (c_f64, [c_i32, c_i32, c_i32]),
     "xc_batch_plan_create": (c_i32, [ctypes.POINTER(XcSubarray), c_i32, c_i32, c_i32, c_i32, c_i32,
-                                     ctypes.POINTER(XcConfig), c_i32, c_vp, ctypes.POINTER(c_vp)]),
+                                     ctypes.POINTER(XcConfig), c_char_p, c_i32, c_vp, ctypes.POINTER(c_vp)]),
     "xc_batch_plan_run": (c_i32, [c_vp, c_vp]),
     "xc_batch_plan_destroy": (None, [c_vp]),
     "xc_batch_plan_units": (c_i64, [c_vp]),
@@ -84,12 +84,20 @@ SIGNATURES = {
     "xc_autotune": (c_i32, [c_vp, c_i32, c_i32, c_i32, c_i32, c_i32, c_vp, c_i32, c_char_p, c_vp,
                             ctypes.POINTER(XcConfig), ctypes.POINTER(c_f64)]),
     "xc_tune_cache_load": (c_i64, [c_char_p]),
+    "xc_tune_candidates": (c_i64, [c_i32, ctypes.POINTER(XcConfig), c_i64]),
+    "xc_tune_bucket": (c_i32, [c_i32, c_i32, c_i32, c_i32, c_i32, ctypes.POINTER(c_i32)]),
     "xc_server_create": (c_i32, [c_size_t, ctypes.POINTER(c_vp)]),
     "xc_server_destroy": (None, [c_vp]),
     "xc_stream_footprint": (c_size_t, [ctypes.POINTER(XcStreamDesc)]),
     "xc_stream_open": (c_i32, [c_vp, ctypes.POINTER(XcStreamDesc), ctypes.POINTER(c_i32)]),
     "xc_stream_acquire": (c_i32, [c_vp, c_i32, ctypes.POINTER(c_vp)]),
     "xc_stream_commit": (c_i32, [c_vp, c_i32, ctypes.c_uint64]),
+    "xc_stream_commit_after": (c_i32, [c_vp, c_i32, ctypes.c_uint64, c_vp]),
+    "xc_stream_integration": (c_i32, [c_vp, c_i32, c_i64, ctypes.POINTER(c_vp), ctypes.POINTER(c_vp)]),
+    "xc_stream_release": (c_i32, [c_vp, c_i32, c_i64, c_vp]),
+    "xc_wait_event": (c_i32, [c_vp, c_vp]),
+    "xc_stream_hold": (c_i32, [c_vp, c_i32, c_f64]),
+    "xc_stream_resume": (c_i32, [c_vp, c_i32]),
     "xc_stream_latest": (c_i32, [c_vp, c_i32, ctypes.POINTER(c_vp), ctypes.POINTER(c_i64)]),
     "xc_stream_stats": (c_i32, [c_vp, c_i32, ctypes.POINTER(XcLatencyStats)]),
     "xc_stream_close": (c_i32, [c_vp, c_i32]),

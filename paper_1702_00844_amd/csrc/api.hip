@@ -60,6 +60,20 @@ static std::mutex g_tune_mu;
 static TuneEntry *g_tune = nullptr;
 static int g_tune_n = 0, g_tune_cap = 0;
 
+static int ceil_log2(int64_t v) {
+    int k = 0;
+    while (((int64_t)1 << k) < v) ++k;
+    return k;
+}
+
+TuneKey tune_bucket(int in_type, int out_type, int S, int C, int T) {
+    const int gran = in_type == XC_IN_CI8 ? 4 : (in_type == XC_IN_CF32 ? 1 : 2);
+    const int64_t nb = (S + 63) / 64;
+    const int64_t units = (int64_t)C * (nb * (nb + 1) / 2);
+    return TuneKey{in_type, out_type, (S + 31) / 32, S % gran == 0 ? 1 : 0, ceil_log2(T),
+                   std::min(ceil_log2(units), 12)};
+}
+
 void tune_put(const TuneKey &k, const xc_config &cfg) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     for (int i = 0; i < g_tune_n; ++i)
@@ -101,11 +115,11 @@ xc_status resolve(const xc_config *cfg_in, xc_in_type in_type, xc_out_type out_t
         return set_error(XC_ERR_OVERFLOW_RISK, "n_times = %d > %d: int32 visibilities could overflow", T,
                          XC_CI32_MAX_TIMES);
 
-    xc_config cfg = {0, 0, 0, 0, 0, 0};
+    xc_config cfg = {0, 0, 0, 0, 0, 0, 0, 0};
     if (cfg_in) cfg = *cfg_in;
     if (cfg.kernel == XC_KERNEL_AUTO && !cfg_in) {
         xc_config tuned;
-        if (tune_get(TuneKey{(int)in_type, (int)out_type, S, C, T}, &tuned)) cfg = tuned;
+        if (tune_get(tune_bucket((int)in_type, (int)out_type, S, C, T), &tuned)) cfg = tuned;
     }
     int kernel = cfg.kernel;
     if (kernel == XC_KERNEL_AUTO) kernel = XC_KERNEL_MFMA;
@@ -118,6 +132,7 @@ xc_status resolve(const xc_config *cfg_in, xc_in_type in_type, xc_out_type out_t
     Plan p;
     p.product = XC_PRODUCT_FOUR;
     p.kernel = kernel;
+    p.tile_w = p.tile_h = 0;
     if (kernel == XC_KERNEL_VALU) {
         if (in_type != XC_IN_CF32)
             return set_error(XC_ERR_UNSUPPORTED, "the vector-ALU kernel takes complex-float32 samples only");
@@ -125,11 +140,12 @@ xc_status resolve(const xc_config *cfg_in, xc_in_type in_type, xc_out_type out_t
         p.time_chunk = cfg.time_chunk ? cfg.time_chunk : 16;
         p.time_split = cfg.time_split ? cfg.time_split : 4;
         p.staging = cfg.staging ? cfg.staging : XC_STAGING_REGISTERS;
+        p.tile_w = cfg.tile_w ? cfg.tile_w : 4;
+        p.tile_h = cfg.tile_h ? cfg.tile_h : 4;
         if (p.block != 32) return set_error(XC_ERR_INVALID_ARG, "VALU block must be 32 (got %d)", p.block);
-        const bool ok = (p.time_chunk == 16 && (p.time_split == 1 || p.time_split == 2 || p.time_split == 4)) ||
-                        (p.time_chunk == 32 && (p.time_split == 2 || p.time_split == 4 || p.time_split == 8));
-        if (!ok)
-            return set_error(XC_ERR_INVALID_ARG, "VALU (time_chunk, time_split) = (%d, %d) not available",
+        if (!valu_available(p.tile_w, p.tile_h, p.time_chunk, p.time_split))
+            return set_error(XC_ERR_INVALID_ARG,
+                             "VALU (tile %d x %d, time_chunk %d, time_split %d) not available", p.tile_w, p.tile_h,
                              p.time_chunk, p.time_split);
         if (p.staging != XC_STAGING_REGISTERS)
             return set_error(XC_ERR_INVALID_ARG, "the vector-ALU kernel stages through registers only");
@@ -137,6 +153,8 @@ xc_status resolve(const xc_config *cfg_in, xc_in_type in_type, xc_out_type out_t
         // complex-float32 on few stations: 64-station blocks would leave most
         // of their tiles empty (measured: 8, 24 and 40 stations run 15-20 %
         // faster on 32-station blocks; 64 stations twice as fast on 64)
+        if (cfg.tile_w || cfg.tile_h)
+            return set_error(XC_ERR_INVALID_ARG, "register tiles are a vector-ALU setting (tile_w, tile_h must be 0)");
         p.block = cfg.block ? cfg.block : (in_type == XC_IN_CF32 && S <= 48 ? 32 : 64);
         if (p.block != 32 && p.block != 64)
             return set_error(XC_ERR_INVALID_ARG, "MFMA block must be 32 or 64 (got %d)", p.block);
@@ -251,6 +269,8 @@ Job make_job(const void *samples, void *vis, int S, int C, int T, int block, int
     j.accumulate = accumulate ? 1 : 0;
     j.tblk = T;
     j.bstride = 0;
+    j.slot0 = 0;
+    j.nring = 1 << 30;
     j.cstride = (int64_t)T * S;
     j.tsplit = 1;
     j.tpiece = T;
@@ -316,6 +336,8 @@ xc_status xc_resolve_config(const xc_config *cfg, xc_in_type in_type, xc_out_typ
         resolved->time_split = p.time_split;
         resolved->staging = p.staging;
         resolved->product = p.product;
+        resolved->tile_w = p.tile_w;
+        resolved->tile_h = p.tile_h;
     }
     return XC_OK;
 }
@@ -346,6 +368,34 @@ int64_t xc_correlate_split_bytes(int32_t n_stations, int32_t n_pol, int32_t n_ch
     return (int64_t)K * xc_vis_elems(n_stations, n_pol, n_channels) * 8;
 }
 
+// The integration split over workgroups once the workspace is known: the K
+// pieces' partial sums into `work` (every element written, so it need not be
+// cleared), then vis (+)= their sum in the fixed order k = 0 .. K-1.
+static xc_status split_run(const Plan &plan, const void *samples, xc_in_type in_type, int32_t S, int32_t C,
+                           int32_t T, void *vis, xc_out_type out_type, int32_t accumulate, int32_t K, void *work,
+                           hipStream_t s) {
+    const int64_t elems = xc_vis_elems(S, 2, C);
+    Job job = make_job(samples, work, S, C, T, plan.block, 0);
+    job.tsplit = K;
+    job.tpiece = (T + K - 1) / K;
+    job.xpiece = (int64_t)job.tpiece * S * 2 * in_bytes(in_type);
+    job.vpiece = elems * 8;
+    if ((int64_t)job.C * job.npairs * K > ((int64_t)1 << 30))
+        return set_error(XC_ERR_UNSUPPORTED, "too many work units");
+    xc_status st = launch_plan(plan, in_type, out_type, job, s);
+    if (st != XC_OK) return st;
+    const int blocks = (int)std::min<int64_t>((elems + 255) / 256, 65536);
+    if (out_type == XC_OUT_CI32)
+        hipLaunchKernelGGL(add_pieces<int2>, dim3(blocks), dim3(256), 0, s, static_cast<const int2 *>(work),
+                           static_cast<int2 *>(vis), elems, K, accumulate);
+    else
+        hipLaunchKernelGGL(add_pieces<float2>, dim3(blocks), dim3(256), 0, s, static_cast<const float2 *>(work),
+                           static_cast<float2 *>(vis), elems, K, accumulate);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_error(e, "piece-sum launch");
+    return XC_OK;
+}
+
 xc_status xc_correlate_split(const xc_config *cfg, const void *samples, xc_in_type in_type, int32_t n_stations,
                              int32_t n_pol, int32_t n_channels, int32_t n_times, void *vis, xc_out_type out_type,
                              int32_t accumulate, int32_t n_split, void *work, int64_t work_bytes, void *stream) {
@@ -365,26 +415,8 @@ xc_status xc_correlate_split(const xc_config *cfg, const void *samples, xc_in_ty
     if (work_bytes < (int64_t)K * elems * 8)
         return set_error(XC_ERR_INVALID_ARG, "work holds %lld bytes, %lld needed", (long long)work_bytes,
                          (long long)K * elems * 8);
-    Job job = make_job(samples, work, n_stations, n_channels, n_times, plan.block, 0);
-    job.tsplit = K;
-    job.tpiece = (n_times + K - 1) / K;
-    job.xpiece = (int64_t)job.tpiece * n_stations * 2 * in_bytes(in_type);
-    job.vpiece = elems * 8;
-    if ((int64_t)job.C * job.npairs * K > ((int64_t)1 << 30))
-        return set_error(XC_ERR_UNSUPPORTED, "too many work units");
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    st = launch_plan(plan, in_type, out_type, job, s);
-    if (st != XC_OK) return st;
-    const int blocks = (int)std::min<int64_t>((elems + 255) / 256, 65536);
-    if (out_type == XC_OUT_CI32)
-        hipLaunchKernelGGL(add_pieces<int2>, dim3(blocks), dim3(256), 0, s, static_cast<const int2 *>(work),
-                           static_cast<int2 *>(vis), elems, K, accumulate);
-    else
-        hipLaunchKernelGGL(add_pieces<float2>, dim3(blocks), dim3(256), 0, s, static_cast<const float2 *>(work),
-                           static_cast<float2 *>(vis), elems, K, accumulate);
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return hip_error(e, "piece-sum launch");
-    return XC_OK;
+    return split_run(plan, samples, in_type, n_stations, n_channels, n_times, vis, out_type, accumulate, K, work,
+                     static_cast<hipStream_t>(stream));
 }
 
 xc_status xc_correlate_station_major(const xc_config *cfg, const void *samples, xc_in_type in_type,

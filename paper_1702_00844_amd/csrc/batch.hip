@@ -115,7 +115,7 @@ static hipError_t plan_enqueue(xc_batch_plan *p, hipStream_t s) {
 static bool same_plan(const Plan &a, const Plan &b) {
     return a.kernel == b.kernel && a.block == b.block && a.time_chunk == b.time_chunk &&
            a.time_split == b.time_split && a.staging == b.staging &&
-           a.product == b.product;
+           a.product == b.product && a.tile_w == b.tile_w && a.tile_h == b.tile_h;
 }
 
 extern "C" {
@@ -145,17 +145,35 @@ int64_t xc_batch_worklist(const int32_t *n_stations, const int32_t *n_channels, 
 }
 
 xc_status xc_batch_plan_create(const xc_subarray *items, int32_t n_items, int32_t n_pol, xc_in_type in_type,
-                               xc_out_type out_type, int32_t accumulate, const xc_config *cfg, int32_t use_graph,
-                               void *stream, xc_batch_plan **out) {
+                               xc_out_type out_type, int32_t accumulate, const xc_config *cfg,
+                               const char *tune_cache, int32_t use_graph, void *stream, xc_batch_plan **out) {
     if (!out) return set_error(XC_ERR_INVALID_ARG, "null output plan pointer");
     *out = nullptr;
     if (!items || n_items < 1) return set_error(XC_ERR_INVALID_ARG, "a batch needs at least one item");
     if (accumulate != 0 && accumulate != 1) return set_error(XC_ERR_INVALID_ARG, "accumulate must be 0 or 1");
-    // Without an explicit configuration every item runs one time group per
-    // workgroup; items whose configurations still differ (e.g. the staging of
-    // int8 samples, which depends on the station count) get one launch each.
-    const xc_config one_group = {XC_KERNEL_AUTO, 0, 0, 1, XC_STAGING_AUTO, XC_PRODUCT_AUTO};
-    if (!cfg) cfg = &one_group;
+    // Without an explicit configuration: with a tuning cache, each item takes
+    // the configuration tuned for its shape bucket (buckets the cache lacks are
+    // tuned now on their first item, unless the batch accumulates); without
+    // one, every item runs one time group per workgroup.  Items whose
+    // configurations differ (also the staging of int8 samples, which depends on
+    // the station count) get one launch each.
+    const xc_config one_group = {XC_KERNEL_AUTO, 0, 0, 1, XC_STAGING_AUTO, XC_PRODUCT_AUTO, 0, 0};
+    if (!cfg && tune_cache) {
+        (void)xc_tune_cache_load(tune_cache);      // a missing file is an empty cache
+        for (int i = 0; i < n_items; ++i) {
+            const xc_subarray &it = items[i];
+            if (it.n_stations < 1 || it.n_channels < 1 || it.n_times < 1 || !it.samples || !it.vis) break;
+            xc_config tuned;
+            if (tune_get(tune_bucket(in_type, out_type, it.n_stations, it.n_channels, it.n_times), &tuned)) continue;
+            if (accumulate) continue;              // tuning would overwrite the results being accumulated into
+            double ms;
+            xc_status st = xc_autotune(it.samples, in_type, it.n_stations, n_pol, it.n_channels, it.n_times, it.vis,
+                                       out_type, tune_cache, stream, &tuned, &ms);
+            if (st != XC_OK) return st;
+        }
+    } else if (!cfg) {
+        cfg = &one_group;
+    }
     std::vector<int32_t> S(n_items), C(n_items), T(n_items);
     std::vector<Plan> plans;                 // distinct configurations, in order of first use
     std::vector<std::vector<int>> members;   // their items

@@ -21,11 +21,15 @@ struct Job {
     int32_t nb;        // station blocks per side: ceil(S / block)
     int32_t npairs;    // nb (nb + 1) / 2
     int32_t accumulate;
-    // Time-blocked input (a run of consecutive ring slots of a stream): time t
-    // lives in block t / tblk, each block being x[C][tblk][S][2], bstride
-    // station-samples apart.  Unblocked input has tblk = T and bstride = 0.
+    // Time-blocked input (a run of ring slots of a stream): time t lives in
+    // block t / tblk, each block being x[C][tblk][S][2], bstride
+    // station-samples apart; block b is slot slot0 + b of a ring of nring
+    // slots, wrapping to slot 0 past the last.  Unblocked input has tblk = T
+    // and bstride = 0.
     int32_t tblk;
     int64_t bstride;
+    int32_t slot0;
+    int32_t nring;
     // Unblocked input: station-samples from one channel to the next (T S for
     // a whole block; larger when the job views a sub-range of time).
     int64_t cstride;
@@ -50,7 +54,9 @@ struct Job {
 __host__ __device__ inline size_t row_offset(const Job &job, int c, int t) {
     if (job.bstride == 0) return (size_t)c * job.cstride + (size_t)t * job.S;
     const int blk = t / job.tblk;
-    return (size_t)blk * job.bstride + ((size_t)c * job.tblk + (t - blk * job.tblk)) * job.S;
+    int slot = job.slot0 + blk;
+    if (slot >= job.nring) slot -= job.nring;
+    return (size_t)slot * job.bstride + ((size_t)c * job.tblk + (t - blk * job.tblk)) * job.S;
 }
 
 // True when time steps t0 .. t0 + n - 1 of a channel are consecutive rows in
@@ -127,9 +133,15 @@ struct Plan {
     int time_split;  // waves sharing one output block over time
     int staging;     // XC_STAGING_REGISTERS or XC_STAGING_LDS
     int product;     // XC_PRODUCT_FOUR or XC_PRODUCT_THREE
+    int tile_w;      // vector-ALU register tile: stations of block I per lane (0 elsewhere)
+    int tile_h;      // vector-ALU register tile: stations of block J per lane (0 elsewhere)
 };
 // Product form that AUTO picks for complex-float32 on 64-station matrix-core blocks.
 constexpr int kDefaultProductF32 = XC_PRODUCT_THREE;
+
+// True when the vector-ALU kernel is built for this register tile, time
+// chunk and number of time groups.
+bool valu_available(int tile_w, int tile_h, int time_chunk, int time_split);
 
 // Launchers (return hipSuccess or the launch error).
 hipError_t launch_valu(const Plan &plan, const Job &job, hipStream_t stream);
@@ -162,13 +174,19 @@ hipError_t launch_valu_batch(const Plan &plan, const Job *jobs, const Unit *unit
 hipError_t launch_mfma_batch(const Plan &plan, xc_in_type in_type, xc_out_type out_type, const Job *jobs,
                              const Unit *units, const int *bounds, int grid, hipStream_t stream);
 
-// Process-wide tuning cache (shape -> configuration chosen by xc_autotune).
+// Process-wide tuning cache: shape bucket -> configuration chosen by
+// xc_autotune.  A bucket groups shapes that the same configuration serves:
+// the number of 32-station blocks, whether the station count fills whole copy
+// granules of the direct-to-LDS kernel, the integration length class
+// ceil(log2 T) and the work-unit class ceil(log2(C x 64-station block pairs))
+// (how well the shape fills the device), capped at 2^12 units.
 struct TuneKey {
-    int in, out, S, C, T;
+    int in, out, sb, gran, tb, ub;
     bool operator==(const TuneKey &o) const {
-        return in == o.in && out == o.out && S == o.S && C == o.C && T == o.T;
+        return in == o.in && out == o.out && sb == o.sb && gran == o.gran && tb == o.tb && ub == o.ub;
     }
 };
+TuneKey tune_bucket(int in_type, int out_type, int S, int C, int T);
 void tune_put(const TuneKey &k, const xc_config &cfg);
 bool tune_get(const TuneKey &k, xc_config *cfg);
 

@@ -1,26 +1,43 @@
 // Streaming correlator server.
 //
 // The correlator is a streaming, real-time application (Section 1): sample
-// blocks arrive at a fixed period and must be integrated (Section 2: about one
-// second of samples per integration) without falling behind.  Each stream owns
+// blocks arrive at a fixed period P and must be integrated (Section 2: about
+// one second of samples per integration) without falling behind.  Each
+// stream owns
 //   - a device ring of `ring_blocks` sample blocks x[C][block_times][S][2],
-//   - two resident accumulators V[C][B][2][2]: one integrating, one holding
-//     the last published integration,
-//   - a HIP stream on which its folds run in order.
-// Every `blocks_per_fold` committed blocks, one accumulate-mode correlation
-// over those consecutive ring slots is enqueued (the integration is split into
+//   - two resident accumulators V[C][B][2][2]: integration n lives in
+//     accumulator n % 2, so one is being integrated while the other holds the
+//     last published integration,
+//   - a HIP stream on which its folds run in order, and events that mark an
+//     integration's completion and a consumer's release of it.
+// A fold is one accumulate-mode correlation of some channels over a run of
+// consecutive blocks of the ring (the integration is split into
 // sub-intervals whose partial sums are added into the resident result, as
-// Section 4.5 does with the Cell's local store).  The first fold of an
-// integration overwrites instead of adding, so no clearing pass is needed.
-// A host function enqueued after each fold records its completion time on
-// the host clock; per-block latency = completion - arrival, per-fold latency
-// = completion - arrival of the fold's last block (the deadline applies to
-// folds: finish before the next fold's blocks are all in).
-// Streams are admitted only if their device footprint fits the budget.
+// Section 4.5 does with the Cell's local store); the first fold of a channel
+// in an integration overwrites instead of adding, so nothing is cleared.
+//
+// Fold schedules, with k = blocks_per_fold:
+//   - all channels (staggered = 0): every k committed blocks, one fold of
+//     every channel over those k blocks;
+//   - staggered (staggered = 1): the channels are cut into k groups, and at
+//     every committed block n the group g = n mod k folds the blocks it has
+//     not yet folded (k of them in the steady state).  Each channel is still
+//     folded every k blocks, but the device gets 1/k of the work every block
+//     period instead of all of it every k periods, so a block's last fold
+//     ends within (k - 1) P + (one fold of C/k channels) of its arrival.  At
+//     the end of an integration every group folds what it has left, so that
+//     the integration is complete when it is published.
+// A block's latency runs from its arrival to the completion of the last fold
+// that covers it; its deadline is D = k P.  A fold's latency runs from the
+// arrival of the block that triggered it to its completion, against the
+// interval between fold launches (P staggered, k P otherwise).  Completion
+// times come from host functions enqueued after each fold.  Streams are
+// admitted only if their device footprint fits the budget.
 #include <time.h>
 
 #include <algorithm>
 #include <cmath>
+#include <deque>
 #include <mutex>
 #include <vector>
 
@@ -64,32 +81,58 @@ void on_fold_done(void *arg) {
     __atomic_store_n(&f->done, 1, __ATOMIC_RELEASE);
 }
 
+bool is_done(const FoldDone *f) { return f && __atomic_load_n(&f->done, __ATOMIC_ACQUIRE); }
+
+// Holds a stream until a host flag is set or a time limit has passed (the
+// limit bounds the wait whatever the host does).  One lane polls the flag,
+// sleeping between reads; s_memrealtime counts at a constant 100 MHz.
+__global__ void hold_kernel(const int *flag, uint64_t max_ticks) {
+    if (threadIdx.x != 0) return;
+    const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+    while (__hip_atomic_load(flag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM) == 0) {
+        if (__builtin_amdgcn_s_memrealtime() - t0 >= max_ticks) break;
+        __builtin_amdgcn_s_sleep(64);
+    }
+}
+
+struct Fold {
+    FoldDone *rec;
+    int64_t trigger;   // block whose commit enqueued the fold
+    double flops;      // algorithmic flops of the fold
+};
+
 struct Stream {
     bool open = false;
     xc_stream_desc d{};
     Plan plan{};
+    int groups = 1;           // channel groups folded in turn (k when staggered)
     size_t footprint = 0;
     size_t block_bytes = 0;   // one ring slot
     size_t acc_bytes = 0;
+    size_t chan_sample_bytes = 0;  // one channel of one slot
+    size_t chan_vis_bytes = 0;     // one channel of an accumulator
     int64_t block_elems = 0;  // station-samples per slot (C * block_times * S)
+    int64_t B = 0;
     void *ring = nullptr;
     void *acc[2] = {nullptr, nullptr};
     hipStream_t hs = nullptr;
-    int active = 0;           // accumulator being integrated
+    hipEvent_t ready_ev[2] = {nullptr, nullptr};    // recorded after an integration's last fold
+    hipEvent_t release_ev[2] = {nullptr, nullptr};  // recorded on a consumer's stream by xc_stream_release
+    hipEvent_t fill_ev = nullptr;                   // recorded on a producer's stream by xc_stream_commit_after
+    int32_t *hold_flag = nullptr;                   // host-coherent flag that ends a hold (xc_stream_hold)
+    bool release_pending[2] = {false, false};
     int64_t published_seq = -1;
-    int published = -1;       // accumulator index of the last published integration
     int64_t committed = 0;    // blocks committed so far
     bool acquired = false;    // a slot has been handed out and not yet committed
-    // per ring slot: fold record that must complete before reuse (nullptr = free)
+    std::vector<int64_t> group_next;   // per channel group: first block it has not folded
+    // per ring slot: the last fold that reads it (nullptr = free)
     std::vector<FoldDone *> slot_busy;
-    std::vector<uint64_t> pending_arrivals;  // arrivals of the blocks of the open fold
-    // per fold: completion record and the arrivals of its blocks
-    struct Fold {
-        FoldDone *rec;
-        std::vector<uint64_t> arrivals;
-    };
-    std::vector<Fold> folds;
-    double flops_per_fold = 0;
+    // latency records of blocks rec_base .. committed - 1: arrival and the
+    // last fold covering the block (nullptr while it is not yet folded)
+    int64_t rec_base = 0;
+    std::deque<uint64_t> arrivals;
+    std::deque<FoldDone *> block_fold;
+    std::vector<Fold> folds;          // folds enqueued since the last reset
 };
 
 }  // namespace
@@ -109,27 +152,79 @@ static xc_status validate_desc(const xc_stream_desc *d) {
         return set_error(XC_ERR_INVALID_ARG, "stream sizes must be >= 1");
     if (d->blocks_per_integration % d->blocks_per_fold)
         return set_error(XC_ERR_INVALID_ARG, "blocks_per_integration must be a multiple of blocks_per_fold");
-    if (d->ring_blocks % d->blocks_per_fold || d->ring_blocks < 2 * d->blocks_per_fold)
-        return set_error(XC_ERR_INVALID_ARG, "ring_blocks must be a multiple of blocks_per_fold and >= 2 folds");
+    if (d->ring_blocks < 2 * d->blocks_per_fold)
+        return set_error(XC_ERR_INVALID_ARG, "ring_blocks must be >= 2 * blocks_per_fold");
+    if (d->staggered != 0 && d->staggered != 1) return set_error(XC_ERR_INVALID_ARG, "staggered must be 0 or 1");
     if (!(d->block_period_s >= 0.0)) return set_error(XC_ERR_INVALID_ARG, "block_period_s must be >= 0");
     const int64_t T_int = (int64_t)d->block_times * d->blocks_per_integration;
     if (d->acc_type == XC_OUT_CI32 && T_int > XC_CI32_MAX_TIMES)
         return set_error(XC_ERR_OVERFLOW_RISK, "an integration of %lld samples could overflow int32",
                          (long long)T_int);
+    if ((int64_t)d->block_times * d->blocks_per_fold > (1 << 30))
+        return set_error(XC_ERR_UNSUPPORTED, "a fold of %d blocks of %d samples is too long", d->blocks_per_fold,
+                         d->block_times);
     Plan p;
     return resolve(nullptr, (xc_in_type)d->in_type, (xc_out_type)d->acc_type, d->n_stations, d->n_pol,
                    d->n_channels, d->block_times * d->blocks_per_fold, &p);
 }
 
 static void stream_free(Stream &s) {
+    if (s.hold_flag) __atomic_store_n(s.hold_flag, 1, __ATOMIC_RELEASE);
     if (s.hs) (void)hipStreamSynchronize(s.hs);
     for (auto &f : s.folds) delete f.rec;
     s.folds.clear();
     if (s.ring) (void)hipFree(s.ring);
     for (auto &a : s.acc)
         if (a) (void)hipFree(a);
+    for (int k = 0; k < 2; ++k) {
+        if (s.ready_ev[k]) (void)hipEventDestroy(s.ready_ev[k]);
+        if (s.release_ev[k]) (void)hipEventDestroy(s.release_ev[k]);
+    }
+    if (s.fill_ev) (void)hipEventDestroy(s.fill_ev);
+    if (s.hold_flag) (void)hipHostFree(s.hold_flag);
     if (s.hs) (void)hipStreamDestroy(s.hs);
     s = Stream{};
+}
+
+// Channels [c0, c1) of channel group g of G.
+static void group_channels(const Stream &s, int g, int &c0, int &c1) {
+    const int C = s.d.n_channels;
+    c0 = (int)((int64_t)C * g / s.groups);
+    c1 = (int)((int64_t)C * (g + 1) / s.groups);
+}
+
+// Enqueues the fold of channel group g over blocks first .. last (absolute
+// numbers, all in one integration) and records it.
+static xc_status enqueue_fold(Stream &s, int g, int64_t first, int64_t last, int64_t trigger) {
+    int c0, c1;
+    group_channels(s, g, c0, c1);
+    if (c1 <= c0) return XC_OK;
+    const int64_t bpi = s.d.blocks_per_integration;
+    const int64_t integ = first / bpi;
+    const int nblk = (int)(last - first + 1);
+    const int slot0 = (int)(first % s.d.ring_blocks);
+    const bool overwrite = first == integ * bpi;
+    Job job = make_job(static_cast<uint8_t *>(s.ring) + (size_t)c0 * s.chan_sample_bytes,
+                       static_cast<uint8_t *>(s.acc[integ % 2]) + (size_t)c0 * s.chan_vis_bytes, s.d.n_stations,
+                       c1 - c0, s.d.block_times * nblk, s.plan.block, overwrite ? 0 : 1);
+    job.tblk = s.d.block_times;
+    job.bstride = s.block_elems;
+    job.slot0 = slot0;
+    job.nring = s.d.ring_blocks;
+    xc_status st = launch_plan(s.plan, (xc_in_type)s.d.in_type, (xc_out_type)s.d.acc_type, job, s.hs);
+    if (st != XC_OK) return st;
+    FoldDone *rec = new FoldDone;
+    hipError_t e = hipLaunchHostFunc(s.hs, on_fold_done, rec);
+    if (e != hipSuccess) {
+        delete rec;
+        return hip_error(e, "hipLaunchHostFunc");
+    }
+    for (int64_t b = first; b <= last; ++b) {
+        s.slot_busy[(size_t)(b % s.d.ring_blocks)] = rec;
+        if (b >= s.rec_base) s.block_fold[(size_t)(b - s.rec_base)] = rec;
+    }
+    s.folds.push_back(Fold{rec, trigger, 32.0 * (c1 - c0) * (double)s.d.block_times * nblk * (double)s.B});
+    return XC_OK;
 }
 
 extern "C" {
@@ -189,21 +284,35 @@ xc_status xc_stream_open(xc_server *srv, const xc_stream_desc *desc, int32_t *st
     s.d = *desc;
     resolve(nullptr, (xc_in_type)desc->in_type, (xc_out_type)desc->acc_type, desc->n_stations, 2, desc->n_channels,
             desc->block_times * desc->blocks_per_fold, &s.plan);
+    s.groups = desc->staggered ? desc->blocks_per_fold : 1;
     s.footprint = fp;
-    const size_t B = (size_t)desc->n_stations * (desc->n_stations + 1) / 2;
-    s.acc_bytes = (size_t)desc->n_channels * B * 4 * 8;
+    s.B = (int64_t)desc->n_stations * (desc->n_stations + 1) / 2;
+    s.acc_bytes = (size_t)desc->n_channels * s.B * 4 * 8;
+    s.chan_vis_bytes = (size_t)s.B * 4 * 8;
     s.block_elems = (int64_t)desc->n_channels * desc->block_times * desc->n_stations;
     s.block_bytes = (size_t)s.block_elems * 2 * in_elem_bytes(desc->in_type);
+    s.chan_sample_bytes = (size_t)desc->block_times * desc->n_stations * 2 * in_elem_bytes(desc->in_type);
     hipError_t e = hipMalloc(&s.ring, s.block_bytes * desc->ring_blocks);
     if (e == hipSuccess) e = hipMalloc(&s.acc[0], s.acc_bytes);
     if (e == hipSuccess) e = hipMalloc(&s.acc[1], s.acc_bytes);
-    if (e == hipSuccess) e = hipStreamCreateWithFlags(&s.hs, hipStreamNonBlocking);
     if (e != hipSuccess) {
         stream_free(s);
         return set_error(XC_ERR_OUT_OF_MEMORY, "stream allocation failed: %s", hipGetErrorString(e));
     }
+    e = hipStreamCreateWithFlags(&s.hs, hipStreamNonBlocking);
+    for (int k = 0; k < 2 && e == hipSuccess; ++k) {
+        e = hipEventCreateWithFlags(&s.ready_ev[k], hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&s.release_ev[k], hipEventDisableTiming);
+    }
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&s.fill_ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&s.hold_flag, sizeof(int32_t), hipHostMallocCoherent);
+    if (e == hipSuccess) __atomic_store_n(s.hold_flag, 1, __ATOMIC_RELEASE);
+    if (e != hipSuccess) {
+        stream_free(s);
+        return hip_error(e, "stream or event creation");
+    }
     s.slot_busy.assign(desc->ring_blocks, nullptr);
-    s.flops_per_fold = 32.0 * desc->n_channels * (double)desc->block_times * desc->blocks_per_fold * (double)B;
+    s.group_next.assign(s.groups, 0);
     s.open = true;
     srv->used += fp;
     int id = -1;
@@ -236,7 +345,7 @@ xc_status xc_stream_acquire(xc_server *srv, int32_t id, void **block_dev_ptr) {
     const int slot = (int)(s->committed % s->d.ring_blocks);
     FoldDone *busy = s->slot_busy[slot];
     if (busy) {
-        if (!__atomic_load_n(&busy->done, __ATOMIC_ACQUIRE))
+        if (!is_done(busy))
             return set_error(XC_ERR_BACKPRESSURE, "stream %d: ring full (slot %d still being folded)", id, slot);
         s->slot_busy[slot] = nullptr;
     }
@@ -245,42 +354,108 @@ xc_status xc_stream_acquire(xc_server *srv, int32_t id, void **block_dev_ptr) {
     return XC_OK;
 }
 
+static xc_status commit_locked(Stream *s, int32_t id, uint64_t arrival_ns, hipStream_t producer) {
+    if (!s->acquired) return set_error(XC_ERR_STATE, "stream %d: commit without acquire", id);
+    if (producer) {
+        // the folds that read this slot run after the producer's work so far
+        hipError_t e = hipEventRecord(s->fill_ev, producer);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s->hs, s->fill_ev, 0);
+        if (e != hipSuccess) return hip_error(e, "producer event");
+    }
+    s->acquired = false;
+    const int64_t n = s->committed++;
+    s->arrivals.push_back(arrival_ns);
+    s->block_fold.push_back(nullptr);
+    const int64_t bpi = s->d.blocks_per_integration;
+    const int64_t integ = n / bpi, m = n % bpi;
+    const int k = s->d.blocks_per_fold;
+    if (m == 0) {
+        // a new integration starts: its accumulator held integration integ - 2,
+        // which a consumer may still be reading
+        if (s->release_pending[integ % 2]) {
+            hipError_t e = hipStreamWaitEvent(s->hs, s->release_ev[integ % 2], 0);
+            if (e != hipSuccess) return hip_error(e, "release event");
+            s->release_pending[integ % 2] = false;
+        }
+        for (auto &g : s->group_next) g = n;
+    }
+    const bool last = m == bpi - 1;
+    xc_status st = XC_OK;
+    if (s->groups == 1) {
+        if ((m + 1) % k == 0) {
+            st = enqueue_fold(*s, 0, s->group_next[0], n, n);
+            s->group_next[0] = n + 1;
+        }
+    } else {
+        // group m mod k folds its outstanding blocks; at the end of the
+        // integration every group does
+        const int g0 = (int)(m % k);
+        for (int i = 0; i < s->groups && st == XC_OK; ++i) {
+            const int g = (g0 + 1 + i) % s->groups;     // group g0 last: its fold is the regular one
+            if (!(last || g == g0) || s->group_next[g] > n) continue;
+            st = enqueue_fold(*s, g, s->group_next[g], n, n);
+            s->group_next[g] = n + 1;
+        }
+    }
+    if (st != XC_OK) return st;
+    if (last) {
+        hipError_t e = hipEventRecord(s->ready_ev[integ % 2], s->hs);
+        if (e != hipSuccess) return hip_error(e, "integration event");
+        s->published_seq = integ;
+    }
+    return XC_OK;
+}
+
 xc_status xc_stream_commit(xc_server *srv, int32_t id, uint64_t arrival_ns) {
     if (!srv) return set_error(XC_ERR_INVALID_ARG, "null server");
     std::lock_guard<std::mutex> lk(srv->mu);
     Stream *s = get_stream(srv, id);
     if (!s) return set_error(XC_ERR_INVALID_ARG, "no open stream %d", id);
-    if (!s->acquired) return set_error(XC_ERR_STATE, "stream %d: commit without acquire", id);
-    s->acquired = false;
-    s->pending_arrivals.push_back(arrival_ns);
-    s->committed++;
-    const int k = s->d.blocks_per_fold;
-    if (s->committed % k) return XC_OK;
-    // enqueue the fold over the last k slots
-    const int64_t first_block = s->committed - k;
-    const int slot0 = (int)(first_block % s->d.ring_blocks);
-    const int64_t in_integration = first_block % s->d.blocks_per_integration;
-    Job job = make_job(static_cast<uint8_t *>(s->ring) + (size_t)slot0 * s->block_bytes, s->acc[s->active],
-                       s->d.n_stations, s->d.n_channels, s->d.block_times * k, s->plan.block,
-                       in_integration == 0 ? 0 : 1);
-    job.tblk = s->d.block_times;
-    job.bstride = s->block_elems;
-    xc_status st = launch_plan(s->plan, (xc_in_type)s->d.in_type, (xc_out_type)s->d.acc_type, job, s->hs);
-    if (st != XC_OK) return st;
-    FoldDone *rec = new FoldDone;
-    hipError_t e = hipLaunchHostFunc(s->hs, on_fold_done, rec);
-    if (e != hipSuccess) {
-        delete rec;
-        return hip_error(e, "hipLaunchHostFunc");
-    }
-    for (int b = 0; b < k; ++b) s->slot_busy[(slot0 + b) % s->d.ring_blocks] = rec;
-    s->folds.push_back(Stream::Fold{rec, std::move(s->pending_arrivals)});
-    s->pending_arrivals.clear();
-    if ((s->committed % s->d.blocks_per_integration) == 0) {
-        s->published = s->active;
-        s->published_seq = s->committed / s->d.blocks_per_integration - 1;
-        s->active ^= 1;
-    }
+    return commit_locked(s, id, arrival_ns, nullptr);
+}
+
+xc_status xc_stream_commit_after(xc_server *srv, int32_t id, uint64_t arrival_ns, void *producer_stream) {
+    if (!srv) return set_error(XC_ERR_INVALID_ARG, "null server");
+    std::lock_guard<std::mutex> lk(srv->mu);
+    Stream *s = get_stream(srv, id);
+    if (!s) return set_error(XC_ERR_INVALID_ARG, "no open stream %d", id);
+    return commit_locked(s, id, arrival_ns, static_cast<hipStream_t>(producer_stream));
+}
+
+xc_status xc_stream_integration(xc_server *srv, int32_t id, int64_t k, const void **vis, void **ready) {
+    if (!vis || !ready) return set_error(XC_ERR_INVALID_ARG, "null output pointer");
+    if (!srv) return set_error(XC_ERR_INVALID_ARG, "null server");
+    std::lock_guard<std::mutex> lk(srv->mu);
+    Stream *s = get_stream(srv, id);
+    if (!s) return set_error(XC_ERR_INVALID_ARG, "no open stream %d", id);
+    // integration k + 2 reuses the buffer from its first block on
+    const int64_t started = s->committed ? (s->committed - 1) / s->d.blocks_per_integration : -1;
+    if (k < 0 || k > s->published_seq || started >= k + 2)
+        return set_error(XC_ERR_STATE, "stream %d: integration %lld is not available (published: %lld, started: %lld)",
+                         id, (long long)k, (long long)s->published_seq, (long long)started);
+    *vis = s->acc[k % 2];
+    *ready = s->ready_ev[k % 2];
+    return XC_OK;
+}
+
+xc_status xc_wait_event(void *event, void *stream) {
+    if (!event) return set_error(XC_ERR_INVALID_ARG, "null event");
+    hipError_t e = hipStreamWaitEvent(static_cast<hipStream_t>(stream), static_cast<hipEvent_t>(event), 0);
+    if (e != hipSuccess) return hip_error(e, "hipStreamWaitEvent");
+    return XC_OK;
+}
+
+xc_status xc_stream_release(xc_server *srv, int32_t id, int64_t k, void *consumer_stream) {
+    if (!srv) return set_error(XC_ERR_INVALID_ARG, "null server");
+    std::lock_guard<std::mutex> lk(srv->mu);
+    Stream *s = get_stream(srv, id);
+    if (!s) return set_error(XC_ERR_INVALID_ARG, "no open stream %d", id);
+    const int64_t started = s->committed ? (s->committed - 1) / s->d.blocks_per_integration : -1;
+    if (k < 0 || k > s->published_seq || started >= k + 2)
+        return set_error(XC_ERR_STATE, "stream %d: integration %lld is not available", id, (long long)k);
+    hipError_t e = hipEventRecord(s->release_ev[k % 2], static_cast<hipStream_t>(consumer_stream));
+    if (e != hipSuccess) return hip_error(e, "release event");
+    s->release_pending[k % 2] = true;
     return XC_OK;
 }
 
@@ -290,51 +465,98 @@ xc_status xc_stream_latest(xc_server *srv, int32_t id, const void **vis, int64_t
     std::lock_guard<std::mutex> lk(srv->mu);
     Stream *s = get_stream(srv, id);
     if (!s) return set_error(XC_ERR_INVALID_ARG, "no open stream %d", id);
-    *vis = s->published >= 0 ? s->acc[s->published] : nullptr;
+    *vis = s->published_seq >= 0 ? s->acc[s->published_seq % 2] : nullptr;
     *sequence = s->published_seq;
+    return XC_OK;
+}
+
+xc_status xc_stream_hold(xc_server *srv, int32_t id, double max_wait_s) {
+    if (!srv) return set_error(XC_ERR_INVALID_ARG, "null server");
+    if (!(max_wait_s >= 0.0 && max_wait_s <= 60.0)) return set_error(XC_ERR_INVALID_ARG, "max_wait_s must be in [0, 60]");
+    std::lock_guard<std::mutex> lk(srv->mu);
+    Stream *s = get_stream(srv, id);
+    if (!s) return set_error(XC_ERR_INVALID_ARG, "no open stream %d", id);
+    __atomic_store_n(s->hold_flag, 0, __ATOMIC_RELEASE);
+    const uint64_t ticks = (uint64_t)(max_wait_s * 1e8);   // s_memrealtime: 100 MHz
+    hipLaunchKernelGGL(hold_kernel, dim3(1), dim3(64), 0, s->hs, (const int *)s->hold_flag, ticks);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        __atomic_store_n(s->hold_flag, 1, __ATOMIC_RELEASE);
+        return hip_error(e, "hold launch");
+    }
+    return XC_OK;
+}
+
+xc_status xc_stream_resume(xc_server *srv, int32_t id) {
+    if (!srv) return set_error(XC_ERR_INVALID_ARG, "null server");
+    std::lock_guard<std::mutex> lk(srv->mu);
+    Stream *s = get_stream(srv, id);
+    if (!s) return set_error(XC_ERR_INVALID_ARG, "no open stream %d", id);
+    __atomic_store_n(s->hold_flag, 1, __ATOMIC_RELEASE);
     return XC_OK;
 }
 
 xc_status xc_stream_stats(xc_server *srv, int32_t id, xc_latency_stats *stats) {
     if (!stats) return set_error(XC_ERR_INVALID_ARG, "null output pointer");
     if (!srv) return set_error(XC_ERR_INVALID_ARG, "null server");
+    hipStream_t hs;
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        Stream *s = get_stream(srv, id);
+        if (!s) return set_error(XC_ERR_INVALID_ARG, "no open stream %d", id);
+        hs = s->hs;
+    }
+    // wait without the lock: the server's other streams go on
+    hipError_t e = hipStreamSynchronize(hs);
+    if (e != hipSuccess) return hip_error(e, "hipStreamSynchronize");
     std::lock_guard<std::mutex> lk(srv->mu);
     Stream *s = get_stream(srv, id);
-    if (!s) return set_error(XC_ERR_INVALID_ARG, "no open stream %d", id);
-    hipError_t e = hipStreamSynchronize(s->hs);
-    if (e != hipSuccess) return hip_error(e, "hipStreamSynchronize");
+    if (!s || s->hs != hs) return set_error(XC_ERR_STATE, "stream %d was closed during the call", id);
+    const double P_ms = 1e3 * s->d.block_period_s;
+    const double deadline = P_ms * s->d.blocks_per_fold;
+    const double fold_deadline = s->groups > 1 ? P_ms : deadline;
     std::vector<double> lat, flat;
     uint64_t t_first = UINT64_MAX, t_last = 0;
+    int64_t pending = 0;
+    for (size_t b = 0; b < s->arrivals.size(); ++b) {
+        const FoldDone *f = s->block_fold[b];
+        if (!is_done(f)) {       // not folded yet (or folded by work enqueued after the wait)
+            pending++;
+            continue;
+        }
+        const uint64_t a = s->arrivals[b];
+        lat.push_back(f->done_ns > a ? (double)(f->done_ns - a) * 1e-6 : 0.0);
+        t_first = std::min(t_first, a);
+    }
+    double flops = 0;
     for (auto &f : s->folds) {
-        while (!__atomic_load_n(&f.rec->done, __ATOMIC_ACQUIRE)) {
+        if (!is_done(f.rec)) continue;
+        const int64_t b = f.trigger - s->rec_base;
+        if (b >= 0 && (size_t)b < s->arrivals.size()) {
+            const uint64_t a = s->arrivals[(size_t)b];
+            flat.push_back(f.rec->done_ns > a ? (double)(f.rec->done_ns - a) * 1e-6 : 0.0);
         }
-        uint64_t last_arrival = 0;
-        for (uint64_t a : f.arrivals) {
-            lat.push_back(f.rec->done_ns > a ? (double)(f.rec->done_ns - a) * 1e-6 : 0.0);
-            t_first = std::min(t_first, a);
-            last_arrival = std::max(last_arrival, a);
-        }
-        if (!f.arrivals.empty())
-            flat.push_back(f.rec->done_ns > last_arrival ? (double)(f.rec->done_ns - last_arrival) * 1e-6 : 0.0);
+        flops += f.flops;
         t_last = std::max(t_last, f.rec->done_ns);
     }
-    const double deadline = 1e3 * s->d.block_period_s * s->d.blocks_per_fold;
     xc_latency_stats r{};
     r.blocks = (int64_t)lat.size();
+    r.pending = pending;
     r.folds = (int64_t)flat.size();
     r.deadline_ms = deadline;
+    r.fold_deadline_ms = fold_deadline;
     r.p50_ms = xc_quantile(lat.data(), (int64_t)lat.size(), 0.50);
     r.p99_ms = xc_quantile(lat.data(), (int64_t)lat.size(), 0.99);
     r.max_ms = lat.empty() ? NAN : *std::max_element(lat.begin(), lat.end());
     r.fold_p50_ms = xc_quantile(flat.data(), (int64_t)flat.size(), 0.50);
     r.fold_p99_ms = xc_quantile(flat.data(), (int64_t)flat.size(), 0.99);
     r.fold_max_ms = flat.empty() ? NAN : *std::max_element(flat.begin(), flat.end());
-    for (double v : flat)
-        if (deadline > 0 && v > deadline) r.misses++;
     for (double v : lat)
-        if (deadline > 0 && v > deadline) r.block_misses++;
+        if (deadline > 0 && v > deadline) r.misses++;
+    for (double v : flat)
+        if (fold_deadline > 0 && v > fold_deadline) r.fold_misses++;
     const double span = (t_last > t_first && t_first != UINT64_MAX) ? (double)(t_last - t_first) * 1e-9 : 0.0;
-    r.tflops = span > 0 ? s->flops_per_fold * (double)s->folds.size() / span * 1e-12 : 0.0;
+    r.tflops = span > 0 ? flops / span * 1e-12 : 0.0;
     r.integrations = s->published_seq + 1;
     *stats = r;
     return XC_OK;
@@ -342,19 +564,27 @@ xc_status xc_stream_stats(xc_server *srv, int32_t id, xc_latency_stats *stats) {
 
 xc_status xc_stream_reset_stats(xc_server *srv, int32_t id) {
     if (!srv) return set_error(XC_ERR_INVALID_ARG, "null server");
+    hipStream_t hs;
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        Stream *s = get_stream(srv, id);
+        if (!s) return set_error(XC_ERR_INVALID_ARG, "no open stream %d", id);
+        hs = s->hs;
+    }
+    hipError_t e = hipStreamSynchronize(hs);
+    if (e != hipSuccess) return hip_error(e, "hipStreamSynchronize");
     std::lock_guard<std::mutex> lk(srv->mu);
     Stream *s = get_stream(srv, id);
-    if (!s) return set_error(XC_ERR_INVALID_ARG, "no open stream %d", id);
-    hipError_t e = hipStreamSynchronize(s->hs);
+    if (!s || s->hs != hs) return set_error(XC_ERR_STATE, "stream %d was closed during the call", id);
+    // folds enqueued by another thread after the wait may still run: wait for them too
+    e = hipStreamSynchronize(hs);
     if (e != hipSuccess) return hip_error(e, "hipStreamSynchronize");
-    for (auto &f : s->folds) {
-        while (!__atomic_load_n(&f.rec->done, __ATOMIC_ACQUIRE)) {
-        }
-    }
-    // ring slots still point at completed records: release them first
     for (auto &b : s->slot_busy) b = nullptr;
     for (auto &f : s->folds) delete f.rec;
     s->folds.clear();
+    s->arrivals.clear();
+    s->block_fold.clear();
+    s->rec_base = s->committed;
     return XC_OK;
 }
 

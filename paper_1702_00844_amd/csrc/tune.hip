@@ -1,6 +1,18 @@
 // Auto-tuning: the best tile configuration differs per platform and shape
-// (Section 2: tile size must be tuned to the architecture), so every valid
-// configuration is timed on the caller's buffers and the fastest is kept.
+// (Section 2: the tile size must be tuned to the architecture), so the
+// configurations of a shape are timed on the caller's buffers and the fastest
+// is kept for the shape's bucket (see TuneKey).
+//
+// The candidates span the kernel families and their parameters: matrix-core
+// blocks of 32 or 64 stations, direct-to-LDS or register staging (int8 and
+// 16-bit samples), one or two time groups and three or four real products
+// (complex float32 on 64-station matrix-core blocks), and for the vector-ALU
+// kernel every register tile w x h (w, h in {2, 4, 8}) with every time chunk
+// and time-group count.  Register tiles are pruned with Table 1 before any
+// timing: a tile needs at least 4 (1 + min(w, h)) + 8 w h registers, and the
+// ones that, with the kernel's staging and address registers, do not fit a
+// lane's 256 are dropped (8 x 4, 4 x 8, 8 x 8); a tile and its mirror image
+// cost the same on a square block pair, so only one of them is built.
 #include <cstdio>
 #include <cstring>
 #include <vector>
@@ -9,23 +21,67 @@
 
 using namespace xc;
 
-static std::vector<xc_config> candidates(xc_in_type in_type) {
+namespace {
+
+// Registers a vector-ALU lane needs beyond its Table 1 minimum: the sample
+// loads in flight for the next chunk (one float4 per 16-byte element, spread
+// over the workgroup) and about two dozen for addresses and loop state.
+int valu_overhead_regs(int w, int h, int tc, int ts) {
+    const int threads = (32 / w) * (32 / h) * ts;
+    const int loads = (tc * 64 + threads - 1) / threads;
+    return 4 * loads + 24;
+}
+
+std::vector<xc_config> candidates(xc_in_type in_type) {
     std::vector<xc_config> v;
-    v.push_back(xc_config{XC_KERNEL_MFMA, 32, 0, 0, 0, 0});
-    if (in_type != XC_IN_CF32) {   // both stagings (straight into LDS needs whole granules)
-        v.push_back(xc_config{XC_KERNEL_MFMA, 64, 0, 1, XC_STAGING_LDS, 0});
-        v.push_back(xc_config{XC_KERNEL_MFMA, 64, 0, 1, XC_STAGING_REGISTERS, 0});
-    } else {   // one or two time groups, four or three real products
-        for (int ts = 1; ts <= 2; ++ts)
-            for (int pr = XC_PRODUCT_FOUR; pr <= XC_PRODUCT_THREE; ++pr)
-                v.push_back(xc_config{XC_KERNEL_MFMA, 64, 0, ts, 0, pr});
-        const int opts[][2] = {{16, 1}, {16, 2}, {16, 4}, {32, 2}, {32, 4}, {32, 8}};
-        for (auto &o : opts) v.push_back(xc_config{XC_KERNEL_VALU, 32, o[0], o[1], 0, 0});
+    v.push_back(xc_config{XC_KERNEL_MFMA, 32, 0, 0, 0, 0, 0, 0});
+    if (in_type != XC_IN_CF32) {   // both stagings
+        v.push_back(xc_config{XC_KERNEL_MFMA, 64, 0, 1, XC_STAGING_LDS, 0, 0, 0});
+        v.push_back(xc_config{XC_KERNEL_MFMA, 64, 0, 1, XC_STAGING_REGISTERS, 0, 0, 0});
+        return v;
     }
+    // one or two time groups, four or three real products
+    for (int ts = 1; ts <= 2; ++ts)
+        for (int pr = XC_PRODUCT_FOUR; pr <= XC_PRODUCT_THREE; ++pr)
+            v.push_back(xc_config{XC_KERNEL_MFMA, 64, 0, ts, 0, pr, 0, 0});
+    const int tcts[][2] = {{16, 1}, {16, 2}, {16, 4}, {32, 2}, {32, 4}, {32, 8}};
+    for (int w = 2; w <= 8; w *= 2)
+        for (int h = 2; h <= w; h *= 2) {       // mirror images (h > w) cost the same
+            int64_t flops, bytes, regs;
+            if (xc_tile_cost(w, h, &flops, &bytes, &regs) != XC_OK) continue;
+            for (auto &o : tcts) {
+                if (regs + valu_overhead_regs(w, h, o[0], o[1]) > 256) continue;   // Table 1 pruning
+                if (!valu_available(w, h, o[0], o[1])) continue;
+                v.push_back(xc_config{XC_KERNEL_VALU, 32, o[0], o[1], 0, 0, w, h});
+            }
+        }
     return v;
 }
 
+}  // namespace
+
 extern "C" {
+
+int64_t xc_tune_candidates(xc_in_type in_type, xc_config *out, int64_t capacity) {
+    if (in_type < XC_IN_CF32 || in_type > XC_IN_CBF16) return -1;
+    const std::vector<xc_config> v = candidates(in_type);
+    for (int64_t k = 0; out && k < (int64_t)v.size() && k < capacity; ++k) out[k] = v[(size_t)k];
+    return (int64_t)v.size();
+}
+
+xc_status xc_tune_bucket(xc_in_type in_type, xc_out_type out_type, int32_t n_stations, int32_t n_channels,
+                         int32_t n_times, int32_t key[6]) {
+    if (!key) return set_error(XC_ERR_INVALID_ARG, "null key");
+    if (n_stations < 1 || n_channels < 1 || n_times < 1) return set_error(XC_ERR_INVALID_ARG, "sizes must be >= 1");
+    const TuneKey k = tune_bucket(in_type, out_type, n_stations, n_channels, n_times);
+    key[0] = k.in;
+    key[1] = k.out;
+    key[2] = k.sb;
+    key[3] = k.gran;
+    key[4] = k.tb;
+    key[5] = k.ub;
+    return XC_OK;
+}
 
 xc_status xc_autotune(const void *samples, xc_in_type in_type, int32_t n_stations, int32_t n_pol,
                       int32_t n_channels, int32_t n_times, void *vis, xc_out_type out_type, const char *cache_path,
@@ -79,15 +135,18 @@ xc_status xc_autotune(const void *samples, xc_in_type in_type, int32_t n_station
     if (!found) return last != XC_OK ? last : set_error(XC_ERR_UNSUPPORTED, "no configuration ran");
     *best = best_c;
     *best_ms = best_t;
-    tune_put(TuneKey{(int)in_type, (int)out_type, n_stations, n_channels, n_times}, best_c);
+    const TuneKey key = tune_bucket(in_type, out_type, n_stations, n_channels, n_times);
+    tune_put(key, best_c);
     if (cache_path) {
         FILE *f = fopen(cache_path, "a");
         if (f) {
             fprintf(f,
-                    "{\"in\": %d, \"out\": %d, \"S\": %d, \"C\": %d, \"T\": %d, \"kernel\": %d, \"block\": %d, "
-                    "\"time_chunk\": %d, \"time_split\": %d, \"staging\": %d, \"product\": %d, \"ms\": %.6f}\n",
-                    (int)in_type, (int)out_type, n_stations, n_channels, n_times, best_c.kernel, best_c.block,
-                    best_c.time_chunk, best_c.time_split, best_c.staging, best_c.product, best_t);
+                    "{\"in\": %d, \"out\": %d, \"sb\": %d, \"gran\": %d, \"tb\": %d, \"ub\": %d, \"kernel\": %d, "
+                    "\"block\": %d, \"time_chunk\": %d, \"time_split\": %d, \"staging\": %d, \"product\": %d, "
+                    "\"tile_w\": %d, \"tile_h\": %d, \"ms\": %.6f, \"S\": %d, \"C\": %d, \"T\": %d}\n",
+                    key.in, key.out, key.sb, key.gran, key.tb, key.ub, best_c.kernel, best_c.block,
+                    best_c.time_chunk, best_c.time_split, best_c.staging, best_c.product, best_c.tile_w,
+                    best_c.tile_h, best_t, n_stations, n_channels, n_times);
             fclose(f);
         }
     }
@@ -98,22 +157,27 @@ int64_t xc_tune_cache_load(const char *cache_path) {
     if (!cache_path) return -1;
     FILE *f = fopen(cache_path, "r");
     if (!f) return -1;
-    char line[512];
+    char line[1024];
     int64_t n = 0;
     while (fgets(line, sizeof line, f)) {
-        int in, out, S, C, T, k, b, tc, ts, sg, pr;
+        TuneKey key;
+        xc_config c;
         double ms;
+        int S, C, T;
         if (sscanf(line,
-                   " {\"in\": %d, \"out\": %d, \"S\": %d, \"C\": %d, \"T\": %d, \"kernel\": %d, \"block\": %d, "
-                   "\"time_chunk\": %d, \"time_split\": %d, \"staging\": %d, \"product\": %d, \"ms\": %lf",
-                   &in, &out, &S, &C, &T, &k, &b, &tc, &ts, &sg, &pr, &ms) == 12) {
-            xc_config c{k, b, tc, ts, sg, pr};
-            xc_config r;
-            if (xc_resolve_config(&c, (xc_in_type)in, (xc_out_type)out, S, 2, C, T, &r) == XC_OK) {
-                tune_put(TuneKey{in, out, S, C, T}, r);
-                ++n;
-            }
-        }
+                   " {\"in\": %d, \"out\": %d, \"sb\": %d, \"gran\": %d, \"tb\": %d, \"ub\": %d, \"kernel\": %d, "
+                   "\"block\": %d, \"time_chunk\": %d, \"time_split\": %d, \"staging\": %d, \"product\": %d, "
+                   "\"tile_w\": %d, \"tile_h\": %d, \"ms\": %lf, \"S\": %d, \"C\": %d, \"T\": %d",
+                   &key.in, &key.out, &key.sb, &key.gran, &key.tb, &key.ub, &c.kernel, &c.block, &c.time_chunk,
+                   &c.time_split, &c.staging, &c.product, &c.tile_w, &c.tile_h, &ms, &S, &C, &T) != 18)
+            continue;
+        // keep the entry only if it still resolves for the shape it was tuned on
+        xc_config r;
+        if (xc_resolve_config(&c, (xc_in_type)key.in, (xc_out_type)key.out, S, 2, C, T, &r) != XC_OK) continue;
+        const TuneKey k2 = tune_bucket(key.in, key.out, S, C, T);
+        if (!(k2 == key)) continue;
+        tune_put(key, r);
+        ++n;
     }
     fclose(f);
     return n;

@@ -6,18 +6,22 @@
 //  * The triangle of station pairs is split into square blocks of SB = 32
 //    stations (Section 4.5 blocks large triangles the same way).  One
 //    workgroup owns one (channel, block pair bi <= bj).
-//  * Each lane of a wave owns a 4 x 4 tile of station pairs (Table 1: 512
-//    flops per 128 bytes of samples, 148 registers minimum) and keeps its 64
-//    complex accumulators (4 x 4 stations x 2 x 2 polarisations) in registers.
-//    The 64 lanes cover the 8 x 8 tiles of a 32 x 32 block pair.
+//  * Each lane owns a TW x TH tile of station pairs (TW stations of block I,
+//    TH of block J; Table 1: 32 TW TH flops per 16 (TW + TH) bytes of samples,
+//    4 (1 + min(TW, TH)) + 8 TW TH registers minimum) and keeps its 4 TW TH
+//    complex accumulators (stations x 2 x 2 polarisations) in registers.  The
+//    (32 / TW) (32 / TH) lanes of a time group cover the tiles of a 32 x 32
+//    block pair (one wave for 4 x 4 and 8 x 2 tiles, two for 4 x 2, four for
+//    2 x 2).  The auto-tuner chooses the tile per shape among those whose
+//    Table 1 register count fits the register file.
 //  * Samples of both blocks are staged through LDS per chunk of TC time steps,
 //    loaded with coalesced 16-byte reads of the time-major layout (all stations
 //    of one time step together, Section 4.4) and double-buffered through
 //    registers: the next chunk's global loads are in flight while the current
 //    chunk is correlated.
-//  * TS waves share the block pair; wave w integrates time steps
-//    [w TC/TS, (w+1) TC/TS) of every chunk.  Their partial sums are added in
-//    LDS after the last chunk, in a fixed order (deterministic), and wave 0
+//  * TS time groups share the block pair; group g integrates time steps
+//    [g TC/TS, (g+1) TC/TS) of every chunk.  Their partial sums are added in
+//    LDS after the last chunk, in a fixed order (deterministic), and group 0
 //    stores each visibility once.
 //  * One complex multiply-accumulate is four FMAs (Section 2):
 //    re += a_r b_r + a_i b_i ; im += a_i b_r - a_r b_i.
@@ -29,10 +33,7 @@ namespace xc {
 namespace valu {
 
 constexpr int SB = 32;            // stations per block
-constexpr int TW = 4;             // tile: stations of block I per lane
-constexpr int TH = 4;             // tile: stations of block J per lane
 constexpr int ROW = 2 * SB + 4;   // float4 slots per staged time step (+1 pad per 16 stations)
-constexpr int NACC = TW * TH * 8; // floats of accumulators per lane
 
 // Slot of staged station s in [0, 2 SB): one pad slot after every 16 stations
 // so that the 8 distinct tile rows read by a quarter-wave hit distinct banks.
@@ -50,25 +51,33 @@ __device__ __forceinline__ void cmac(float &re, float &im, float ar, float ai, f
     im = fmaf(-ar, bi, im);
 }
 
-template <int TS, int TC>
+// Lanes of one time group: one per tile of the block pair.
+template <int TW, int TH>
+constexpr int lanes() { return (SB / TW) * (SB / TH); }
+
+template <int TW, int TH, int TS, int TC>
 __device__ __forceinline__ void unit(const Job &job, int c, int bi, int bj, Stage<TC> &st) {
-    static_assert(TC % TS == 0, "time chunk must split evenly over waves");
-    static_assert(sizeof(Stage<TC>) >= 64 * NACC * sizeof(float), "reduction area too small");
-    constexpr int NT = 64 * TS;
+    constexpr int NACC = TW * TH * 8;          // floats of accumulators per lane
+    constexpr int NL = lanes<TW, TH>();
+    static_assert(NL % 64 == 0, "a time group must be whole waves");
+    static_assert(TC % TS == 0, "time chunk must split evenly over time groups");
+    static_assert(sizeof(Stage<TC>) >= NL * NACC * sizeof(float), "reduction area too small");
+    constexpr int NT = NL * TS;
     constexpr int NELEM = TC * 2 * SB;
     constexpr int NLOAD = (NELEM + NT - 1) / NT;
 
     const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform across the wave
-    const int ti = lane & 7;
-    const int tj = lane >> 3;
+    const int lane = tid % NL;                                       // tile of this lane
+    const int wave = __builtin_amdgcn_readfirstlane(tid / NL);       // time group, uniform across the wave
+    const int ti = lane % (SB / TW);
+    const int tj = lane / (SB / TW);
     const int S = job.S;
     const int T = job.T;
     const bool diag = (bi == bj);
     const int I0 = bi * SB;
     const int J0 = bj * SB;
-    const bool active = !(diag && ti > tj);
+    // on a diagonal block pair, tiles wholly below the diagonal have no output
+    const bool active = !(diag && ti * TW > tj * TH + TH - 1);
     const int jbase = diag ? 0 : SB;
     const float4 *__restrict__ x = static_cast<const float4 *>(job.x);
 
@@ -135,19 +144,19 @@ __device__ __forceinline__ void unit(const Job &job, int c, int bi, int bj, Stag
         __syncthreads();
     }
 
-    // Add the partial sums of waves 1..TS-1 into wave 0, one wave per round.
+    // Add the partial sums of time groups 1..TS-1 into group 0, one group per round.
     if constexpr (TS > 1) {
         float *red = reinterpret_cast<float *>(&st.v[0][0][0]);
 #pragma unroll 1
         for (int w = 1; w < TS; ++w) {
             if (wave == w) {
 #pragma unroll
-                for (int f = 0; f < NACC; ++f) red[f * 64 + lane] = acc[f];
+                for (int f = 0; f < NACC; ++f) red[f * NL + lane] = acc[f];
             }
             __syncthreads();
             if (wave == 0) {
 #pragma unroll
-                for (int f = 0; f < NACC; ++f) acc[f] += red[f * 64 + lane];
+                for (int f = 0; f < NACC; ++f) acc[f] += red[f * NL + lane];
             }
             __syncthreads();
         }
@@ -184,64 +193,108 @@ __device__ __forceinline__ void unit(const Job &job, int c, int bi, int bj, Stag
     }
 }
 
-template <int TS, int TC>
-__global__ __launch_bounds__(64 * TS) void kernel(Job job, int nwork) {
+template <int TW, int TH, int TS, int TC>
+__global__ __launch_bounds__((lanes<TW, TH>() * TS)) void kernel(Job job, int nwork) {
     __shared__ Stage<TC> st;
     const int w = xcd_remap(blockIdx.x, nwork);
     if (w < 0) return;
     int c, bi, bj;
     unit_decode(job, w, c, bi, bj);
-    unit<TS, TC>(job, c, bi, bj, st);
+    unit<TW, TH, TS, TC>(job, c, bi, bj, st);
 }
 
 // Batch form: one workgroup per unit of a batch's unit list.
-template <int TS, int TC>
-__global__ __launch_bounds__(64 * TS) void kernel_batch(const Job *__restrict__ jobs,
-                                                         const Unit *__restrict__ units, const int *__restrict__ bounds) {
+template <int TW, int TH, int TS, int TC>
+__global__ __launch_bounds__((lanes<TW, TH>() * TS)) void kernel_batch(const Job *__restrict__ jobs,
+                                                                     const Unit *__restrict__ units,
+                                                                     const int *__restrict__ bounds) {
     __shared__ Stage<TC> st;
     const int u = batch_unit(bounds, blockIdx.x);
     if (u < 0) return;
     const Unit un = units[u];
     const Job job = jobs[un.item];
-    unit<TS, TC>(job, un.channel, un.bi, un.bj, st);
+    unit<TW, TH, TS, TC>(job, un.channel, un.bi, un.bj, st);
 }
 
-template <int TS, int TC>
+template <int TW, int TH, int TS, int TC>
 hipError_t launch_t(const Job &job, hipStream_t stream) {
     const int nwork = job_units(job);
-    hipLaunchKernelGGL((kernel<TS, TC>), dim3(xcd_grid(nwork)), dim3(64 * TS), 0, stream, job, nwork);
+    hipLaunchKernelGGL((kernel<TW, TH, TS, TC>), dim3(xcd_grid(nwork)), dim3(lanes<TW, TH>() * TS), 0, stream, job,
+                       nwork);
     return hipGetLastError();
 }
 
-template <int TS, int TC>
+template <int TW, int TH, int TS, int TC>
 hipError_t launch_batch_t(const Job *jobs, const Unit *units, const int *bounds, int grid, hipStream_t stream) {
-    hipLaunchKernelGGL((kernel_batch<TS, TC>), dim3(grid), dim3(64 * TS), 0, stream, jobs, units, bounds);
+    hipLaunchKernelGGL((kernel_batch<TW, TH, TS, TC>), dim3(grid), dim3(lanes<TW, TH>() * TS), 0, stream, jobs, units,
+                       bounds);
     return hipGetLastError();
+}
+
+// Every (tile, time chunk, time groups) the library builds: tiles 4 x 4,
+// 8 x 2, 4 x 2 and 2 x 2 (those of Table 1's shapes that divide a 32-station
+// block, whose register count leaves room for staging, and whose time groups
+// are whole waves), each with the (chunk, groups) pairs below, at most 1024
+// threads per workgroup.
+template <int TW, int TH, typename F>
+hipError_t dispatch_tc_ts(int tc, int ts, F &&f) {
+    constexpr int NL = lanes<TW, TH>();
+    if (tc == 16 && ts == 1) return f.template operator()<TW, TH, 1, 16>();
+    if (tc == 16 && ts == 2) return f.template operator()<TW, TH, 2, 16>();
+    if (tc == 16 && ts == 4) return f.template operator()<TW, TH, 4, 16>();
+    if (tc == 32 && ts == 2) return f.template operator()<TW, TH, 2, 32>();
+    if (tc == 32 && ts == 4) return f.template operator()<TW, TH, 4, 32>();
+    if constexpr (NL * 8 <= 1024)
+        if (tc == 32 && ts == 8) return f.template operator()<TW, TH, 8, 32>();
+    return hipErrorInvalidValue;
+}
+
+template <typename F>
+hipError_t dispatch(const Plan &plan, F &&f) {
+    const int w = plan.tile_w, h = plan.tile_h, tc = plan.time_chunk, ts = plan.time_split;
+    if (w == 4 && h == 4) return dispatch_tc_ts<4, 4>(tc, ts, f);
+    if (w == 8 && h == 2) return dispatch_tc_ts<8, 2>(tc, ts, f);
+    if (w == 4 && h == 2) return dispatch_tc_ts<4, 2>(tc, ts, f);
+    if (w == 2 && h == 2) return dispatch_tc_ts<2, 2>(tc, ts, f);
+    return hipErrorInvalidValue;
 }
 
 }  // namespace valu
 
+bool valu_available(int tile_w, int tile_h, int time_chunk, int time_split) {
+    const bool tile = (tile_w == 4 && tile_h == 4) || (tile_w == 8 && tile_h == 2) || (tile_w == 4 && tile_h == 2) ||
+                      (tile_w == 2 && tile_h == 2);
+    const int nl = (32 / tile_w) * (32 / tile_h);
+    const bool tcts = (time_chunk == 16 && (time_split == 1 || time_split == 2 || time_split == 4)) ||
+                      (time_chunk == 32 && (time_split == 2 || time_split == 4 || (time_split == 8 && nl * 8 <= 1024)));
+    return tile && tcts;
+}
+
+namespace {
+struct FlatLaunch {
+    const Job &job;
+    hipStream_t stream;
+    template <int TW, int TH, int TS, int TC>
+    hipError_t operator()() const { return valu::launch_t<TW, TH, TS, TC>(job, stream); }
+};
+struct BatchLaunch {
+    const Job *jobs;
+    const Unit *units;
+    const int *bounds;
+    int grid;
+    hipStream_t stream;
+    template <int TW, int TH, int TS, int TC>
+    hipError_t operator()() const { return valu::launch_batch_t<TW, TH, TS, TC>(jobs, units, bounds, grid, stream); }
+};
+}  // namespace
+
 hipError_t launch_valu(const Plan &plan, const Job &job, hipStream_t stream) {
-    const int ts = plan.time_split, tc = plan.time_chunk;
-    if (ts == 1 && tc == 16) return valu::launch_t<1, 16>(job, stream);
-    if (ts == 2 && tc == 16) return valu::launch_t<2, 16>(job, stream);
-    if (ts == 4 && tc == 16) return valu::launch_t<4, 16>(job, stream);
-    if (ts == 2 && tc == 32) return valu::launch_t<2, 32>(job, stream);
-    if (ts == 4 && tc == 32) return valu::launch_t<4, 32>(job, stream);
-    if (ts == 8 && tc == 32) return valu::launch_t<8, 32>(job, stream);
-    return hipErrorInvalidValue;
+    return valu::dispatch(plan, FlatLaunch{job, stream});
 }
 
 hipError_t launch_valu_batch(const Plan &plan, const Job *jobs, const Unit *units, const int *bounds, int grid,
                              hipStream_t stream) {
-    const int ts = plan.time_split, tc = plan.time_chunk;
-    if (ts == 1 && tc == 16) return valu::launch_batch_t<1, 16>(jobs, units, bounds, grid, stream);
-    if (ts == 2 && tc == 16) return valu::launch_batch_t<2, 16>(jobs, units, bounds, grid, stream);
-    if (ts == 4 && tc == 16) return valu::launch_batch_t<4, 16>(jobs, units, bounds, grid, stream);
-    if (ts == 2 && tc == 32) return valu::launch_batch_t<2, 32>(jobs, units, bounds, grid, stream);
-    if (ts == 4 && tc == 32) return valu::launch_batch_t<4, 32>(jobs, units, bounds, grid, stream);
-    if (ts == 8 && tc == 32) return valu::launch_batch_t<8, 32>(jobs, units, bounds, grid, stream);
-    return hipErrorInvalidValue;
+    return valu::dispatch(plan, BatchLaunch{jobs, units, bounds, grid, stream});
 }
 
 }  // namespace xc

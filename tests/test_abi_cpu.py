@@ -114,13 +114,14 @@ def test_config_resolution():
     F4, F3 = _lib.XC_PRODUCT_FOUR, _lib.XC_PRODUCT_THREE
     shp = (_lib.XC_IN_CF32, 256, 768, 64, 2)
     r = xe.resolve_config(shp, config={"kernel": _lib.XC_KERNEL_VALU})
-    assert r == {"kernel": 1, "block": 32, "time_chunk": 16, "time_split": 4, "staging": R, "product": F4}
+    assert r == {"kernel": 1, "block": 32, "time_chunk": 16, "time_split": 4, "staging": R, "product": F4,
+                 "tile_w": 4, "tile_h": 4}
     r = xe.resolve_config(shp, config={"kernel": _lib.XC_KERNEL_MFMA})
-    assert r == {"kernel": 2, "block": 64, "time_chunk": 32, "time_split": 2, "staging": L, "product": F3}
+    assert r == {"kernel": 2, "block": 64, "time_chunk": 32, "time_split": 2, "staging": L, "product": F3, "tile_w": 0, "tile_h": 0}
     r = xe.resolve_config((_lib.XC_IN_CF32, 1024, 1024, 256, 2), config={"kernel": _lib.XC_KERNEL_MFMA})
-    assert r == {"kernel": 2, "block": 64, "time_chunk": 16, "time_split": 1, "staging": L, "product": F3}
+    assert r == {"kernel": 2, "block": 64, "time_chunk": 16, "time_split": 1, "staging": L, "product": F3, "tile_w": 0, "tile_h": 0}
     r = xe.resolve_config(shp, config={"kernel": _lib.XC_KERNEL_MFMA, "block": 32})
-    assert r == {"kernel": 2, "block": 32, "time_chunk": 16, "time_split": 1, "staging": R, "product": F4}
+    assert r == {"kernel": 2, "block": 32, "time_chunk": 16, "time_split": 1, "staging": R, "product": F4, "tile_w": 0, "tile_h": 0}
     with pytest.raises(xe.XengineError):     # FP32 on 64-station blocks copies straight into LDS only
         xe.resolve_config(shp, config={"kernel": _lib.XC_KERNEL_MFMA, "staging": R})
     with pytest.raises(xe.XengineError):     # VALU stages through registers only
@@ -132,38 +133,38 @@ def test_config_resolution():
     # int8 and 16-bit on 64-station blocks: straight into LDS for every station
     # count (16- or 4-byte granules), through registers on request
     r = xe.resolve_config((_lib.XC_IN_CI8, 1024, 1024, 256, 2), _lib.XC_OUT_CI32)
-    assert r == {"kernel": 2, "block": 64, "time_chunk": 64, "time_split": 1, "staging": L, "product": F4}
+    assert r == {"kernel": 2, "block": 64, "time_chunk": 64, "time_split": 1, "staging": L, "product": F4, "tile_w": 0, "tile_h": 0}
     r = xe.resolve_config((_lib.XC_IN_CI8, 8, 64, 70, 2), _lib.XC_OUT_CI32)
-    assert r == {"kernel": 2, "block": 64, "time_chunk": 64, "time_split": 1, "staging": L, "product": F4}
+    assert r == {"kernel": 2, "block": 64, "time_chunk": 64, "time_split": 1, "staging": L, "product": F4, "tile_w": 0, "tile_h": 0}
     r = xe.resolve_config((_lib.XC_IN_CI8, 8, 64, 68, 2), _lib.XC_OUT_CI32, config={"kernel": 2, "staging": R})
-    assert r == {"kernel": 2, "block": 64, "time_chunk": 64, "time_split": 1, "staging": R, "product": F4}
+    assert r == {"kernel": 2, "block": 64, "time_chunk": 64, "time_split": 1, "staging": R, "product": F4, "tile_w": 0, "tile_h": 0}
     with pytest.raises(xe.XengineError):
         xe.resolve_config((_lib.XC_IN_CI8, 8, 64, 68, 2), config={"kernel": 2, "block": 32, "staging": L})
     with pytest.raises(xe.XengineError):
         xe.resolve_config((_lib.XC_IN_CI8, 8, 64, 68, 2), config={"kernel": 2, "time_chunk": 32})
     r = xe.resolve_config((_lib.XC_IN_CF16, 1024, 1024, 256, 2))
-    assert r == {"kernel": 2, "block": 64, "time_chunk": 32, "time_split": 1, "staging": L, "product": F4}
+    assert r == {"kernel": 2, "block": 64, "time_chunk": 32, "time_split": 1, "staging": L, "product": F4, "tile_w": 0, "tile_h": 0}
     r = xe.resolve_config((_lib.XC_IN_CBF16, 8, 64, 33, 2))
-    assert r == {"kernel": 2, "block": 64, "time_chunk": 32, "time_split": 1, "staging": L, "product": F4}
+    assert r == {"kernel": 2, "block": 64, "time_chunk": 32, "time_split": 1, "staging": L, "product": F4, "tile_w": 0, "tile_h": 0}
     r = xe.resolve_config((_lib.XC_IN_CBF16, 8, 64, 33, 2), config={"kernel": 2, "staging": R})
-    assert r == {"kernel": 2, "block": 64, "time_chunk": 32, "time_split": 1, "staging": R, "product": F4}
+    assert r == {"kernel": 2, "block": 64, "time_chunk": 32, "time_split": 1, "staging": R, "product": F4, "tile_w": 0, "tile_h": 0}
     with pytest.raises(xe.XengineError):
         xe.resolve_config((_lib.XC_IN_CI8, 4, 16, 8, 2), config={"kernel": _lib.XC_KERNEL_VALU})
     with pytest.raises(xe.XengineError):
         xe.resolve_config(shp, config={"kernel": _lib.XC_KERNEL_VALU, "time_split": 3})
     # the three-product form: complex-float32 on 64-station matrix-core blocks only
-    r = xe.resolve_config(shp, config={"kernel": _lib.XC_KERNEL_MFMA, "product": F4})
-    assert r == {"kernel": 2, "block": 64, "time_chunk": 32, "time_split": 2, "staging": L, "product": F4}
-    r = xe.resolve_config(shp, config={"kernel": _lib.XC_KERNEL_MFMA, "time_split": 1, "product": F3})
-    assert r == {"kernel": 2, "block": 64, "time_chunk": 16, "time_split": 1, "staging": L, "product": F3}
-    for bad in ({"kernel": _lib.XC_KERNEL_VALU, "product": F3}, {"kernel": 2, "block": 32, "product": F3},
+    r = xe.resolve_config(shp, config={"kernel": _lib.XC_KERNEL_MFMA, "product": F4, "tile_w": 0, "tile_h": 0})
+    assert r == {"kernel": 2, "block": 64, "time_chunk": 32, "time_split": 2, "staging": L, "product": F4, "tile_w": 0, "tile_h": 0}
+    r = xe.resolve_config(shp, config={"kernel": _lib.XC_KERNEL_MFMA, "time_split": 1, "product": F3, "tile_w": 0, "tile_h": 0})
+    assert r == {"kernel": 2, "block": 64, "time_chunk": 16, "time_split": 1, "staging": L, "product": F3, "tile_w": 0, "tile_h": 0}
+    for bad in ({"kernel": _lib.XC_KERNEL_VALU, "product": F3, "tile_w": 0, "tile_h": 0}, {"kernel": 2, "block": 32, "product": F3, "tile_w": 0, "tile_h": 0},
                 {"kernel": 2, "product": 3}, {"kernel": 2, "product": -1}):
         with pytest.raises(xe.XengineError):
             xe.resolve_config(shp, config=bad)
     with pytest.raises(xe.XengineError):
-        xe.resolve_config((_lib.XC_IN_CI8, 1024, 1024, 256, 2), _lib.XC_OUT_CI32, config={"product": F3})
+        xe.resolve_config((_lib.XC_IN_CI8, 1024, 1024, 256, 2), _lib.XC_OUT_CI32, config={"product": F3, "tile_w": 0, "tile_h": 0})
     with pytest.raises(xe.XengineError):
-        xe.resolve_config((_lib.XC_IN_CF16, 1024, 1024, 256, 2), config={"product": F3})
+        xe.resolve_config((_lib.XC_IN_CF16, 1024, 1024, 256, 2), config={"product": F3, "tile_w": 0, "tile_h": 0})
 
 
 def test_status_strings():
@@ -318,3 +319,53 @@ def test_station_major_validation():
         assert lib.xc_resolve_config(ctypes.byref(_lib.XcConfig(xe.XC_KERNEL_MFMA, 64, 0, 0, 0, 0)), 0, 0, S, 2, 3,
                                      50, ctypes.byref(r)) == 0
         assert (r.kernel, r.block) == (xe.XC_KERNEL_MFMA, 64)
+
+
+def test_tune_candidates_pruned_by_table1():
+    """The vector-ALU register tiles the tuner times are those of {2, 4, 8}^2
+    (one of each mirror pair) whose Table 1 register count, plus staging and
+    address registers, fits 256: 8 x 4, 4 x 8 and 8 x 8 are pruned."""
+    cands = xe.tune_candidates(_lib.XC_IN_CF32)
+    tiles = {(c["tile_w"], c["tile_h"]) for c in cands if c["kernel"] == _lib.XC_KERNEL_VALU}
+    assert tiles == {(4, 4), (8, 2), (4, 2), (2, 2)}
+    for w, h in [(8, 4), (8, 8)]:
+        assert xe.tile_cost(w, h)[2] > 256 - 24
+    for c in cands:        # every candidate resolves for a shape
+        r = xe.resolve_config((_lib.XC_IN_CF32, 4, 64, 40, 2), config=c)
+        assert r["kernel"] == c["kernel"]
+    i8 = xe.tune_candidates(_lib.XC_IN_CI8)
+    assert all(c["kernel"] == _lib.XC_KERNEL_MFMA for c in i8) and len(i8) == 3
+
+
+def test_tune_buckets():
+    b = lambda S, C, T, it=_lib.XC_IN_CI8: xe.tune_bucket(it, _lib.XC_OUT_CI32 if it == 1 else 0, S, C, T)
+    assert b(100, 500, 768) == b(120, 600, 700)          # same 32-station blocks, T and unit classes
+    assert b(100, 500, 768) != b(130, 500, 768)          # another station-block count
+    assert b(100, 500, 768) != b(101, 500, 768)          # 101 stations are not whole int8 copy granules
+    assert b(100, 500, 768) != b(100, 500, 2000)         # another integration-length class
+    assert b(100, 8, 768) != b(100, 500, 768)            # few units against a full device
+    assert b(100, 5000, 768) == b(100, 9000, 768)        # unit class capped
+    assert b(8, 16, 256, 0)[3] == 1                      # complex float32 is always whole granules
+    with pytest.raises(xe.XengineError):
+        xe.tune_bucket(0, 0, 0, 1, 1)
+
+
+def test_server_rejects_bad_stream_descriptions():
+    lib = _lib.load()
+    srv = ctypes.c_void_p()
+    assert lib.xc_server_create(1 << 30, ctypes.byref(srv)) == 0
+    sid = ctypes.c_int32()
+    bad = [dict(blocks_per_fold=3, blocks_per_integration=8),          # not a multiple
+           dict(ring_blocks=3, blocks_per_fold=2),                     # fewer than two folds of slots
+           dict(staggered=2), dict(n_pol=1), dict(block_times=0),
+           dict(acc_type=_lib.XC_OUT_CI32, block_times=512, blocks_per_integration=256)]   # int32 bound
+    for kw in bad:
+        a = dict(n_stations=8, n_channels=2, block_times=16, blocks_per_integration=4, blocks_per_fold=2,
+                 ring_blocks=4, in_type=_lib.XC_IN_CI8, acc_type=_lib.XC_OUT_CI32, staggered=1, n_pol=2,
+                 block_period_s=0.0)
+        a.update(kw)
+        d = _lib.XcStreamDesc(a["n_stations"], a["n_pol"], a["n_channels"], a["block_times"],
+                              a["blocks_per_integration"], a["blocks_per_fold"], a["ring_blocks"], a["in_type"],
+                              a["acc_type"], a["staggered"], a["block_period_s"])
+        assert lib.xc_stream_open(srv, ctypes.byref(d), ctypes.byref(sid)) != 0, kw
+    lib.xc_server_destroy(srv)

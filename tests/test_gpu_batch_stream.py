@@ -113,68 +113,168 @@ def test_autotune_and_cache(tmp_path):
     assert rel_err(gpu_vis_numpy(v), oracle_vis(x)) <= 1e-5
 
 
-# block_times 24: the int8 kernel's 32-step chunks straddle the ring slots of a fold
-@pytest.mark.parametrize("kind,bt", [("ci8", 32), ("ci8", 24), ("cf32", 32), ("cf16", 32), ("cbf16", 24)])
-def test_stream_integrations_match_oracle(kind, bt):
-    S, C, bpi, k = 20, 3, 6, 2
-    n_int = 2
+def _fill_slot(ptr, blk, kind, C, bt, S):
+    if kind == "ci8":
+        xe.device_tensor(ptr, (C, bt, S, 2, 2), torch.int8).copy_(blk)
+    elif kind != "cf32":
+        # 16-bit samples copied bit for bit (there is no bfloat16 array-interface type)
+        xe.device_tensor(ptr, (C, bt, S, 2, 2), torch.int16).copy_(blk.view(torch.int16))
+    else:
+        slot = xe.device_tensor(ptr, (C, bt, S, 2 * 2), torch.float32)
+        slot.copy_(torch.view_as_real(blk).reshape(C, bt, S, 4))
+
+
+def _acquire(srv, sid):
+    while True:
+        try:
+            return srv.acquire(sid)
+        except xe.XengineError as e:
+            assert e.status_name == "XC_ERR_BACKPRESSURE"
+            time.sleep(0.001)
+
+
+# block_times 24: the int8 kernel's 64-step chunks straddle the ring slots of a
+# fold; k = 3 with a ring of 7 slots makes folds wrap around the ring's end;
+# staggered folds give each channel group its own fold boundaries
+@pytest.mark.parametrize("kind,bt,k,ring,staggered,events", [
+    ("ci8", 32, 2, 4, False, False), ("ci8", 24, 2, 4, True, False), ("ci8", 24, 3, 7, True, True),
+    ("cf32", 32, 2, 4, True, True), ("cf32", 16, 3, 7, False, False), ("cf16", 32, 2, 5, True, False),
+    ("cbf16", 24, 2, 4, False, True)],
+    ids=["ci8_all", "ci8_stag", "ci8_stag_wrap_ev", "cf32_stag_ev", "cf32_all_wrap", "cf16_stag", "cbf16_all_ev"])
+def test_stream_integrations_match_oracle(kind, bt, k, ring, staggered, events):
+    """Every integration read back through xc_stream_integration (its ready
+    event waited on by a consumer stream) equals the oracle over its blocks;
+    with events, blocks are filled on a producer stream and committed with
+    xc_stream_commit_after, and every integration is released."""
+    S, C, bpi = 20, 5, 6
+    n_int = 3
     srv = xe.Server()
     in_type = {"ci8": xe.XC_IN_CI8, "cf32": xe.XC_IN_CF32, "cf16": xe.XC_IN_CF16, "cbf16": xe.XC_IN_CBF16}[kind]
     acc = xe.XC_OUT_CI32 if kind == "ci8" else xe.XC_OUT_CF32
-    d = xe.Server.desc(S, C, bt, bpi, blocks_per_fold=k, ring_blocks=4, in_type=in_type, acc_type=acc,
-                       block_period_s=0.001)
+    d = xe.Server.desc(S, C, bt, bpi, blocks_per_fold=k, ring_blocks=ring, in_type=in_type, acc_type=acc,
+                       block_period_s=0.001, staggered=staggered)
     sid = srv.open(d)
+    producer, consumer = torch.cuda.Stream(), torch.cuda.Stream()
     blocks = []
     for b in range(bpi * n_int):
         if kind == "cf32":
             blk = inputs.cn_gaussian(C, bt, S, seed=500 + b, device=DEV)
         else:
             # 16-bit samples hold the int8 values exactly, and every partial sum
-            # (at most 192 x 2 x 127^2 < 2^24) is exact in float32
+            # (at most 144 x 2 x 127^2 < 2^24) is exact in float32
             blk = inputs.ci8_gaussian(C, bt, S, seed=500 + b, device=DEV)
             if kind != "ci8":
                 blk = blk.to(torch.float16 if kind == "cf16" else torch.bfloat16)
         blocks.append(blk)
-        while True:
-            try:
-                ptr = srv.acquire(sid)
-                break
-            except xe.XengineError as e:
-                assert e.status_name == "XC_ERR_BACKPRESSURE"
-                time.sleep(0.001)
-        if kind == "ci8":
-            xe.device_tensor(ptr, (C, bt, S, 2, 2), torch.int8).copy_(blk)
-        elif kind != "cf32":
-            # 16-bit samples copied bit for bit (there is no bfloat16 array-interface type)
-            xe.device_tensor(ptr, (C, bt, S, 2, 2), torch.int16).copy_(blk.view(torch.int16))
+        ptr = _acquire(srv, sid)
+        if events:
+            producer.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(producer):
+                _fill_slot(ptr, blk, kind, C, bt, S)
+            srv.commit(sid, time.monotonic_ns(), producer_stream=producer)
         else:
-            slot = xe.device_tensor(ptr, (C, bt, S, 2 * 2), torch.float32)
-            slot.copy_(torch.view_as_real(blk).reshape(C, bt, S, 4))
-        torch.cuda.synchronize()
-        srv.commit(sid, time.monotonic_ns())
+            _fill_slot(ptr, blk, kind, C, bt, S)
+            torch.cuda.synchronize()
+            srv.commit(sid, time.monotonic_ns())
         if (b + 1) % bpi == 0:
-            st = srv.stats(sid)                 # waits for the folds
-            vptr, seq = srv.latest(sid)
-            assert seq == (b + 1) // bpi - 1
+            n = (b + 1) // bpi - 1
             shape = xe.vis_shape(C, S, acc)
-            got = xe.device_tensor(vptr, shape, torch.int32 if kind == "ci8" else torch.complex64)
+            with torch.cuda.stream(consumer):
+                vptr = srv.wait_integration(sid, n, stream=consumer)     # the host does not wait
+                got = xe.device_tensor(vptr, shape, torch.int32 if kind == "ci8" else torch.complex64).clone()
+                if events:
+                    srv.release(sid, n, stream=consumer)
+            consumer.synchronize()
             window = torch.cat(blocks[b + 1 - bpi:b + 1], dim=1)
             ref = oracle_vis(window.to(torch.int8) if kind in ("cf16", "cbf16") else window)
             if kind == "ci8":
-                assert np.array_equal(gpu_vis_numpy(got), ref)
+                assert np.array_equal(gpu_vis_numpy(got), ref), n
             elif kind in ("cf16", "cbf16"):
-                assert np.array_equal(gpu_vis_numpy(got), ref[..., 0] + 1j * ref[..., 1])
+                assert np.array_equal(gpu_vis_numpy(got), ref[..., 0] + 1j * ref[..., 1]), n
             else:
-                assert rel_err(gpu_vis_numpy(got), ref) <= 1e-5
+                assert rel_err(gpu_vis_numpy(got), ref) <= 1e-5, n
+            assert srv.latest(sid)[1] == n
+    with pytest.raises(xe.XengineError) as e:          # integration 0's buffer now holds integration 2
+        srv.integration(sid, 0)
+    assert e.value.status_name == "XC_ERR_STATE"
     st = srv.stats(sid)
-    assert st["blocks"] == bpi * n_int and st["integrations"] == n_int
-    assert st["folds"] == bpi * n_int // k
+    assert st["blocks"] == bpi * n_int and st["integrations"] == n_int and st["pending"] == 0
+    folds_per_int = (bpi if staggered else bpi // k) if C >= k else None
+    if folds_per_int is not None:
+        # staggered: one fold per block plus the end-of-integration folds of the other groups
+        expected = (bpi + (k - 1) if staggered else bpi // k) * n_int
+        assert st["folds"] == expected
     assert 0 <= st["p50_ms"] <= st["p99_ms"] <= st["max_ms"]
     assert 0 <= st["fold_p50_ms"] <= st["fold_p99_ms"] <= st["fold_max_ms"] <= st["max_ms"]
-    assert st["deadline_ms"] == pytest.approx(2.0)
+    assert st["deadline_ms"] == pytest.approx(1.0 * k)
+    assert st["fold_deadline_ms"] == pytest.approx(1.0 if staggered else 1.0 * k)
     srv.reset_stats(sid)
     assert srv.stats(sid)["blocks"] == 0
     srv.close_stream(sid)
+    srv.close()
+
+
+def test_stream_late_arrivals_are_misses():
+    """Miss accounting against a host clock moved by the test: blocks stamped
+    one second in the past exceed the k P deadline, blocks stamped in the
+    future complete before they 'arrive' (latency 0)."""
+    S, C, bt, bpi, k = 16, 4, 32, 4, 2
+    srv = xe.Server()
+    d = xe.Server.desc(S, C, bt, bpi, blocks_per_fold=k, ring_blocks=4, block_period_s=0.001)
+    sid = srv.open(d)
+    now = time.monotonic_ns()
+    for b in range(bpi):
+        ptr = srv.acquire(sid)
+        xe.device_tensor(ptr, (C, bt, S, 2, 2), torch.int8).zero_()
+        torch.cuda.synchronize()
+        srv.commit(sid, now - 1_000_000_000 if b < 2 else now + 60_000_000_000)
+    st = srv.stats(sid)
+    assert st["blocks"] == bpi
+    assert st["misses"] == 2
+    assert st["max_ms"] >= 1000.0
+    assert st["p50_ms"] == 0.0      # nearest rank of [0, 0, ~1000, ~1000]
+    srv.close()
+
+
+def test_stream_backpressure_is_deterministic():
+    """A held stream cannot finish its folds: once the ring's slots are all
+    waiting for folds, acquire returns XC_ERR_BACKPRESSURE, and it succeeds
+    again after the hold is released.  A hold that is never released ends at
+    its time limit."""
+    S, C, bt, bpi, k, ring = 16, 4, 32, 8, 2, 4
+    srv = xe.Server()
+    d = xe.Server.desc(S, C, bt, bpi, blocks_per_fold=k, ring_blocks=ring, staggered=False)
+    sid = srv.open(d)
+    blocks = [inputs.ci8_gaussian(C, bt, S, seed=900 + b, device=DEV) for b in range(bpi)]
+    torch.cuda.synchronize()
+    srv.hold(sid, 30.0)
+    for b in range(ring):                 # fill the ring: two folds wait behind the hold
+        ptr = srv.acquire(sid)
+        xe.device_tensor(ptr, (C, bt, S, 2, 2), torch.int8).copy_(blocks[b])
+        torch.cuda.current_stream().synchronize()      # not the device: the held stream must not be waited for
+        srv.commit(sid, time.monotonic_ns())
+    t0 = time.monotonic()
+    for _ in range(3):
+        with pytest.raises(xe.XengineError) as e:
+            srv.acquire(sid)
+        assert e.value.status_name == "XC_ERR_BACKPRESSURE"
+    srv.resume(sid)
+    for b in range(ring, bpi):
+        ptr = _acquire(srv, sid)
+        xe.device_tensor(ptr, (C, bt, S, 2, 2), torch.int8).copy_(blocks[b])
+        torch.cuda.current_stream().synchronize()      # not the device: the held stream must not be waited for
+        srv.commit(sid, time.monotonic_ns())
+    assert time.monotonic() - t0 < 20.0  # released by resume, not by the time limit
+    srv.stats(sid)
+    vptr, seq = srv.latest(sid)
+    assert seq == 0
+    got = xe.device_tensor(vptr, xe.vis_shape(C, S, xe.XC_OUT_CI32), torch.int32)
+    assert np.array_equal(gpu_vis_numpy(got), oracle_vis(torch.cat(blocks, dim=1)))
+    # a hold nobody releases ends by itself
+    srv.hold(sid, 0.05)
+    t0 = time.monotonic()
+    srv.stats(sid)
+    assert time.monotonic() - t0 < 5.0
     srv.close()
 
 
