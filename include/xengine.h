@@ -225,6 +225,28 @@ xc_status xc_correlate_split(const xc_config *cfg, const void *samples, xc_in_ty
                              int32_t accumulate, int32_t n_split, void *work, int64_t work_bytes, void *stream);
 
 /*
+ * xc_correlate_split without a workspace argument and without any allocation,
+ * for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the pieces'
+ * partial sums go to a fixed scratch array of XC_SPLIT_STATIC_SCRATCH_BYTES
+ * in device memory, one per device, that the library holds until the process
+ * ends (its device address is looked up on the first call on each device).
+ * The call makes no hipMalloc, hipFree or other allocating call, and it does
+ * not run the XC_CHECK scan (which allocates).  Every call on a device shares
+ * that device's scratch: calls that overlap on one device (different streams,
+ * or threads) race and may return wrong sums; serialise them.  The scratch
+ * keeps the last call's partial sums, which the next call overwrites
+ * completely (nothing needs clearing).  Errors as xc_correlate_split, and
+ * XC_ERR_UNSUPPORTED when K x C x B x 4 complex values (8 bytes each) exceed
+ * the scratch.  n_split = 1 (or T = 1) runs the unsplit kernel, with no
+ * scratch.
+ */
+#define XC_SPLIT_STATIC_SCRATCH_BYTES (64ll << 20)
+xc_status xc_correlate_split_static(const xc_config *cfg, const void *samples, xc_in_type in_type,
+                                    int32_t n_stations, int32_t n_pol, int32_t n_channels, int32_t n_times, void *vis,
+                                    xc_out_type out_type, int32_t accumulate, int32_t n_split, void *stream);
+
+/*
  * The same correlation from station-major samples, samples[C][S][T][P]
  * (device; each station's time series contiguous, the layout a station's
  * receiver produces; Section 4.4 discusses both layouts).  The corner turn to

@@ -141,14 +141,18 @@ def resolve_config(x_shape_type, out_type=XC_OUT_CF32, config=None) -> dict:
 
 
 def correlate_into(x: torch.Tensor, out: torch.Tensor, accumulate: bool = False, stream=None,
-                   config=None, split: int = 1, layout: int = XC_LAYOUT_TIME_MAJOR) -> torch.Tensor:
+                   config=None, split: int = 1, layout: int = XC_LAYOUT_TIME_MAJOR,
+                   static_scratch: bool = False) -> torch.Tensor:
     """out (+)= correlation of x; out dtype complex64 (XC_OUT_CF32) or int32 (XC_OUT_CI32).
     split > 1 cuts the integration into that many pieces, one set of
     workgroups each, and adds their partial sums in a fixed order (for
     workloads with few channels and stations); the workspace is a torch
     allocation on the device.  layout = XC_LAYOUT_STATION_MAJOR takes
     complex64 x[C, S, T, 2] (each station's series contiguous) and corner-turns
-    it in the kernel's copies into LDS (64-station matrix-core kernel)."""
+    it in the kernel's copies into LDS (64-station matrix-core kernel).
+    static_scratch = True runs the split through xc_correlate_split_static,
+    which allocates nothing: the partial sums go to the library's fixed
+    per-device scratch (calls on one device must not overlap)."""
     if layout == XC_LAYOUT_STATION_MAJOR:
         in_type, C, S, T, P = in_type_of(x)      # dims 1 and 2 are (S, T) here
         if split > 1:
@@ -173,6 +177,12 @@ def correlate_into(x: torch.Tensor, out: torch.Tensor, accumulate: bool = False,
         raise ValueError(f"out has shape {tuple(out.shape)}, expected {vis_shape(C, S, out_type, P)}")
     _require_device(x, out)
     cfg = _config(config)
+    if static_scratch:
+        st = lib().xc_correlate_split_static(ctypes.byref(cfg) if cfg else None, ctypes.c_void_p(x.data_ptr()),
+                                             in_type, S, P, C, T, ctypes.c_void_p(out.data_ptr()), out_type,
+                                             1 if accumulate else 0, int(split), _stream_ptr(stream))
+        _lib.check(st)
+        return out
     if split > 1:
         nbytes = lib().xc_correlate_split_bytes(S, P, C, T, split)
         if nbytes < 0:

@@ -20,6 +20,7 @@ XC_IN_CF32, XC_IN_CI8, XC_IN_CF16, XC_IN_CBF16 = 0, 1, 2, 3
 XC_OUT_CF32, XC_OUT_CI32 = 0, 1
 XC_KERNEL_AUTO, XC_KERNEL_VALU, XC_KERNEL_MFMA = 0, 1, 2
 XC_CI32_MAX_TIMES = 66572
+XC_SPLIT_STATIC_SCRATCH_BYTES = 64 << 20
 XC_PEAK_F32_MFMA16, XC_PEAK_F32_MFMA32, XC_PEAK_I8_MFMA, XC_PEAK_F16_MFMA, XC_PEAK_BF16_MFMA, XC_PEAK_F32_FMA, \
     XC_PEAK_HBM_COPY = range(7)
 
@@ -67,6 +68,8 @@ SIGNATURES = {
     "xc_correlate_split_bytes": (c_i64, [c_i32, c_i32, c_i32, c_i32, c_i32]),
     "xc_correlate_split": (c_i32, [ctypes.POINTER(XcConfig), c_vp, c_i32, c_i32, c_i32, c_i32, c_i32, c_vp, c_i32,
                                    c_i32, c_i32, c_vp, c_i64, c_vp]),
+    "xc_correlate_split_static": (c_i32, [ctypes.POINTER(XcConfig), c_vp, c_i32, c_i32, c_i32, c_i32, c_i32, c_vp,
+                                          c_i32, c_i32, c_i32, c_vp]),
     "xc_correlate_station_major": (c_i32, [ctypes.POINTER(XcConfig), c_vp, c_i32, c_i32, c_i32, c_i32, c_i32,
                                            c_vp, c_i32, c_i32, c_vp]),
     "xc_tile_cost": (c_i32, [c_i32, c_i32, ctypes.POINTER(c_i64), ctypes.POINTER(c_i64),

@@ -396,6 +396,31 @@ static xc_status split_run(const Plan &plan, const void *samples, xc_in_type in_
     return XC_OK;
 }
 
+// Scratch of xc_correlate_split_static: one array per device, kept until the
+// process ends.  Host code reaches it only through the device address that
+// hipGetSymbolAddress returns for the current device (the array's name in host
+// code is not a device address).
+static __device__ __align__(256) uint8_t scratch[XC_SPLIT_STATIC_SCRATCH_BYTES];
+static std::mutex g_scratch_mu;
+constexpr int kMaxDevices = 64;
+static void *g_scratch_dev[kMaxDevices];
+
+static xc_status static_scratch(void **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_error(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return set_error(XC_ERR_UNSUPPORTED, "device %d: too many devices", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return hip_error(e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)");
+        g_scratch_dev[dev] = p;
+    }
+    *out = g_scratch_dev[dev];
+    return XC_OK;
+}
+
 xc_status xc_correlate_split(const xc_config *cfg, const void *samples, xc_in_type in_type, int32_t n_stations,
                              int32_t n_pol, int32_t n_channels, int32_t n_times, void *vis, xc_out_type out_type,
                              int32_t accumulate, int32_t n_split, void *work, int64_t work_bytes, void *stream) {
@@ -417,6 +442,34 @@ xc_status xc_correlate_split(const xc_config *cfg, const void *samples, xc_in_ty
                          (long long)K * elems * 8);
     return split_run(plan, samples, in_type, n_stations, n_channels, n_times, vis, out_type, accumulate, K, work,
                      static_cast<hipStream_t>(stream));
+}
+
+xc_status xc_correlate_split_static(const xc_config *cfg, const void *samples, xc_in_type in_type,
+                                    int32_t n_stations, int32_t n_pol, int32_t n_channels, int32_t n_times, void *vis,
+                                    xc_out_type out_type, int32_t accumulate, int32_t n_split, void *stream) {
+    if (n_split < 1) return set_error(XC_ERR_INVALID_ARG, "n_split must be >= 1");
+    Plan plan;
+    xc_status st = resolve(cfg, in_type, out_type, n_stations, n_pol, n_channels, n_times, &plan);
+    if (st != XC_OK) return st;
+    if (!samples || !vis) return set_error(XC_ERR_INVALID_ARG, "null samples or vis pointer");
+    if (!aligned16(samples) || !aligned16(vis))
+        return set_error(XC_ERR_INVALID_ARG, "samples and vis must be 16-byte aligned");
+    if (accumulate != 0 && accumulate != 1) return set_error(XC_ERR_INVALID_ARG, "accumulate must be 0 or 1");
+    const int32_t K = split_pieces(n_times, n_split);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (K == 1) {
+        const Job job = make_job(samples, vis, n_stations, n_channels, n_times, plan.block, accumulate);
+        return launch_plan(plan, in_type, out_type, job, s);
+    }
+    const int64_t need = (int64_t)K * xc_vis_elems(n_stations, n_pol, n_channels) * 8;
+    if (need > (int64_t)XC_SPLIT_STATIC_SCRATCH_BYTES)
+        return set_error(XC_ERR_UNSUPPORTED, "%d pieces of %lld visibilities need %lld bytes of scratch, more than %lld",
+                         K, (long long)xc_vis_elems(n_stations, n_pol, n_channels), (long long)need,
+                         (long long)XC_SPLIT_STATIC_SCRATCH_BYTES);
+    void *work = nullptr;
+    st = static_scratch(&work);
+    if (st != XC_OK) return st;
+    return split_run(plan, samples, in_type, n_stations, n_channels, n_times, vis, out_type, accumulate, K, work, s);
 }
 
 xc_status xc_correlate_station_major(const xc_config *cfg, const void *samples, xc_in_type in_type,
