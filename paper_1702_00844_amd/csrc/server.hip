@@ -25,8 +25,9 @@
 //     folded every k blocks, but the device gets 1/k of the work every block
 //     period instead of all of it every k periods, so a block's last fold
 //     ends within (k - 1) P + (one fold of C/k channels) of its arrival.  At
-//     the end of an integration every group folds what it has left, so that
-//     the integration is complete when it is published.
+//     the end of an integration every group folds what it has left (oldest
+//     pending block first), so that the integration is complete when it is
+//     published.
 // A block's latency runs from its arrival to the completion of the last fold
 // that covers it; its deadline is D = k P.  A fold's latency runs from the
 // arrival of the block that triggered it to its completion, against the
@@ -387,13 +388,18 @@ static xc_status commit_locked(Stream *s, int32_t id, uint64_t arrival_ns, hipSt
             s->group_next[0] = n + 1;
         }
     } else {
-        // group m mod k folds its outstanding blocks; at the end of the
-        // integration every group does
-        const int g0 = (int)(m % k);
-        for (int i = 0; i < s->groups && st == XC_OK; ++i) {
-            const int g = (g0 + 1 + i) % s->groups;     // group g0 last: its fold is the regular one
-            if (!(last || g == g0) || s->group_next[g] > n) continue;
+        // group m mod k folds its outstanding blocks.  At the end of the
+        // integration every group does, in the order of their oldest pending
+        // block (the regular group's k blocks first, then the others' shorter
+        // remainders), so that each block's last fold comes as early as it can.
+        std::vector<int> order;
+        for (int g = 0; g < s->groups; ++g)
+            if ((last || g == (int)(m % k)) && s->group_next[g] <= n) order.push_back(g);
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int a, int b) { return s->group_next[a] < s->group_next[b]; });
+        for (int g : order) {
             st = enqueue_fold(*s, g, s->group_next[g], n, n);
+            if (st != XC_OK) break;
             s->group_next[g] = n + 1;
         }
     }
