@@ -115,7 +115,7 @@ def test_config_resolution():
     shp = (_lib.XC_IN_CF32, 256, 768, 64, 2)
     r = xe.resolve_config(shp, config={"kernel": _lib.XC_KERNEL_VALU})
     assert r == {"kernel": 1, "block": 32, "time_chunk": 16, "time_split": 4, "staging": R, "product": F4,
-                 "tile_w": 4, "tile_h": 4}
+                 "tile_w": 4, "tile_h": 2}
     r = xe.resolve_config(shp, config={"kernel": _lib.XC_KERNEL_MFMA})
     assert r == {"kernel": 2, "block": 64, "time_chunk": 32, "time_split": 2, "staging": L, "product": F3, "tile_w": 0, "tile_h": 0}
     r = xe.resolve_config((_lib.XC_IN_CF32, 1024, 1024, 256, 2), config={"kernel": _lib.XC_KERNEL_MFMA})

@@ -20,6 +20,9 @@ FP32_TOL = 1e-5
 
 VALU = [dict(kernel=xe.XC_KERNEL_VALU, time_chunk=tc, time_split=ts)
         for tc, ts in [(16, 1), (16, 2), (16, 4), (32, 2), (32, 4), (32, 8)]]
+# the other register tiles (the default is 4 x 2)
+VALU += [dict(kernel=xe.XC_KERNEL_VALU, tile_w=w, tile_h=h, time_chunk=tc, time_split=ts)
+         for w, h in [(4, 4), (8, 2), (2, 2)] for tc, ts in [(16, 1), (32, 4)]]
 MFMA = dict(kernel=xe.XC_KERNEL_MFMA)
 # complex-float32 matrix-core variants: 32x32 tiles on 32-station blocks, and
 # 16x16 tiles on 64-station blocks with one or two time groups, each with the
@@ -39,7 +42,8 @@ def _cf32(S, C, T, seed):
 
 def _cfg_id(c):
     if c["kernel"] == xe.XC_KERNEL_VALU:
-        return "valu_tc%d_ts%d" % (c["time_chunk"], c["time_split"])
+        tile = "_t%dx%d" % (c["tile_w"], c["tile_h"]) if "tile_w" in c else ""
+        return "valu_tc%d_ts%d%s" % (c["time_chunk"], c["time_split"], tile)
     return "mfma_b%d_ts%d%s" % (c.get("block", 0), c.get("time_split", 0),
                                 "_p4" if c.get("product") == xe.XC_PRODUCT_FOUR else "")
 
