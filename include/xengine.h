@@ -250,15 +250,17 @@ xc_status xc_correlate_split_static(const xc_config *cfg, const void *samples, x
  * The same correlation from station-major samples, samples[C][S][T][P]
  * (device; each station's time series contiguous, the layout a station's
  * receiver produces; Section 4.4 discusses both layouts).  The corner turn to
- * time-major order happens in the copies into LDS, so there is no transposed
- * copy in device memory: the kernel's LDS image, and hence the result bit for
- * bit, are those of xc_correlate_config on the time-major block.  Complex
- * float32 samples, on the 64-station matrix-core kernel (kernel AUTO or
- * XC_KERNEL_MFMA, block 0 or 64; cfg may set its time split and product form)
- * or on the vector-ALU kernel (XC_KERNEL_VALU, whose loads into registers do
- * the corner turn the same way).  Errors as for xc_correlate_config, and
- * XC_ERR_UNSUPPORTED for another sample type or the 32-station matrix-core
- * kernel.  Allocates nothing.
+ * time-major order happens in the copies into LDS (or the vector-ALU
+ * kernel's loads), so there is no transposed copy in device memory: the
+ * kernel's LDS image, and hence the result bit for bit, are those of
+ * xc_correlate_config on the time-major block.  Kernels: complex float32 on
+ * the 64-station matrix-core kernel (kernel AUTO or XC_KERNEL_MFMA, block 0
+ * or 64; cfg may set its time split and product form) or on the vector-ALU
+ * kernel (XC_KERNEL_VALU); int8 and 16-bit samples on the 64-station
+ * direct-to-LDS matrix-core kernel, in 4-byte copies (one station's word per
+ * lane, gathered from 64 station series per copy).  Errors as for
+ * xc_correlate_config, and XC_ERR_UNSUPPORTED for the 32-station or
+ * register-staged matrix-core kernels.  Allocates nothing.
  */
 xc_status xc_correlate_station_major(const xc_config *cfg, const void *samples, xc_in_type in_type,
                                      int32_t n_stations, int32_t n_pol, int32_t n_channels, int32_t n_times,

@@ -478,15 +478,20 @@ xc_status xc_correlate_split_static(const xc_config *cfg, const void *samples, x
 xc_status xc_correlate_station_major(const xc_config *cfg, const void *samples, xc_in_type in_type,
                                      int32_t n_stations, int32_t n_pol, int32_t n_channels, int32_t n_times,
                                      void *vis, xc_out_type out_type, int32_t accumulate, void *stream) {
-    if (in_type != XC_IN_CF32)
-        return set_error(XC_ERR_UNSUPPORTED, "station-major input: complex float32 samples only");
     // the kernels whose sample loads take either layout: the 64-station
-    // matrix-core kernel (copies into LDS) and the vector-ALU kernel
+    // matrix-core kernels that copy straight into LDS (complex float32 16 x 16
+    // tiles; int8 and 16-bit samples in 4-byte copies) and the vector-ALU
+    // kernel (complex float32)
     xc_config c = cfg ? *cfg : xc_config{};
     if (c.kernel == XC_KERNEL_AUTO) c.kernel = XC_KERNEL_MFMA;
     if (c.kernel == XC_KERNEL_MFMA && c.block != 0 && c.block != 64)
         return set_error(XC_ERR_UNSUPPORTED, "station-major input: the matrix-core kernel on 64-station blocks only");
     if (c.kernel == XC_KERNEL_MFMA) c.block = 64;
+    if (in_type != XC_IN_CF32 && c.kernel == XC_KERNEL_MFMA) {
+        if (c.staging == XC_STAGING_REGISTERS)
+            return set_error(XC_ERR_UNSUPPORTED, "station-major int8 / 16-bit input is copied straight into LDS");
+        c.staging = XC_STAGING_LDS;
+    }
     Plan plan;
     xc_status st = resolve(&c, in_type, out_type, n_stations, n_pol, n_channels, n_times, &plan);
     if (st != XC_OK) return st;
@@ -498,7 +503,13 @@ xc_status xc_correlate_station_major(const xc_config *cfg, const void *samples, 
     if (accumulate != 0 && accumulate != 1) return set_error(XC_ERR_INVALID_ARG, "accumulate must be 0 or 1");
     Job job = make_job(samples, vis, n_stations, n_channels, n_times, plan.block, accumulate);
     job.sstride = n_times;
-    return launch_plan(plan, in_type, out_type, job, static_cast<hipStream_t>(stream));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (in_type != XC_IN_CF32) {
+        const hipError_t e = launch_mfma_dma_station_major(in_type, out_type, job, s);
+        if (e != hipSuccess) return hip_error(e, "kernel launch");
+        return XC_OK;
+    }
+    return launch_plan(plan, in_type, out_type, job, s);
 }
 
 xc_status xc_correlate(const void *samples, xc_in_type in_type, int32_t n_stations, int32_t n_pol,

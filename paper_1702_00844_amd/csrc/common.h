@@ -44,8 +44,9 @@ struct Job {
     // Station-major input (x[C][S][T][2]: each station's time series
     // contiguous): station-samples from one station's series to the next;
     // 0 for the time-major layout.  Read by the 16 x 16 complex-float32
-    // matrix-core kernel (its copies into LDS do the corner turn) and the
-    // vector-ALU kernel (its loads into registers do).
+    // matrix-core kernel and the int8 / 16-bit direct-to-LDS kernel (their
+    // copies into LDS do the corner turn) and the vector-ALU kernel (its
+    // loads into registers do).
     int64_t sstride;
 };
 
@@ -152,6 +153,10 @@ hipError_t launch_mfma(const Plan &plan, xc_in_type in_type, xc_out_type out_typ
 // LDS (16-byte granules when n_stations is a multiple of 4 for int8 or of 2
 // for 16-bit samples, 4-byte granules otherwise).
 hipError_t launch_mfma_dma(xc_in_type in_type, xc_out_type out_type, const Job &job, hipStream_t stream);
+// The same from station-major samples x[C][S][T][2] (job.sstride = T): 4-byte
+// copies gather each station's word from its own series (same LDS image).
+hipError_t launch_mfma_dma_station_major(xc_in_type in_type, xc_out_type out_type, const Job &job,
+                                         hipStream_t stream);
 // g4: the items' station counts are not multiples of dma_granule (4-byte copies).
 hipError_t launch_mfma_dma_batch(xc_in_type in_type, xc_out_type out_type, const Job *jobs, const Unit *units,
                                  const int *bounds, int grid, bool g4, hipStream_t stream);

@@ -149,8 +149,14 @@ __device__ __forceinline__ ACC mma(const v4i &a, const v4i &b, const ACC &c) {
 // copies for the same LDS image.  The swizzle is applied on the source side:
 // the word landing at byte 4 L of the row is the one the 16-byte-granule copy
 // would have put there.
-template <int KIND, typename OUT, bool G4>
+//
+// SM: station-major input x[C][S][T][2] (each station's series contiguous,
+// job.sstride = T): the 4-byte copies take each lane's word from its
+// station's own series, so the LDS image, and hence the result, is that of
+// the time-major input.
+template <int KIND, typename OUT, bool G4, bool SM = false>
 __device__ __forceinline__ void unit(const Job &job, int c, int bi, int bj, uint8_t *lds_generic) {
+    static_assert(G4 || !SM, "station-major input is copied in 4-byte granules");
     typedef Geo<KIND> G;
     typedef typename Acc<KIND>::type acc_t;
     const lds_u8 *lds = (const lds_u8 *)lds_generic;
@@ -191,6 +197,7 @@ __device__ __forceinline__ void unit(const Job &job, int c, int bi, int bj, uint
     constexpr int NC4 = G::KT / 2 * IPR;                // copies per wave and chunk (half on the diagonal)
     const int nload4 = diag ? NC4 / 2 : NC4;
     uint32_t woff[4];     // byte offset of the lane's word within a time row, per combination
+    size_t soff[SM ? 4 : 1];   // station-major: byte offset of the lane's word at time 0 of its station
     if constexpr (G4) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
@@ -200,6 +207,8 @@ __device__ __forceinline__ void unit(const Job &job, int c, int bi, int bj, uint
             const int st = (blk ? J0 : I0) + G::GS * gl + (G::I8 ? lane % 4 : (lane % 4) / 2);
             const int stw = st < S ? st : S - 1;
             woff[v] = (uint32_t)(stw * G::SAMPLE + (G::I8 ? 0 : 4 * (lane & 1)));
+            if constexpr (SM)
+                soff[v] = ((size_t)c * job.cstride + (size_t)stw * job.sstride) * G::SAMPLE + (G::I8 ? 0 : 4 * (lane & 1));
         }
     }
     auto combo = [&](int i) { return G::I8 ? (i & 3) : (((i >> 3) & 1) * 2 + (i & 1)); };
@@ -207,7 +216,16 @@ __device__ __forceinline__ void unit(const Job &job, int c, int bi, int bj, uint
     auto issue = [&](int ch) {
         const int t0 = ch * G::KT;
         const uint32_t dst = dst0 + (ch % NSTAGE) * STAGE;
-        if constexpr (G4) {
+        if constexpr (SM) {
+#pragma unroll
+            for (int i = 0; i < NC4; ++i) {
+                if (i >= nload4) break;
+                const int t = t0 + rbase + i / IPR;
+                const void *src = t < T ? static_cast<const void *>(x + soff[combo(i)] + (size_t)t * G::SAMPLE)
+                                        : static_cast<const void *>(g_zero16);
+                dma4(src, dst + (i / IPR) * G::ROWB + (i % IPR) * 256);
+            }
+        } else if constexpr (G4) {
             if (t0 + G::KT <= T && rows_contiguous(job, t0, G::KT)) {
                 const uint8_t *src = x + (row_offset(job, c, t0) + (size_t)rbase * S) * G::SAMPLE;
 #pragma unroll
@@ -330,14 +348,14 @@ __device__ __forceinline__ void unit(const Job &job, int c, int bi, int bj, uint
             }
 }
 
-template <int KIND, typename OUT, bool G4>
+template <int KIND, typename OUT, bool G4, bool SM = false>
 __global__ __launch_bounds__(256, 2) void kernel(Job job, int nwork) {
     __shared__ __attribute__((aligned(16))) uint8_t lds[LDS_BYTES];
     const int w = xcd_remap(blockIdx.x, nwork);
     if (w < 0) return;
     int c, bi, bj;
     unit_decode(job, w, c, bi, bj);
-    unit<KIND, OUT, G4>(job, c, bi, bj, lds);
+    unit<KIND, OUT, G4, SM>(job, c, bi, bj, lds);
 }
 
 template <int KIND, typename OUT, bool G4>
@@ -358,6 +376,12 @@ hipError_t launch_t(const Job &job, hipStream_t stream) {
         hipLaunchKernelGGL((kernel<KIND, OUT, true>), dim3(xcd_grid(nwork)), dim3(256), 0, stream, job, nwork);
     else
         hipLaunchKernelGGL((kernel<KIND, OUT, false>), dim3(xcd_grid(nwork)), dim3(256), 0, stream, job, nwork);
+    return hipGetLastError();
+}
+template <int KIND, typename OUT>
+hipError_t launch_sm_t(const Job &job, hipStream_t stream) {
+    const int nwork = job_units(job);
+    hipLaunchKernelGGL((kernel<KIND, OUT, true, true>), dim3(xcd_grid(nwork)), dim3(256), 0, stream, job, nwork);
     return hipGetLastError();
 }
 template <int KIND, typename OUT>
@@ -383,6 +407,13 @@ hipError_t launch_batch_t(const Job *jobs, const Unit *units, const int *bounds,
 hipError_t launch_mfma_dma(xc_in_type in_type, xc_out_type out_type, const Job &job, hipStream_t stream) {
     using namespace dma;
     XC_DMA_DISPATCH(launch_t, job, stream)
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_mfma_dma_station_major(xc_in_type in_type, xc_out_type out_type, const Job &job,
+                                         hipStream_t stream) {
+    using namespace dma;
+    XC_DMA_DISPATCH(launch_sm_t, job, stream)
     return hipErrorInvalidValue;
 }
 

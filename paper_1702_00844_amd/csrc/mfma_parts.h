@@ -2,8 +2,9 @@
 // geometry of a (sample type, block size) variant, staging of time chunks
 // (global -> registers -> LDS, with the corner turn for 8- and 16-bit
 // samples), one chunk of MFMAs for a wave's quadrant, and the tile stores.
-// The kernels themselves are in mfma.hip (four waves per workgroup) and
-// mfma_ws.hip (four compute waves fed by four loader waves).
+// The kernels themselves are in mfma.hip (register staging, four waves per
+// workgroup) and mfma_dma.hip (copies straight into LDS), which also uses the
+// tile stores.
 #pragma once
 #include "common.h"
 

@@ -18,9 +18,12 @@
 //    are loaded into registers at once, coalesced (a frame is N consecutive
 //    samples), so that the block waits for memory once;
 //    the branch outputs of the block's frames go to LDS and are transformed
-//    there by a radix-2 Stockham FFT (two ping-pong buffers, twiddles from a
-//    table computed on the host in double precision), then weighted and
-//    written as rows of N channels per frame: y[stream][t][k].
+//    there: for N = 256 by a four-step 16 x 16 FFT (16-point DFTs in
+//    registers, the W_256 twiddle between the passes, LDS rows padded against
+//    bank conflicts), for N = 512 by a radix-2 Stockham FFT in two ping-pong
+//    LDS buffers; twiddles come from a table computed on the host in double
+//    precision.  The channels are then weighted and written as rows of N
+//    channels per frame: y[stream][t][k].
 //  * the corner turn y[stream][t][k] -> x[k][t][stream] through LDS tiles
 //    (transpose.h): coalesced on both sides.
 #include <cmath>

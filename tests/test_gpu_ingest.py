@@ -155,8 +155,38 @@ def test_station_major_against_oracle_with_accumulation():
     assert rel_err(gpu_vis_numpy(out), oracle_vis(torch.cat([x1, x2], dim=1))) <= 1e-5
 
 
-def test_station_major_rejects_other_sample_types():
-    xi = _station_major(_samples("ci8", 2, 40, 12, seed=933))
-    with pytest.raises(xe.XengineError) as e:
-        xe.correlate(xi, layout=SM)
-    assert e.value.status_name == "XC_ERR_UNSUPPORTED"
+@pytest.mark.parametrize("kind", ["ci8", "cf16", "cbf16"])
+@pytest.mark.parametrize("shape", [(2, 64, 64), (1, 130, 97), (3, 20, 5), (2, 251, 300), (1, 1, 7)],
+                         ids=lambda s: "C%d_S%d_T%d" % s)
+def test_station_major_int8_16bit_matches_time_major(kind, shape):
+    """int8 and 16-bit station-major input: the 4-byte copies gather each
+    station's word from its own series into the time-major kernel's LDS image,
+    so the result equals the time-major kernel's bit for bit (and the oracle:
+    int8 and integer-valued 16-bit samples are exact), for ragged station
+    counts, ragged time tails and diagonal and off-diagonal block pairs."""
+    C, S, T = shape
+    x = _samples(kind, C, T, S, seed=950 + S + T)
+    ref = xe.correlate(x)
+    got = xe.correlate(_station_major(x), layout=SM)
+    assert torch.equal(_bits(got), _bits(ref))
+    xo = x.to(torch.int8) if kind != "ci8" else x
+    o = oracle_vis(xo)
+    g = gpu_vis_numpy(got)
+    if kind == "ci8":
+        assert np.array_equal(g, o)
+    else:
+        assert np.array_equal(g, o[..., 0] + 1j * o[..., 1])
+
+
+def test_station_major_int8_accumulates_and_rejects_register_staging():
+    C, S, T = 2, 68, 200
+    x1 = _samples("ci8", C, T, S, seed=961)
+    x2 = _samples("ci8", C, 33, S, seed=962)
+    out = xe.correlate(_station_major(x1), layout=SM)
+    xe.correlate(_station_major(x2), out=out, accumulate=True, layout=SM)
+    assert np.array_equal(gpu_vis_numpy(out), oracle_vis(torch.cat([x1, x2], dim=1)))
+    for cfg in ({"kernel": xe.XC_KERNEL_MFMA, "staging": xe.XC_STAGING_REGISTERS},
+                {"kernel": xe.XC_KERNEL_MFMA, "block": 32}, {"kernel": xe.XC_KERNEL_VALU}):
+        with pytest.raises(xe.XengineError) as e:
+            xe.correlate(_station_major(x1), layout=SM, config=cfg)
+        assert e.value.status_name in ("XC_ERR_UNSUPPORTED", "XC_ERR_INVALID_ARG")
