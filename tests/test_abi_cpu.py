@@ -294,8 +294,9 @@ def test_split_workspace_and_validation():
 
 def test_station_major_validation():
     """The station-major entry point takes complex float32 on the 64-station
-    matrix-core kernel or the vector-ALU kernel, and rejects everything else
-    before any launch."""
+    matrix-core kernel or the vector-ALU kernel, int8 and 16-bit samples on the
+    64-station direct-to-LDS kernel, and rejects everything else before any
+    launch."""
     lib = _lib.load()
     X, V = VP(1 << 20), VP(2 << 20)
 
@@ -304,8 +305,14 @@ def test_station_major_validation():
                                               out_type, acc, None)
 
     unsupported, invalid = 2, 1
-    assert call(None, in_type=xe.XC_IN_CI8, out_type=xe.XC_OUT_CI32) == unsupported
-    assert call(None, in_type=xe.XC_IN_CF16) == unsupported
+    # int8 and 16-bit: accepted (a null pointer then fails the argument check)
+    assert call(None, in_type=xe.XC_IN_CI8, out_type=xe.XC_OUT_CI32, x=None) == invalid
+    assert call(None, in_type=xe.XC_IN_CF16, x=None) == invalid
+    # but not on the register-staged, 32-station or vector-ALU kernels
+    assert call(_lib.XcConfig(xe.XC_KERNEL_MFMA, 64, 0, 0, xe.XC_STAGING_REGISTERS, 0), in_type=xe.XC_IN_CI8,
+                out_type=xe.XC_OUT_CI32) == unsupported
+    assert call(_lib.XcConfig(xe.XC_KERNEL_MFMA, 32, 0, 0, 0, 0), in_type=xe.XC_IN_CBF16) == unsupported
+    assert call(_lib.XcConfig(xe.XC_KERNEL_VALU, 0, 0, 0, 0, 0), in_type=xe.XC_IN_CF16) == unsupported
     assert call(_lib.XcConfig(xe.XC_KERNEL_VALU, 0, 0, 0, 0, 0), x=None) == invalid   # VALU takes it
     assert call(_lib.XcConfig(xe.XC_KERNEL_MFMA, 32, 0, 0, 0, 0)) == unsupported
     assert call(None, P=3) == unsupported
