@@ -359,6 +359,9 @@ def main():
     ap.add_argument("--stream-multi-blocks", type=int, default=384)
     ap.add_argument("--no-oracle-timing", action="store_true", help="skip the oracle timing on every workload")
     ap.add_argument("--no-precision", action="store_true", help="skip the 16-bit error measurement")
+    ap.add_argument("--no-fengine", action="store_true", help="skip the filter-bank measurement")
+    ap.add_argument("--no-small-launch", action="store_true", help="skip the 8-station launch-latency measurement")
+    ap.add_argument("--paths-steps", type=int, default=10, help="timed launches per 256-station kernel path")
     ap.add_argument("--stream-only", action="store_true", help="run only the streaming measurements")
     ap.add_argument("--batch-only", action="store_true", help="run only the batch measurement")
     ap.add_argument("--no-ingest", action="store_true", help="skip the host-ingest measurement")
@@ -464,7 +467,7 @@ def main():
     if not args.no_compare and args.workload == "lofar64":
         del x, out
         torch.cuda.empty_cache()
-        res["paths"] = compare_paths(xe, inputs, torch, dev, stream)
+        res["paths"] = compare_paths(xe, inputs, torch, dev, stream, steps=args.paths_steps)
 
     if not args.no_compare and args.workload == "lofar64":
         if args.batch != "none":
@@ -473,8 +476,10 @@ def main():
         res.update(stream_all(xe, inputs, torch, args))
         if not args.no_ingest:
             res["ingest"] = ingest_bench(xe, inputs, torch, dev, stream)
-        res["fengine"] = fengine_bench(xe, inputs, torch, dev, stream)
-        res["small_launch"] = small_launch_bench(xe, inputs, torch, dev, stream)
+        if not args.no_fengine:
+            res["fengine"] = fengine_bench(xe, inputs, torch, dev, stream)
+        if not args.no_small_launch:
+            res["small_launch"] = small_launch_bench(xe, inputs, torch, dev, stream)
         if not args.no_precision:
             res["precision"] = precision_bench(xe, inputs, torch, dev)
         if not args.no_oracle_timing:
