@@ -175,14 +175,16 @@ int64_t xc_correlate_split_bytes(int32_t n_stations, int32_t n_pol, int32_t n_ch
  *                 splits large triangles into blocks).  VALU: 32.  MFMA: 32 or 64
  *                 (AUTO: 32 for complex-float32 on at most 48 stations, else 64).
  *   time_chunk    time steps staged in LDS per pipeline stage (fixed by the
- *                 other fields except for VALU: 16 or 32; complex-float32 on
- *                 64-station blocks reports its off-diagonal chunk, diagonal
- *                 block pairs stage one block with twice as many steps).
+ *                 other fields except for VALU: 16 or 32, default 32;
+ *                 reported for off-diagonal block pairs: diagonal pairs stage
+ *                 one block, with up to twice as many steps).
  *   time_split    waves of a workgroup that share one output block, each
  *                 integrating a different part of every time chunk; their
  *                 partial sums are added in LDS before the single store.
- *                 VALU: 1, 2, 4 or 8.  MFMA: 1, or 2 for complex-float32 on
- *                 64-station blocks.
+ *                 VALU: 1, 2, 4 (default) or 8, for off-diagonal block pairs
+ *                 (a diagonal pair packs its threads over its tiles with
+ *                 outputs, in as many time groups as fit).  MFMA: 1, or 2 for
+ *                 complex-float32 on 64-station blocks.
  *   staging       xc_staging.  Complex-float32 on 64-station blocks always
  *                 copies straight into LDS; VALU and 32-station blocks always
  *                 stage through registers; int8 and 16-bit samples on
@@ -190,9 +192,10 @@ int64_t xc_correlate_split_bytes(int32_t n_stations, int32_t n_pol, int32_t n_ch
  *   product       xc_product.  AUTO: three products for complex-float32 on
  *                 64-station matrix-core blocks, four everywhere else.
  *   tile_w,       VALU only: the register tile of one lane, tile_w stations of
- *   tile_h        block I by tile_h stations of block J (Table 1): 4 x 4
- *                 (default), 8 x 2, 4 x 2 or 2 x 2.  VALU time_split 8 needs a
- *                 tile of 64 lanes per time group (4 x 4 or 8 x 2).
+ *   tile_h        block I by tile_h stations of block J (Table 1): 4 x 2
+ *                 (default), 4 x 4, 8 x 2 or 2 x 2.  VALU time_split 8 needs
+ *                 time_chunk 32 and at most 128 lanes per time group (not
+ *                 2 x 2).
  *                 Matrix-core kernels: 0.
  */
 typedef struct xc_config {

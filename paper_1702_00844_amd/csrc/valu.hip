@@ -27,6 +27,14 @@
 //    re += a_r b_r + a_i b_i ; im += a_i b_r - a_r b_i.
 //  * Autocorrelations (i == j) are written Hermitian by construction: XX and
 //    YY get imaginary part 0 and YX is stored as conj(XY).
+//  * A diagonal block pair (I = J) has outputs in only NA of its tiles (those
+//    holding some pair i <= j: 72 of 128 for 4 x 2 tiles).  Rather than
+//    leaving the other lanes masked inside their waves, the workgroup's
+//    threads are packed as (active tile, time group) tasks: G = threads / NA
+//    time groups (7 for 4 x 2 tiles and 512 threads), each taking TCD / G time
+//    steps of chunks of TCD steps of the one staged block (a row of one block
+//    is half a pair's row, so the stage holds up to 2 TC of them).  The
+//    groups' sums are added in a fixed order as for the off-diagonal pairs.
 #include "common.h"
 
 namespace xc {
@@ -55,114 +63,42 @@ __device__ __forceinline__ void cmac(float &re, float &im, float ar, float ai, f
 template <int TW, int TH>
 constexpr int lanes() { return (SB / TW) * (SB / TH); }
 
-template <int TW, int TH, int TS, int TC>
-__device__ __forceinline__ void unit(const Job &job, int c, int bi, int bj, Stage<TC> &st) {
-    constexpr int NACC = TW * TH * 8;          // floats of accumulators per lane
-    constexpr int NL = lanes<TW, TH>();
-    static_assert(NL % 64 == 0, "a time group must be whole waves");
-    static_assert(TC % TS == 0, "time chunk must split evenly over time groups");
-    static_assert(sizeof(Stage<TC>) >= NL * NACC * sizeof(float), "reduction area too small");
-    constexpr int NT = NL * TS;
-    constexpr int NELEM = TC * 2 * SB;
-    constexpr int NLOAD = (NELEM + NT - 1) / NT;
+// Tiles of a diagonal block pair that hold some output pair i <= j: in
+// column tj, tile rows ti with ti TW <= tj TH + TH - 1; and in all.
+template <int TW, int TH>
+__host__ __device__ constexpr int diag_col_tiles(int tj) {
+    const int n = (tj * TH + TH - 1) / TW + 1;
+    return n < SB / TW ? n : SB / TW;
+}
+template <int TW, int TH>
+constexpr int diag_tiles() {
+    int n = 0;
+    for (int tj = 0; tj < SB / TH; ++tj) n += diag_col_tiles<TW, TH>(tj);
+    return n;
+}
 
-    const int tid = threadIdx.x;
-    const int lane = tid % NL;                                       // tile of this lane
-    const int wave = __builtin_amdgcn_readfirstlane(tid / NL);       // time group, uniform across the wave
-    const int ti = lane % (SB / TW);
-    const int tj = lane / (SB / TW);
+template <int TW, int TH>
+__device__ __forceinline__ void cmac_tile(float *acc, const float4 (&a)[TW], const float4 (&b)[TH]) {
+#pragma unroll
+    for (int i = 0; i < TW; ++i) {
+#pragma unroll
+        for (int j = 0; j < TH; ++j) {
+            float *r = &acc[(i * TH + j) * 8];
+            // pol p of station i: (x, y) = X, (z, w) = Y; same for q of station j
+            cmac(r[0], r[1], a[i].x, a[i].y, b[j].x, b[j].y);  // XX
+            cmac(r[2], r[3], a[i].x, a[i].y, b[j].z, b[j].w);  // XY
+            cmac(r[4], r[5], a[i].z, a[i].w, b[j].x, b[j].y);  // YX
+            cmac(r[6], r[7], a[i].z, a[i].w, b[j].z, b[j].w);  // YY
+        }
+    }
+}
+
+// Store (or add, in accumulate mode) one lane's TW x TH tile of block pair
+// (I0, J0); pairs past the last station or below the diagonal are skipped.
+template <int TW, int TH>
+__device__ __forceinline__ void store_lane_tile(const Job &job, int c, const float *acc, int I0, int J0, int ti,
+                                                int tj) {
     const int S = job.S;
-    const int T = job.T;
-    const bool diag = (bi == bj);
-    const int I0 = bi * SB;
-    const int J0 = bj * SB;
-    // on a diagonal block pair, tiles wholly below the diagonal have no output
-    const bool active = !(diag && ti * TW > tj * TH + TH - 1);
-    const int jbase = diag ? 0 : SB;
-    const float4 *__restrict__ x = static_cast<const float4 *>(job.x);
-
-    float acc[NACC];
-#pragma unroll
-    for (int f = 0; f < NACC; ++f) acc[f] = 0.f;
-
-    float4 pre[NLOAD];
-    auto gload = [&](int t0) {
-#pragma unroll
-        for (int k = 0; k < NLOAD; ++k) {
-            const int e = tid + k * NT;
-            const int t = e / (2 * SB);
-            const int s = e % (2 * SB);
-            const int station = s < SB ? I0 + s : J0 + s - SB;
-            const bool ok = (e < NELEM) && (t0 + t < T) && station < S && !(diag && s >= SB);
-            // time-major: all stations of a time step together; station-major
-            // (sstride != 0): each station's series together
-            const size_t e_x = job.sstride ? (size_t)c * job.cstride + (size_t)station * job.sstride + (t0 + t)
-                                           : row_offset(job, c, t0 + t) + station;
-            pre[k] = ok ? x[e_x] : make_float4(0.f, 0.f, 0.f, 0.f);
-        }
-    };
-    auto lstore = [&](int buf) {
-#pragma unroll
-        for (int k = 0; k < NLOAD; ++k) {
-            const int e = tid + k * NT;
-            const int t = e / (2 * SB);
-            const int s = e % (2 * SB);
-            if (e < NELEM && !(diag && s >= SB)) st.v[buf][t][slot(s)] = pre[k];
-        }
-    };
-
-    const int nchunk = (T + TC - 1) / TC;
-    gload(0);
-    lstore(0);
-    __syncthreads();
-    for (int ch = 0; ch < nchunk; ++ch) {
-        const int buf = ch & 1;
-        if (ch + 1 < nchunk) gload((ch + 1) * TC);
-        if (active) {
-            const int tbeg = wave * (TC / TS);
-            for (int tt = tbeg; tt < tbeg + TC / TS; ++tt) {
-                float4 a[TW], b[TH];
-#pragma unroll
-                for (int i = 0; i < TW; ++i) a[i] = st.v[buf][tt][slot(ti * TW + i)];
-#pragma unroll
-                for (int j = 0; j < TH; ++j) b[j] = st.v[buf][tt][slot(jbase + tj * TH + j)];
-#pragma unroll
-                for (int i = 0; i < TW; ++i) {
-#pragma unroll
-                    for (int j = 0; j < TH; ++j) {
-                        float *r = &acc[(i * TH + j) * 8];
-                        // pol p of station i: (x, y) = X, (z, w) = Y; same for q of station j
-                        cmac(r[0], r[1], a[i].x, a[i].y, b[j].x, b[j].y);  // XX
-                        cmac(r[2], r[3], a[i].x, a[i].y, b[j].z, b[j].w);  // XY
-                        cmac(r[4], r[5], a[i].z, a[i].w, b[j].x, b[j].y);  // YX
-                        cmac(r[6], r[7], a[i].z, a[i].w, b[j].z, b[j].w);  // YY
-                    }
-                }
-            }
-        }
-        if (ch + 1 < nchunk) lstore(buf ^ 1);
-        __syncthreads();
-    }
-
-    // Add the partial sums of time groups 1..TS-1 into group 0, one group per round.
-    if constexpr (TS > 1) {
-        float *red = reinterpret_cast<float *>(&st.v[0][0][0]);
-#pragma unroll 1
-        for (int w = 1; w < TS; ++w) {
-            if (wave == w) {
-#pragma unroll
-                for (int f = 0; f < NACC; ++f) red[f * NL + lane] = acc[f];
-            }
-            __syncthreads();
-            if (wave == 0) {
-#pragma unroll
-                for (int f = 0; f < NACC; ++f) acc[f] += red[f * NL + lane];
-            }
-            __syncthreads();
-        }
-    }
-
-    if (wave != 0 || !active) return;
     float4 *__restrict__ V = static_cast<float4 *>(job.vis) + (size_t)c * ((size_t)S * (S + 1) / 2) * 2;
 #pragma unroll
     for (int j = 0; j < TH; ++j) {
@@ -193,13 +129,261 @@ __device__ __forceinline__ void unit(const Job &job, int c, int bi, int bj, Stag
     }
 }
 
+// Diagonal block pair b: (active tile, time group) tasks packed over the
+// workgroup's threads.
 template <int TW, int TH, int TS, int TC>
-__global__ __launch_bounds__((lanes<TW, TH>() * TS)) void kernel(Job job, int nwork) {
+__device__ __forceinline__ void unit_diag(const Job &job, int c, int b, Stage<TC> &st) {
+    constexpr int NACC = TW * TH * 8;
+    constexpr int NT = lanes<TW, TH>() * TS;
+    constexpr int NA = diag_tiles<TW, TH>();
+    constexpr int G = NT / NA;                     // time groups
+    constexpr int TCD = G * ((2 * TC) / G);        // time steps per chunk
+    constexpr int STEPS = TCD / G;                 // time steps per group and chunk
+    constexpr int DROW = SB + SB / 16;             // float4 slots per staged time step of one block
+    constexpr int NELEM = TCD * SB;
+    constexpr int NLOAD = (NELEM + NT - 1) / NT;
+    static_assert(G >= 1 && STEPS >= 1, "at least one time group and step");
+    static_assert(TCD * DROW <= TC * ROW, "a chunk must fit one staging buffer");
+    static_assert(NA * NACC * sizeof(float) <= sizeof(Stage<TC>), "reduction area too small");
+    static_assert(NACC % 4 == 0, "accumulators move as float4");
+
+    const int tid = threadIdx.x;
+    const int g = tid / NA;                        // time group; G: no task
+    const int k = tid - g * NA;
+    const bool has = g < G;
+    int tj = 0, ti = k;
+    while (tj < SB / TH - 1 && ti >= diag_col_tiles<TW, TH>(tj)) {
+        ti -= diag_col_tiles<TW, TH>(tj);
+        ++tj;
+    }
+    const int S = job.S;
+    const int T = job.T;
+    const int I0 = b * SB;
+    const float4 *__restrict__ x = static_cast<const float4 *>(job.x);
+    float4 *buf0 = &st.v[0][0][0];
+    float4 *buf1 = &st.v[1][0][0];
+
+    float acc[NACC];
+#pragma unroll
+    for (int f = 0; f < NACC; ++f) acc[f] = 0.f;
+
+    float4 pre[NLOAD];
+    auto gload = [&](int t0) {
+#pragma unroll
+        for (int q = 0; q < NLOAD; ++q) {
+            const int e = tid + q * NT;
+            const int t = e / SB;
+            const int station = I0 + e % SB;
+            const bool ok = (e < NELEM) && (t0 + t < T) && station < S;
+            const size_t e_x = job.sstride ? (size_t)c * job.cstride + (size_t)station * job.sstride + (t0 + t)
+                                           : row_offset(job, c, t0 + t) + station;
+            pre[q] = ok ? x[e_x] : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+    };
+    auto lstore = [&](float4 *dst) {
+#pragma unroll
+        for (int q = 0; q < NLOAD; ++q) {
+            const int e = tid + q * NT;
+            if (e < NELEM) dst[(e / SB) * DROW + slot(e % SB)] = pre[q];
+        }
+    };
+
+    const int nchunk = (T + TCD - 1) / TCD;
+    gload(0);
+    lstore(buf0);
+    __syncthreads();
+    for (int ch = 0; ch < nchunk; ++ch) {
+        const float4 *cur = (ch & 1) ? buf1 : buf0;
+        if (ch + 1 < nchunk) gload((ch + 1) * TCD);
+        if (has) {
+            const float4 *row = cur + g * STEPS * DROW;
+#pragma unroll 1
+            for (int tt = 0; tt < STEPS; ++tt, row += DROW) {
+                float4 a[TW], bb[TH];
+#pragma unroll
+                for (int i = 0; i < TW; ++i) a[i] = row[slot(ti * TW + i)];
+#pragma unroll
+                for (int j = 0; j < TH; ++j) bb[j] = row[slot(tj * TH + j)];
+                cmac_tile<TW, TH>(acc, a, bb);
+            }
+        }
+        if (ch + 1 < nchunk) lstore((ch & 1) ? buf0 : buf1);
+        __syncthreads();
+    }
+
+    // Add the sums of groups 1 .. G - 1 into group 0, one group per round.
+    if constexpr (G > 1) {
+        float4 *red = buf0;
+#pragma unroll 1
+        for (int w = 1; w < G; ++w) {
+            if (g == w) {
+#pragma unroll
+                for (int f = 0; f < NACC / 4; ++f)
+                    red[f * NA + k] = make_float4(acc[4 * f], acc[4 * f + 1], acc[4 * f + 2], acc[4 * f + 3]);
+            }
+            __syncthreads();
+            if (g == 0) {
+#pragma unroll
+                for (int f = 0; f < NACC / 4; ++f) {
+                    const float4 o = red[f * NA + k];
+                    acc[4 * f] += o.x;
+                    acc[4 * f + 1] += o.y;
+                    acc[4 * f + 2] += o.z;
+                    acc[4 * f + 3] += o.w;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    if (g != 0) return;
+    store_lane_tile<TW, TH>(job, c, acc, I0, I0, ti, tj);
+}
+
+template <int TW, int TH, int TS, int TC>
+__device__ __forceinline__ void unit(const Job &job, int c, int bi, int bj, Stage<TC> &st) {
+    if (bi == bj) {
+        unit_diag<TW, TH, TS, TC>(job, c, bi, st);
+        return;
+    }
+    constexpr int NACC = TW * TH * 8;          // floats of accumulators per lane
+    constexpr int NL = lanes<TW, TH>();
+    static_assert(NL % 64 == 0, "a time group must be whole waves");
+    static_assert(TC % TS == 0, "time chunk must split evenly over time groups");
+    static_assert(sizeof(Stage<TC>) >= NL * NACC * sizeof(float), "reduction area too small");
+    constexpr int NT = NL * TS;
+    constexpr int NELEM = TC * 2 * SB;
+    constexpr int NLOAD = (NELEM + NT - 1) / NT;
+
+    const int tid = threadIdx.x;
+    const int lane = tid % NL;                                       // tile of this lane
+    const int wave = __builtin_amdgcn_readfirstlane(tid / NL);       // time group, uniform across the wave
+    const int ti = lane % (SB / TW);
+    const int tj = lane / (SB / TW);
+    const int S = job.S;
+    const int T = job.T;
+    const int I0 = bi * SB;
+    const int J0 = bj * SB;
+    const float4 *__restrict__ x = static_cast<const float4 *>(job.x);
+
+    float acc[NACC];
+#pragma unroll
+    for (int f = 0; f < NACC; ++f) acc[f] = 0.f;
+
+    float4 pre[NLOAD];
+    auto gload = [&](int t0) {
+#pragma unroll
+        for (int k = 0; k < NLOAD; ++k) {
+            const int e = tid + k * NT;
+            const int t = e / (2 * SB);
+            const int s = e % (2 * SB);
+            const int station = s < SB ? I0 + s : J0 + s - SB;
+            const bool ok = (e < NELEM) && (t0 + t < T) && station < S;
+            // time-major: all stations of a time step together; station-major
+            // (sstride != 0): each station's series together
+            const size_t e_x = job.sstride ? (size_t)c * job.cstride + (size_t)station * job.sstride + (t0 + t)
+                                           : row_offset(job, c, t0 + t) + station;
+            pre[k] = ok ? x[e_x] : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+    };
+    auto lstore = [&](int buf) {
+#pragma unroll
+        for (int k = 0; k < NLOAD; ++k) {
+            const int e = tid + k * NT;
+            const int t = e / (2 * SB);
+            const int s = e % (2 * SB);
+            if (e < NELEM) st.v[buf][t][slot(s)] = pre[k];
+        }
+    };
+
+    const int nchunk = (T + TC - 1) / TC;
+    gload(0);
+    lstore(0);
+    __syncthreads();
+    for (int ch = 0; ch < nchunk; ++ch) {
+        const int buf = ch & 1;
+        if (ch + 1 < nchunk) gload((ch + 1) * TC);
+        const int tbeg = wave * (TC / TS);
+#pragma unroll 1
+        for (int tt = tbeg; tt < tbeg + TC / TS; ++tt) {
+            float4 a[TW], b[TH];
+#pragma unroll
+            for (int i = 0; i < TW; ++i) a[i] = st.v[buf][tt][slot(ti * TW + i)];
+#pragma unroll
+            for (int j = 0; j < TH; ++j) b[j] = st.v[buf][tt][slot(SB + tj * TH + j)];
+            cmac_tile<TW, TH>(acc, a, b);
+        }
+        if (ch + 1 < nchunk) lstore(buf ^ 1);
+        __syncthreads();
+    }
+
+    // Add the partial sums of time groups 1..TS-1 into group 0, one group per round.
+    if constexpr (TS > 1) {
+        float *red = reinterpret_cast<float *>(&st.v[0][0][0]);
+#pragma unroll 1
+        for (int w = 1; w < TS; ++w) {
+            if (wave == w) {
+#pragma unroll
+                for (int f = 0; f < NACC; ++f) red[f * NL + lane] = acc[f];
+            }
+            __syncthreads();
+            if (wave == 0) {
+#pragma unroll
+                for (int f = 0; f < NACC; ++f) acc[f] += red[f * NL + lane];
+            }
+            __syncthreads();
+        }
+    }
+
+    if (wave != 0) return;
+    store_lane_tile<TW, TH>(job, c, acc, I0, J0, ti, tj);
+}
+
+// Flat launch, longest units first: each XCD takes a contiguous range of
+// cper channels, and its workgroups (dispatched to it in id order) run the
+// off-diagonal block pairs of those channels first and the diagonal pairs
+// (shorter, their threads being packed over fewer tiles) after them, so that
+// the short units fill the end of the launch instead of extending it.  The
+// grid is kNumXcd cper npairs; ids past the last channel return false.
+__device__ inline bool longest_first(const Job &job, int phys, int cper, int &c, int &bi, int &bj) {
+    const int r = phys / kNumXcd;
+    const int c0 = (phys % kNumXcd) * cper;
+    const int nc = job.C - c0 < cper ? job.C - c0 : cper;
+    const int nb = job.nb;
+    const int noff = job.npairs - nb;
+    if (nc <= 0) return false;
+    if (r < nc * noff) {
+        int j;
+        c = c0 + r / noff;
+        pair_decode(r % noff, bi, j);     // off-diagonal pair m = j (j + 1) / 2 + bi: bi <= j < nb - 1
+        bj = j + 1;
+        return true;
+    }
+    const int q = r - nc * noff;
+    if (q >= nc * nb) return false;
+    c = c0 + q / nb;
+    bi = bj = q % nb;
+    return true;
+}
+
+// Channels per XCD for the longest-first order, or 0 for the plain order
+// (split integrations, a single block, or too few channels to give every
+// XCD a whole share).
+inline int longest_first_channels(const Job &job) {
+    if (job.tsplit > 1 || job.nb < 2 || job.C < 8 * kNumXcd) return 0;
+    return (job.C + kNumXcd - 1) / kNumXcd;
+}
+
+template <int TW, int TH, int TS, int TC>
+__global__ __launch_bounds__((lanes<TW, TH>() * TS)) void kernel(Job job, int nwork, int cper) {
     __shared__ Stage<TC> st;
-    const int w = xcd_remap(blockIdx.x, nwork);
-    if (w < 0) return;
     int c, bi, bj;
-    unit_decode(job, w, c, bi, bj);
+    if (cper > 0) {
+        if (!longest_first(job, blockIdx.x, cper, c, bi, bj)) return;
+    } else {
+        const int w = xcd_remap(blockIdx.x, nwork);
+        if (w < 0) return;
+        unit_decode(job, w, c, bi, bj);
+    }
     unit<TW, TH, TS, TC>(job, c, bi, bj, st);
 }
 
@@ -219,8 +403,10 @@ __global__ __launch_bounds__((lanes<TW, TH>() * TS)) void kernel_batch(const Job
 template <int TW, int TH, int TS, int TC>
 hipError_t launch_t(const Job &job, hipStream_t stream) {
     const int nwork = job_units(job);
-    hipLaunchKernelGGL((kernel<TW, TH, TS, TC>), dim3(xcd_grid(nwork)), dim3(lanes<TW, TH>() * TS), 0, stream, job,
-                       nwork);
+    const int cper = longest_first_channels(job);
+    const int grid = cper > 0 ? kNumXcd * cper * job.npairs : xcd_grid(nwork);
+    hipLaunchKernelGGL((kernel<TW, TH, TS, TC>), dim3(grid), dim3(lanes<TW, TH>() * TS), 0, stream, job, nwork,
+                       cper);
     return hipGetLastError();
 }
 

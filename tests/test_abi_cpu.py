@@ -114,7 +114,7 @@ def test_config_resolution():
     F4, F3 = _lib.XC_PRODUCT_FOUR, _lib.XC_PRODUCT_THREE
     shp = (_lib.XC_IN_CF32, 256, 768, 64, 2)
     r = xe.resolve_config(shp, config={"kernel": _lib.XC_KERNEL_VALU})
-    assert r == {"kernel": 1, "block": 32, "time_chunk": 16, "time_split": 4, "staging": R, "product": F4,
+    assert r == {"kernel": 1, "block": 32, "time_chunk": 32, "time_split": 4, "staging": R, "product": F4,
                  "tile_w": 4, "tile_h": 2}
     r = xe.resolve_config(shp, config={"kernel": _lib.XC_KERNEL_MFMA})
     assert r == {"kernel": 2, "block": 64, "time_chunk": 32, "time_split": 2, "staging": L, "product": F3, "tile_w": 0, "tile_h": 0}
