@@ -135,13 +135,7 @@ __device__ __forceinline__ void unit(const Job &job, int c, int bi, int bj, uint
         // the staging buffers are free after the last barrier: one image region per wave
         static_assert(4 * IMG_BYTES <= 2 * G::STAGE_BYTES, "tile images must fit the staging area");
         uint8_t *img = lds + wave * IMG_BYTES;
-#pragma unroll
-        for (int rs = 0; rs < NS; ++rs)
-#pragma unroll
-            for (int cs = 0; cs < NS; ++cs)
-                if (run[rs][cs])
-                    store_tile_lds<acc_t, OUT>(job, c, are[rs][cs], aim[rs][cs], bk.I0 * 2 + wr * SB + rs * 32,
-                                               bk.J0 * 2 + wc * SB + cs * 32, lane, img);
+        store_tiles_lds<acc_t, OUT>(job, c, are, aim, run, bk.I0 * 2 + wr * SB, bk.J0 * 2 + wc * SB, lane, img);
     } else {
 #pragma unroll
         for (int rs = 0; rs < NS; ++rs)

@@ -336,16 +336,14 @@ __device__ __forceinline__ void unit(const Job &job, int c, int bi, int bj, uint
     __syncthreads();
     if (!any) return;
     uint8_t *img = lds_generic + wave * mfma::IMG_BYTES;
+    if constexpr (G::I8) {
+        // the int8 accumulators hold minus the imaginary part
 #pragma unroll
-    for (int rs = 0; rs < 2; ++rs)
+        for (int rs = 0; rs < 2; ++rs)
 #pragma unroll
-        for (int cs = 0; cs < 2; ++cs)
-            if (run[rs][cs]) {
-                // the int8 accumulators hold minus the imaginary part
-                const acc_t im = G::I8 ? -aim[rs][cs] : aim[rs][cs];
-                mfma::store_tile_lds<acc_t, OUT>(job, c, are[rs][cs], im, I0 * 2 + wr * SB + rs * 32,
-                                                 J0 * 2 + wc * SB + cs * 32, lane, img);
-            }
+            for (int cs = 0; cs < 2; ++cs) aim[rs][cs] = -aim[rs][cs];
+    }
+    mfma::store_tiles_lds<acc_t, OUT>(job, c, are, aim, run, I0 * 2 + wr * SB, J0 * 2 + wc * SB, lane, img);
 }
 
 template <int KIND, typename OUT, bool G4, bool SM = false>

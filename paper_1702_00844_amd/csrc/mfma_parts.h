@@ -458,7 +458,7 @@ __device__ __forceinline__ void store_tile(const Job &job, int c, const ACC &re,
     }
 }
 
-// Coalesced store of one 32 x 32 tile (16 x 16 station pairs) through this
+// Coalesced store of a 32 x 32 tile (16 x 16 station pairs) through this
 // wave's private LDS region: the accumulators are written as an image of the
 // output (for each station j, the 16 baselines (i, j) of 32 bytes each, rows
 // padded by 16 bytes), then every lane stores whole baselines, so that 16
@@ -489,9 +489,34 @@ struct Vec<int2> {
     __device__ static uint32_t neg(uint32_t v) { return 0u - v; }
 };
 
-template <typename ACC, typename OUT>
-__device__ __forceinline__ void store_tile_lds(const Job &job, int c, const ACC &re, const ACC &im, int row0,
-                                               int col0, int lane, uint8_t *img) {
+// Old values of the whole baselines this lane stores for one tile (accumulate
+// mode), in the order the store visits them.  Every lane loads: addresses of
+// baselines past the last station or below the diagonal are clamped to a
+// valid one (its value is discarded), so the loads need no branches and can
+// be issued well before they are used.
+template <typename OUT>
+__device__ __forceinline__ void tile_old(const Job &job, int c, int row0, int col0, int lane, uint4 (&old)[4][2]) {
+    const int S = job.S;
+    const OUT *__restrict__ V = static_cast<const OUT *>(job.vis) + (size_t)c * ((size_t)S * (S + 1) / 2) * 4;
+    const int i0 = row0 >> 1, j0 = col0 >> 1;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int bl = lane + 64 * k;
+        int j = j0 + (bl >> 4);
+        j = j < S ? j : S - 1;
+        int i = i0 + (bl & 15);
+        i = i <= j ? i : j;
+        const uint4 *src = reinterpret_cast<const uint4 *>(V + ((size_t)j * (j + 1) / 2 + i) * 4);
+        old[k][0] = src[0];
+        old[k][1] = src[1];
+    }
+}
+
+// Coalesced store of one 32 x 32 tile through this wave's LDS region; with
+// ACCUM the tile is added to the old values `old` (from tile_old).
+template <bool ACCUM, typename ACC, typename OUT>
+__device__ __forceinline__ void store_tile_img(const Job &job, int c, const ACC &re, const ACC &im, int row0,
+                                               int col0, int lane, uint8_t *img, const uint4 (&old)[4][2]) {
     const int S = job.S;
     // 1. image: element (lane, r) is row 8 (r/4) + 4 (lane/32) + r%4, column lane % 32
     {
@@ -524,15 +549,47 @@ __device__ __forceinline__ void store_tile_lds(const Job &job, int c, const ACC 
             hi.y = Vec<OUT>::neg(lo.w);
         }
         uint4 *dst = reinterpret_cast<uint4 *>(V + ((size_t)j * (j + 1) / 2 + i) * 4);
-        if (job.accumulate) {
-            lo = Vec<OUT>::add(lo, dst[0]);
-            hi = Vec<OUT>::add(hi, dst[1]);
+        if constexpr (ACCUM) {
+            lo = Vec<OUT>::add(lo, old[k][0]);
+            hi = Vec<OUT>::add(hi, old[k][1]);
         }
         dst[0] = lo;
         dst[1] = hi;
     }
     __builtin_amdgcn_s_waitcnt(0xc07f);   // reads done before the region is reused
     __builtin_amdgcn_wave_barrier();
+}
+
+// Stores of a wave's 2 x 2 tiles (row0 + 32 rs, col0 + 32 cs) where run[rs][cs].
+// In accumulate mode each tile's old values are loaded before its image is
+// assembled, so a wave waits for memory once per tile instead of once per
+// group of baselines.
+template <typename ACC, typename OUT>
+__device__ __forceinline__ void store_tiles_lds(const Job &job, int c, const ACC (&re)[2][2], const ACC (&im)[2][2],
+                                                const bool (&run)[2][2], int row0, int col0, int lane,
+                                                uint8_t *img) {
+    if (job.accumulate) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int rs = t >> 1, cs = t & 1;
+            if (!run[rs][cs]) continue;
+            uint4 old[4][2];
+            __builtin_amdgcn_sched_barrier(0);
+            tile_old<OUT>(job, c, row0 + 32 * rs, col0 + 32 * cs, lane, old);
+            __builtin_amdgcn_sched_barrier(0);
+            store_tile_img<true, ACC, OUT>(job, c, re[rs][cs], im[rs][cs], row0 + 32 * rs, col0 + 32 * cs, lane, img,
+                                           old);
+        }
+    } else {
+        const uint4 none[4][2] = {};
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int rs = t >> 1, cs = t & 1;
+            if (run[rs][cs])
+                store_tile_img<false, ACC, OUT>(job, c, re[rs][cs], im[rs][cs], row0 + 32 * rs, col0 + 32 * cs, lane,
+                                                img, none);
+        }
+    }
 }
 
 }  // namespace mfma
