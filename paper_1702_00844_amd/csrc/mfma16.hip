@@ -94,6 +94,20 @@ __device__ __forceinline__ void store_tile(const Job &job, int c, const v4f &re,
     if (j >= S) return;
     float2 *__restrict__ V = static_cast<float2 *>(job.vis) + (size_t)c * ((size_t)S * (S + 1) / 2) * 4;
     const size_t jbase = (size_t)j * (j + 1) / 2;
+    // accumulate mode: every old value this lane adds to is loaded before the
+    // first store, so that the loads are in flight together (a store to V
+    // would otherwise keep each later load behind it)
+    // (old2[r / 2]: the YX element that rows r = 0, 2 write for an autocorrelation)
+    float2 old[4], old2[2];
+    if (job.accumulate) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = row0 + 4 * (lane >> 4) + r;
+            const int i = (row >> 1) <= j ? (row >> 1) : j;    // clamped: the value is not used
+            old[r] = V[(jbase + i) * 4 + (row & 1) * 2 + q];
+            if ((r & 1) == 0) old2[r >> 1] = V[(jbase + i) * 4 + 2];
+        }
+    }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int row = row0 + 4 * (lane >> 4) + r;
@@ -108,12 +122,12 @@ __device__ __forceinline__ void store_tile(const Job &job, int c, const v4f &re,
         }
         float2 v = make_float2(vr, vi);
         const size_t e = (jbase + i) * 4 + p * 2 + q;
-        if (job.accumulate) v = Out<float2>::add(v, V[e]);
+        if (job.accumulate) v = Out<float2>::add(v, old[r]);
         V[e] = v;
         if (i == j && p == 0 && q == 1) {
             float2 w = make_float2(vr, -vi);
             const size_t e2 = (jbase + i) * 4 + 2;
-            if (job.accumulate) w = Out<float2>::add(w, V[e2]);
+            if (job.accumulate) w = Out<float2>::add(w, old2[r >> 1]);
             V[e2] = w;
         }
     }
@@ -353,20 +367,32 @@ __device__ __forceinline__ void wave_unit(const Job &job, int c, int bi, int bj,
         float4 *__restrict__ V4 = reinterpret_cast<float4 *>(static_cast<float2 *>(job.vis) +
                                                              (size_t)c * ((size_t)S * (S + 1) / 2) * 4);
         const int ng = nj * (nj + 1);     // 16-byte granules: two per baseline
-        for (int g = tid; g < ng; g += 256 * TS) {
-            const int bl = g >> 1;
-            int jl = (int)((sqrtf(8.f * (float)bl + 1.f) - 1.f) * 0.5f);
-            while ((jl + 1) * (jl + 2) / 2 <= bl) ++jl;
-            while (jl * (jl + 1) / 2 > bl) --jl;
-            const int il = bl - jl * (jl + 1) / 2;
-            const int j = J0 + jl;
-            float4 *dst = V4 + (((size_t)j * (j + 1) / 2 + I0 + il) * 2 + (g & 1));
-            float4 v = img4[g];
-            if (job.accumulate) {
-                const float4 o = *dst;
-                v = make_float4(v.x + o.x, v.y + o.y, v.z + o.z, v.w + o.w);
+        // granules in groups of NB per thread: in accumulate mode the group's
+        // old values are all loaded before its stores
+        constexpr int NB = 4;
+        for (int g0 = tid; g0 < ng; g0 += NB * 256 * TS) {
+            float4 *dst[NB];
+            float4 o[NB];
+#pragma unroll
+            for (int n = 0; n < NB; ++n) {
+                const int g = g0 + n * 256 * TS < ng ? g0 + n * 256 * TS : g0;
+                const int bl = g >> 1;
+                int jl = (int)((sqrtf(8.f * (float)bl + 1.f) - 1.f) * 0.5f);
+                while ((jl + 1) * (jl + 2) / 2 <= bl) ++jl;
+                while (jl * (jl + 1) / 2 > bl) --jl;
+                const int il = bl - jl * (jl + 1) / 2;
+                const int j = J0 + jl;
+                dst[n] = V4 + (((size_t)j * (j + 1) / 2 + I0 + il) * 2 + (g & 1));
+                if (job.accumulate) o[n] = *dst[n];
             }
-            *dst = v;
+#pragma unroll
+            for (int n = 0; n < NB; ++n) {
+                const int g = g0 + n * 256 * TS;
+                if (g >= ng) break;
+                float4 v = img4[g];
+                if (job.accumulate) v = make_float4(v.x + o[n].x, v.y + o[n].y, v.z + o[n].z, v.w + o[n].w);
+                *dst[n] = v;
+            }
         }
         return;
     }

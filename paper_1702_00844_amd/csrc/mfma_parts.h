@@ -433,27 +433,45 @@ __device__ __forceinline__ void store_tile(const Job &job, int c, const ACC &re,
     if (j >= S) return;
     OUT *__restrict__ V = static_cast<OUT *>(job.vis) + (size_t)c * ((size_t)S * (S + 1) / 2) * 4;
     const size_t jbase = (size_t)j * (j + 1) / 2;
+    // two halves of 8 rows; in accumulate mode a half's old values (and the
+    // YX elements its even rows write for autocorrelations) are all loaded
+    // before its first store, so that the loads are in flight together
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-        const int row = row0 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-        const int i = row >> 1;
-        const int p = row & 1;
-        if (i > j) continue;
-        auto vr = re[r];
-        auto vi = im[r];
-        if (i == j) {
-            if (p == 1 && q == 0) continue;      // written as conj(XY) by the q = 1 lane
-            if (p == q) vi = 0;
+    for (int h = 0; h < 2; ++h) {
+        OUT old[8], old2[4];
+        if (job.accumulate) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int r = 8 * h + k;
+                const int row = row0 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                const int i = (row >> 1) <= j ? (row >> 1) : j;     // clamped: the value is not used
+                old[k] = V[(jbase + i) * 4 + (row & 1) * 2 + q];
+                if ((k & 1) == 0) old2[k >> 1] = V[(jbase + i) * 4 + 2];
+            }
         }
-        OUT v = Out<OUT>::make(vr, vi);
-        const size_t e = (jbase + i) * 4 + p * 2 + q;
-        if (job.accumulate) v = Out<OUT>::add(v, V[e]);
-        V[e] = v;
-        if (i == j && p == 0 && q == 1) {       // YX = conj(XY) for autocorrelations
-            OUT w = Out<OUT>::make(vr, -vi);
-            const size_t e2 = (jbase + i) * 4 + 2;
-            if (job.accumulate) w = Out<OUT>::add(w, V[e2]);
-            V[e2] = w;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int r = 8 * h + k;
+            const int row = row0 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+            const int i = row >> 1;
+            const int p = row & 1;
+            if (i > j) continue;
+            auto vr = re[r];
+            auto vi = im[r];
+            if (i == j) {
+                if (p == 1 && q == 0) continue;      // written as conj(XY) by the q = 1 lane
+                if (p == q) vi = 0;
+            }
+            OUT v = Out<OUT>::make(vr, vi);
+            const size_t e = (jbase + i) * 4 + p * 2 + q;
+            if (job.accumulate) v = Out<OUT>::add(v, old[k]);
+            V[e] = v;
+            if (i == j && p == 0 && q == 1) {       // YX = conj(XY) for autocorrelations
+                OUT w = Out<OUT>::make(vr, -vi);
+                const size_t e2 = (jbase + i) * 4 + 2;
+                if (job.accumulate) w = Out<OUT>::add(w, old2[k >> 1]);
+                V[e2] = w;
+            }
         }
     }
 }
