@@ -365,11 +365,14 @@ __device__ inline bool longest_first(const Job &job, int phys, int cper, int &c,
     return true;
 }
 
-// Channels per XCD for the longest-first order, or 0 for the plain order
-// (split integrations, a single block, or too few channels to give every
-// XCD a whole share).
+// Channels per XCD for the longest-first order, or 0 for the plain order:
+// split integrations, a single block, too few channels to give every XCD a
+// whole share, or more than four blocks (diagonal pairs are then a small
+// share of the work, and running a channel's pairs together keeps its
+// samples in L2: on 256 stations the longest-first order read 2.2 times the
+// algorithmic bytes against 1.5 for the plain order, at the same speed).
 inline int longest_first_channels(const Job &job) {
-    if (job.tsplit > 1 || job.nb < 2 || job.C < 8 * kNumXcd) return 0;
+    if (job.tsplit > 1 || job.nb < 2 || job.nb > 4 || job.C < 8 * kNumXcd) return 0;
     return (job.C + kNumXcd - 1) / kNumXcd;
 }
 
