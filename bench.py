@@ -133,8 +133,16 @@ def cpu_info():
     return {"cpu_model": model, "sockets": len(phys) or None, "logical_cpus": n or os.cpu_count()}
 
 
-def time_launches(fn, steps: int, warmup: int, stream):
+def time_launches(fn, steps: int, warmup: int, stream, settle_s: float = 0.2):
+    """ms per launch of fn over `steps` launches, after `settle_s` seconds of
+    untimed launches (the GPU's clock ramps up over the first few hundred
+    microseconds of a busy period: a 0.73 ms int8 launch timed from idle
+    measures 0.8-0.9 ms) and `warmup` more."""
     import torch
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < settle_s:
+        fn()
+        torch.cuda.synchronize()
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
