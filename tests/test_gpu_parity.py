@@ -248,10 +248,25 @@ def test_config2_full():
     every output, both FP32 kernels, in the configurations the benchmark times."""
     x, _ = inputs.point_sources(256, 768, 64, seed=2, device=DEV)
     ref = oracle_vis(x)
-    for cfg in [VALU[2], VALU[5]] + MFMA_F32 + [None]:
+    for cfg in VALU[2:] + MFMA_F32 + [None]:
         got = gpu_vis_numpy(xe.correlate(x, config=cfg))
         assert rel_err(got, ref) <= FP32_TOL
         assert_hermitian_autos(got, 64)
+
+
+@pytest.mark.parametrize("shape", [(70, 70, 45), (128, 66, 20), (96, 64, 33)], ids=lambda s: "S%d_C%d_T%d" % s)
+def test_valu_longest_first_order(shape):
+    """At least 64 channels on two to four 32-station blocks: the vector-ALU
+    launch runs each XCD's off-diagonal block pairs before its diagonal ones,
+    over contiguous channel ranges (70 and 66 channels leave the last range
+    short).  Every output against the oracle, for each register tile."""
+    S, C, T = shape
+    x = _cf32(S, C, T, seed=S + C + T)
+    ref = oracle_vis(x)
+    for cfg in [VALU[4], VALU[0]] + VALU[6:]:
+        got = gpu_vis_numpy(xe.correlate(x, config=cfg))
+        assert rel_err(got, ref) <= FP32_TOL, cfg
+        assert_hermitian_autos(got, S)
 
 
 def test_config3_sampled_channels():
