@@ -32,8 +32,20 @@
  *     enqueue work and return before it completes.
  *   - Argument errors are reported before anything is enqueued; HIP errors
  *     return XC_ERR_HIP.  xc_last_error() gives a thread-local message for the
- *     last failing call.  The library never aborts and never prints.
+ *     last failing call.  The library never aborts, and prints nothing
+ *     unless XC_LOG is set (below).
  *   - Only n_pol == 2 is supported (dual-polarised stations, Section 2).
+ *
+ * Environment variables, read by the library:
+ *   XC_CHECK=1       scan XC_IN_CI8 input for -128 before correlating
+ *                    (xc_correlate and the calls built on it; see below).
+ *   XC_TUNE_CACHE    tuning-cache path used by xc_batch_plan_create when it
+ *                    gets neither a configuration nor a cache path.
+ *   XC_LOG           log of events that happen once per plan, stream or tuning
+ *                    run (tuned configurations, cache loads, batch plans,
+ *                    stream admission, opening and closing), one line each:
+ *                    unset or "0" none, "1" or "stderr" standard error, any
+ *                    other value a file appended to.  Read once per process.
  */
 #ifndef XENGINE_H
 #define XENGINE_H
@@ -323,7 +335,8 @@ typedef struct xc_batch_plan xc_batch_plan;
  * length), so a channel's block pairs share an L2 and the longest units
  * start first.  If use_graph != 0 the launches are captured into a hipGraph
  * and replayed by xc_batch_plan_run.  The plan owns its device work lists;
- * xc_batch_plan_destroy frees them.  Pointers in `items` are baked into the
+ * xc_batch_plan_destroy frees them.  tune_cache NULL (and cfg NULL) takes
+ * the path in XC_TUNE_CACHE, if set.  Pointers in `items` are baked into the
  * plan: they must stay valid while the plan is used.
  * Errors: as xc_correlate for each item; XC_ERR_OUT_OF_MEMORY.
  */

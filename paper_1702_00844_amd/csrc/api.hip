@@ -26,6 +26,32 @@ xc_status set_error(xc_status st, const char *fmt, ...) {
     return st;
 }
 
+namespace {
+std::mutex g_log_mu;
+FILE *log_file() {
+    static FILE *f = [] {
+        const char *v = getenv("XC_LOG");
+        if (!v || !*v || strcmp(v, "0") == 0) return (FILE *)nullptr;
+        if (strcmp(v, "1") == 0 || strcmp(v, "stderr") == 0) return stderr;
+        return fopen(v, "a");
+    }();
+    return f;
+}
+}  // namespace
+
+void log_line(const char *fmt, ...) {
+    FILE *f = log_file();
+    if (!f) return;
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    std::lock_guard<std::mutex> lk(g_log_mu);
+    fprintf(f, "[xengine] %s\n", buf);
+    fflush(f);
+}
+
 xc_status hip_error(hipError_t err, const char *what) {
     return set_error(XC_ERR_HIP, "%s: %s (%d)", what, hipGetErrorString(err), (int)err);
 }

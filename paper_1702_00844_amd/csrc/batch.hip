@@ -9,6 +9,7 @@
 // drain, which cost about a fifth of the time.  With one workgroup per unit the
 // next workgroup starts while the previous one's stores drain.)
 #include <algorithm>
+#include <cstdlib>
 #include <vector>
 
 #include "common.h"
@@ -158,6 +159,10 @@ xc_status xc_batch_plan_create(const xc_subarray *items, int32_t n_items, int32_
     // configurations differ (also the staging of int8 samples, which depends on
     // the station count) get one launch each.
     const xc_config one_group = {XC_KERNEL_AUTO, 0, 0, 1, XC_STAGING_AUTO, XC_PRODUCT_AUTO, 0, 0};
+    if (!cfg && !tune_cache) {
+        const char *env = getenv("XC_TUNE_CACHE");
+        if (env && *env) tune_cache = env;
+    }
     if (!cfg && tune_cache) {
         (void)xc_tune_cache_load(tune_cache);      // a missing file is an empty cache
         for (int i = 0; i < n_items; ++i) {
@@ -255,6 +260,9 @@ xc_status xc_batch_plan_create(const xc_subarray *items, int32_t n_items, int32_
     }
     (void)stream;
     *out = p;
+    log_line("batch plan: %d items, %lld work units, %zu launch%s (%s)%s%s", n_items, (long long)p->n_units,
+             p->segs.size(), p->segs.size() == 1 ? "" : "es", use_graph ? "graph" : "direct",
+             tune_cache && !cfg ? ", tune cache " : "", tune_cache && !cfg ? tune_cache : "");
     return XC_OK;
 }
 

@@ -262,6 +262,7 @@ xc_status xc_server_create(size_t hbm_budget_bytes, xc_server **out) {
     xc_server *s = new xc_server;
     s->budget = budget;
     *out = s;
+    log_line("server: device-memory budget %.3f GB", budget / 1e9);
     return XC_OK;
 }
 
@@ -278,9 +279,13 @@ xc_status xc_stream_open(xc_server *srv, const xc_stream_desc *desc, int32_t *st
     if (st != XC_OK) return st;
     std::lock_guard<std::mutex> lk(srv->mu);
     const size_t fp = xc_stream_footprint(desc);
-    if (srv->used + fp > srv->budget)
+    if (srv->used + fp > srv->budget) {
+        log_line("stream refused: %d stations x %d channels, k %d, needs %.3f GB, %.3f of %.3f GB left",
+                 desc->n_stations, desc->n_channels, desc->blocks_per_fold, fp / 1e9, (srv->budget - srv->used) / 1e9,
+                 srv->budget / 1e9);
         return set_error(XC_ERR_ADMISSION, "stream needs %zu bytes, %zu of %zu left", fp, srv->budget - srv->used,
                          srv->budget);
+    }
     Stream s;
     s.d = *desc;
     resolve(nullptr, (xc_in_type)desc->in_type, (xc_out_type)desc->acc_type, desc->n_stations, 2, desc->n_channels,
@@ -328,6 +333,9 @@ xc_status xc_stream_open(xc_server *srv, const xc_stream_desc *desc, int32_t *st
     }
     srv->streams[id] = std::move(s);
     *stream_id = id;
+    log_line("stream %d opened: %d stations x %d channels, blocks of %d samples, k %d (%s), ring %d blocks, "
+             "%.3f GB", id, desc->n_stations, desc->n_channels, desc->block_times, desc->blocks_per_fold,
+             desc->staggered ? "staggered" : "all channels", desc->ring_blocks, fp / 1e9);
     return XC_OK;
 }
 
@@ -600,6 +608,7 @@ xc_status xc_stream_close(xc_server *srv, int32_t id) {
     Stream *s = get_stream(srv, id);
     if (!s) return set_error(XC_ERR_INVALID_ARG, "no open stream %d", id);
     srv->used -= s->footprint;
+    log_line("stream %d closed after %lld blocks", id, (long long)s->committed);
     stream_free(*s);
     return XC_OK;
 }

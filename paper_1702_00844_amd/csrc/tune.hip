@@ -137,6 +137,11 @@ xc_status xc_autotune(const void *samples, xc_in_type in_type, int32_t n_station
     *best_ms = best_t;
     const TuneKey key = tune_bucket(in_type, out_type, n_stations, n_channels, n_times);
     tune_put(key, best_c);
+    log_line("tuned %d stations x %d channels x %d samples (in %d, out %d): kernel %d, block %d, time_chunk %d, "
+             "time_split %d, staging %d, product %d, tile %dx%d, %.4f ms",
+             n_stations, n_channels, n_times, (int)in_type, (int)out_type, best_c.kernel, best_c.block,
+             best_c.time_chunk, best_c.time_split, best_c.staging, best_c.product, best_c.tile_w, best_c.tile_h,
+             best_t);
     if (cache_path) {
         FILE *f = fopen(cache_path, "a");
         if (f) {
@@ -180,6 +185,7 @@ int64_t xc_tune_cache_load(const char *cache_path) {
         ++n;
     }
     fclose(f);
+    log_line("tune cache %s: %lld entries loaded", cache_path, (long long)n);
     return n;
 }
 

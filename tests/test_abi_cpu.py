@@ -376,3 +376,28 @@ def test_server_rejects_bad_stream_descriptions():
                               a["acc_type"], a["staggered"], a["block_period_s"])
         assert lib.xc_stream_open(srv, ctypes.byref(d), ctypes.byref(sid)) != 0, kw
     lib.xc_server_destroy(srv)
+
+
+def test_xc_log_records_tune_cache_loads(tmp_path):
+    """XC_LOG names a file: a tuning-cache load is logged there, one line; with
+    XC_LOG unset nothing is written.  (A fresh process each time: the library
+    reads XC_LOG once.)"""
+    import subprocess
+    import sys as _sys
+    cache = tmp_path / "tune.jsonl"
+    cache.write_text('{"in": 0, "out": 1, "sb": 2, "gran": 1, "tb": 10, "ub": 10, "kernel": 2, "block": 64, '
+                     '"time_chunk": 0, "time_split": 2, "staging": 0, "product": 0, "tile_w": 0, "tile_h": 0, '
+                     '"ms": 0.1, "S": 64, "C": 256, "T": 768}\n')
+    code = ("import sys; sys.path.insert(0, %r); import paper_1702_00844_amd as xe; "
+            "print(xe.tune_cache_load(%r))" % (os.path.dirname(os.path.dirname(os.path.abspath(__file__))), str(cache)))
+    log = tmp_path / "xc.log"
+    env = dict(os.environ, XC_LOG=str(log))
+    out = subprocess.run([_sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=120)
+    assert out.returncode == 0, out.stderr
+    n = int(out.stdout.strip().splitlines()[-1])
+    lines = log.read_text().splitlines()
+    assert lines == ["[xengine] tune cache %s: %d entries loaded" % (cache, n)], lines
+    env.pop("XC_LOG")
+    log2 = tmp_path / "none.log"
+    out = subprocess.run([_sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=120)
+    assert out.returncode == 0 and not log2.exists() and "[xengine]" not in out.stderr

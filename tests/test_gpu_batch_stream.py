@@ -113,6 +113,32 @@ def test_autotune_and_cache(tmp_path):
     assert rel_err(gpu_vis_numpy(v), oracle_vis(x)) <= 1e-5
 
 
+@pytest.mark.parametrize("via", ["argument", "environment"])
+def test_batch_plan_tunes_buckets_into_cache(tmp_path, monkeypatch, via):
+    """A batch plan without a configuration but with a tuning cache (the
+    argument, or XC_TUNE_CACHE) tunes each missing shape bucket, appends it to
+    the cache, and runs every item in its tuned configuration: results match
+    the oracle."""
+    path = str(tmp_path / "tune.jsonl")
+    # shapes in buckets no other test tunes (a bucket tuned earlier in the
+    # process is not tuned again, so nothing would be written)
+    shapes = [(24, 5, 768), (70, 3, 300)] if via == "argument" else [(40, 4, 1500), (100, 2, 2100)]
+    xs = _make("cf32", shapes, seed=140)
+    outs = [torch.empty(xe.vis_shape(s[1], s[0], xe.XC_OUT_CF32), dtype=torch.complex64, device=DEV) for s in shapes]
+    if via == "environment":
+        monkeypatch.setenv("XC_TUNE_CACHE", path)
+        plan = xe.BatchPlan(xs, outs, use_graph=True)
+    else:
+        monkeypatch.delenv("XC_TUNE_CACHE", raising=False)
+        plan = xe.BatchPlan(xs, outs, use_graph=True, tune_cache=path)
+    plan.run()
+    torch.cuda.synchronize()
+    plan.close()
+    assert os.path.exists(path)
+    assert xe.tune_cache_load(path) == len(shapes)
+    _check("cf32", xs, outs)
+
+
 def _fill_slot(ptr, blk, kind, C, bt, S):
     if kind == "ci8":
         xe.device_tensor(ptr, (C, bt, S, 2, 2), torch.int8).copy_(blk)
