@@ -9,6 +9,7 @@
 #include <string>
 
 #include "common.h"
+#include "log.h"
 
 namespace xc {
 

@@ -200,10 +200,6 @@ int device_cu_count();
 
 // Status plumbing.
 xc_status set_error(xc_status st, const char *fmt, ...);
-// One line to the log named by XC_LOG (unset or "0": no log; "1" or "stderr":
-// standard error; anything else: a file appended to), for events that happen
-// once per plan, stream or tuning run, never per correlation.
-void log_line(const char *fmt, ...) __attribute__((format(printf, 1, 2)));
 xc_status hip_error(hipError_t err, const char *what);
 
 // Validation and plan resolution shared by the entry points.

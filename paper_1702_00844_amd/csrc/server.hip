@@ -43,6 +43,7 @@
 #include <vector>
 
 #include "common.h"
+#include "log.h"
 
 namespace xc {
 xc_status resolve(const xc_config *cfg, xc_in_type in_type, xc_out_type out_type, int32_t S, int32_t P, int32_t C,

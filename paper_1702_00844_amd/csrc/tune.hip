@@ -18,6 +18,7 @@
 #include <vector>
 
 #include "common.h"
+#include "log.h"
 
 using namespace xc;
 
