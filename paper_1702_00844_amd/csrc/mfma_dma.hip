@@ -42,6 +42,8 @@ namespace xc {
 namespace dma {
 
 using mfma::Acc;
+using mfma::Out;
+using mfma::Vec;
 using mfma::K_BF16;
 using mfma::K_F16;
 using mfma::K_I8;
@@ -139,6 +141,72 @@ __device__ __forceinline__ ACC mma(const v4i &a, const v4i &b, const ACC &c) {
     else
         return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(v8bf, a), __builtin_bit_cast(v8bf, b), c, 0,
                                                        0, 0);
+}
+
+// Store (or add, in accumulate mode) one 32 x 32 tile straight from the
+// accumulators, whose column (one per lane) is the (station, pol) row
+// row0 + lane % 32 of block I and whose register r holds row
+// 8 (r / 4) + 4 (lane / 32) + r % 4 of block J's tile from col0.  Registers r
+// and r + 1 (r % 4 in {0, 2}) are the two polarisations q of one station j, so
+// a lane holds 16 consecutive bytes of V (pol p of station i against both q
+// of station j), and the 32 lanes of a half-wave write one baseline row's
+// 16 baselines, 512 contiguous bytes: eight 16-byte stores per lane and tile,
+// no LDS.  Autocorrelations (i = j) are made Hermitian on the way: XX and YY
+// get imaginary part 0 and the p = 1 lane writes YX = conj(XY), XY coming
+// from its p = 0 neighbour.  Accumulate mode loads the tile's old values
+// first (addresses of the lanes that store nothing clamped to a valid
+// baseline), so that the loads are in flight together.
+template <typename ACC, typename OUT>
+__device__ __forceinline__ void store_tile_direct(const Job &job, int c, const ACC &re, const ACC &im, int row0,
+                                                  int col0, int lane) {
+    const int S = job.S;
+    OUT *__restrict__ V = static_cast<OUT *>(job.vis) + (size_t)c * ((size_t)S * (S + 1) / 2) * 4;
+    const int m = lane & 31;
+    const int i = (row0 >> 1) + (m >> 1);
+    const int p = m & 1;
+    const bool on_diag = row0 == col0;       // the tile holds autocorrelations (wave-uniform)
+    int jj[8];
+    bool ok[8];
+    size_t e[8];                              // element index of the lane's 16 bytes (q = 0)
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const int r = (k >> 1) * 4 + (k & 1) * 2;
+        const int n = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        jj[k] = (col0 >> 1) + (n >> 1);
+        ok[k] = jj[k] < S && i <= jj[k];
+        const int jc = jj[k] < S ? jj[k] : S - 1;
+        const int ic = i <= jc ? i : jc;
+        e[k] = ((size_t)jc * (jc + 1) / 2 + ic) * 4 + p * 2;
+    }
+    uint4 old[8];
+    if (job.accumulate) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) old[k] = *reinterpret_cast<const uint4 *>(V + e[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const int r = (k >> 1) * 4 + (k & 1) * 2;
+        OUT v0 = Out<OUT>::make(re[r], im[r]);            // q = 0
+        OUT v1 = Out<OUT>::make(re[r + 1], im[r + 1]);    // q = 1
+        if (on_diag) {
+            // the p = 0 neighbour's XY (its q = 1 value), for YX = conj(XY)
+            const uint32_t xr = (uint32_t)__builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v1.x), 0xb1, 0xf, 0xf, false);
+            const uint32_t xi = (uint32_t)__builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v1.y), 0xb1, 0xf, 0xf, false);
+            if (i == jj[k]) {
+                if (p == 0) {
+                    v0.y = 0;                                  // Im XX
+                } else {
+                    v0.x = __builtin_bit_cast(decltype(v0.x), xr);
+                    v0.y = __builtin_bit_cast(decltype(v0.y), Vec<OUT>::neg(xi));
+                    v1.y = 0;                                  // Im YY
+                }
+            }
+        }
+        uint4 w = make_uint4(__builtin_bit_cast(uint32_t, v0.x), __builtin_bit_cast(uint32_t, v0.y),
+                             __builtin_bit_cast(uint32_t, v1.x), __builtin_bit_cast(uint32_t, v1.y));
+        if (job.accumulate) w = Vec<OUT>::add(w, old[k]);
+        if (ok[k]) *reinterpret_cast<uint4 *>(V + e[k]) = w;
+    }
 }
 
 // G4: 4-byte granules.  With n_stations a multiple of the 16-byte granule
@@ -321,21 +389,20 @@ __device__ __forceinline__ void unit(const Job &job, int c, int bi, int bj, uint
 #pragma unroll
                 for (int e = 0; e < 4; ++e)
                     bn[k][e] = (int)(G::I8 ? mfma::conj_neg_i8((uint32_t)b[k][e]) : mfma::conj_swap_h((uint32_t)b[k][e]));
+            // B first: the accumulator's columns (one per lane) are then the
+            // (station, pol) rows of block I, its rows (registers) those of
+            // block J, which is the order of the output in memory
 #pragma unroll
             for (int rs = 0; rs < 2; ++rs)
 #pragma unroll
-                for (int cs = 0; cs < 2; ++cs) are[rs][cs] = mma<KIND>(a[rs], b[cs], are[rs][cs]);
+                for (int cs = 0; cs < 2; ++cs) are[rs][cs] = mma<KIND>(b[cs], a[rs], are[rs][cs]);
 #pragma unroll
             for (int rs = 0; rs < 2; ++rs)
 #pragma unroll
-                for (int cs = 0; cs < 2; ++cs) aim[rs][cs] = mma<KIND>(a[rs], bn[cs], aim[rs][cs]);
+                for (int cs = 0; cs < 2; ++cs) aim[rs][cs] = mma<KIND>(bn[cs], a[rs], aim[rs][cs]);
         }
     }
-    // all copies are complete (the last chunk waited for none pending); the
-    // ring becomes the tile-image area once every wave is done reading it
-    __syncthreads();
     if (!any) return;
-    uint8_t *img = lds_generic + wave * mfma::IMG_BYTES;
     if constexpr (G::I8) {
         // the int8 accumulators hold minus the imaginary part
 #pragma unroll
@@ -343,7 +410,13 @@ __device__ __forceinline__ void unit(const Job &job, int c, int bi, int bj, uint
 #pragma unroll
             for (int cs = 0; cs < 2; ++cs) aim[rs][cs] = -aim[rs][cs];
     }
-    mfma::store_tiles_lds<acc_t, OUT>(job, c, are, aim, run, I0 * 2 + wr * SB, J0 * 2 + wc * SB, lane, img);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int rs = t >> 1, cs = t & 1;
+        if (run[rs][cs])
+            store_tile_direct<acc_t, OUT>(job, c, are[rs][cs], aim[rs][cs], I0 * 2 + wr * SB + rs * 32,
+                                          J0 * 2 + wc * SB + cs * 32, lane);
+    }
 }
 
 template <int KIND, typename OUT, bool G4, bool SM = false>
