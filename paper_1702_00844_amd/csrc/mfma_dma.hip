@@ -33,6 +33,8 @@
 //
 // Station counts that are not whole 16-byte granules (n_stations % 4 != 0 for
 // int8, odd for 16-bit) are copied in 4-byte granules (G4 below).
+#include <type_traits>
+
 #include "common.h"
 
 #include "lds_dma.h"
@@ -330,19 +332,41 @@ __device__ __forceinline__ void unit(const Job &job, int c, int bi, int bj, uint
     };
     const int npend = G4 ? nload4 : nload;    // copies per wave and chunk
 
-    // -- tiles of this wave (as in the register-staged kernels)
+    // -- tiles of this wave.  Wave (wr, wc) takes the 2 x 2 tiles of quadrant
+    // (wr, wc) of the block pair's 128 x 128 (station, pol) rows.  On a
+    // diagonal pair the quadrant below the diagonal has no outputs: its wave
+    // takes the last tile of quadrant (0, 1) instead, and the quadrants on
+    // the diagonal skip their tile below it, so no wave computes more than
+    // three tiles (a diagonal unit then takes three quarters of the time).
+    int rrow[2], ccol[2];   // first (station, pol) row of the wave's tile rows (block I) and columns (block J)
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        rrow[k] = wr * SB + 32 * k;
+        ccol[k] = wc * SB + 32 * k;
+    }
+    const bool lend = diag && wr == 0 && wc == 1;
+    const bool borrow = diag && wr == 1 && wc == 0;
+    if (borrow) {
+        rrow[0] = rrow[1] = 32;
+        ccol[0] = ccol[1] = SB + 32;
+    }
     bool run[2][2];
     bool any = false;
 #pragma unroll
     for (int rs = 0; rs < 2; ++rs)
 #pragma unroll
         for (int cs = 0; cs < 2; ++cs) {
-            const int r0 = I0 * 2 + wr * SB + rs * 32;
-            const int c0 = J0 * 2 + wc * SB + cs * 32;
+            const int r0 = I0 * 2 + rrow[rs];
+            const int c0 = J0 * 2 + ccol[cs];
             const bool below = (r0 >> 1) > ((c0 + 31) >> 1);
             run[rs][cs] = !below && r0 < 2 * S && c0 < 2 * S;
-            any |= run[rs][cs];
         }
+    if (lend) run[1][1] = false;
+    if (borrow) run[0][0] = run[0][1] = run[1][0] = false;
+#pragma unroll
+    for (int rs = 0; rs < 2; ++rs)
+#pragma unroll
+        for (int cs = 0; cs < 2; ++cs) any |= run[rs][cs];
     acc_t are[2][2], aim[2][2];
 #pragma unroll
     for (int rs = 0; rs < 2; ++rs)
@@ -354,53 +378,72 @@ __device__ __forceinline__ void unit(const Job &job, int c, int bi, int bj, uint
     uint32_t aoff[2], boff[2];
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
-        aoff[k] = frag_offset<KIND>(wr * SB + 32 * k, lane);
-        boff[k] = (diag ? 0 : G::BLK) + frag_offset<KIND>(wc * SB + 32 * k, lane);
+        aoff[k] = frag_offset<KIND>(rrow[k], lane);
+        boff[k] = (diag ? 0 : G::BLK) + frag_offset<KIND>(ccol[k], lane);
     }
 
     const int nchunk = (T + G::KT - 1) / G::KT;
 #pragma unroll
     for (int k = 0; k < NSTAGE - 1; ++k)
         if (k < nchunk) issue(k);
-    for (int ch = 0; ch < nchunk; ++ch) {
-        // this wave's copies of chunk ch are done once only those of the
-        // (at most NSTAGE - 2) chunks issued after it may be pending
-        const int later = min(nchunk - 1 - ch, NSTAGE - 2);
-        wait_vm_n(later * npend);
-        barrier_lds();
-        // every wave is past chunk ch - 1: its stage takes chunk ch + NSTAGE - 1
-        if (ch + NSTAGE - 1 < nchunk) issue(ch + NSTAGE - 1);
-        if (!any) continue;
-        const lds_u8 *sb = lds + (ch % NSTAGE) * STAGE;
-        // (The compiler reads two k-steps' fragments, then issues their
-        // MFMAs.  Reading k-step ks + 1 before the MFMAs of ks, held in place
-        // by scheduling fences, measured no faster: the other wave of the
-        // SIMD covers the LDS latency.)
+    // The chunk loop, compiled once per set of tiles a wave computes (bit
+    // 2 rs + cs for tile (rs, cs)): every tile (15), a diagonal quadrant
+    // without its tile below the diagonal (11), quadrant (0, 1) of a diagonal
+    // pair without the tile it hands over (7), the handed-over tile alone (8),
+    // none (0: the wave only copies).  Tiles past the last station are
+    // computed on clamped samples and not stored.
+    auto chunks = [&](auto mask_c) {
+        constexpr int MASK = decltype(mask_c)::value;
+        constexpr bool NA0 = MASK & 3, NA1 = MASK & 12, NB0 = MASK & 5, NB1 = MASK & 10;
+        for (int ch = 0; ch < nchunk; ++ch) {
+            // this wave's copies of chunk ch are done once only those of the
+            // (at most NSTAGE - 2) chunks issued after it may be pending
+            const int later = min(nchunk - 1 - ch, NSTAGE - 2);
+            wait_vm_n(later * npend);
+            barrier_lds();
+            // every wave is past chunk ch - 1: its stage takes chunk ch + NSTAGE - 1
+            if (ch + NSTAGE - 1 < nchunk) issue(ch + NSTAGE - 1);
+            if constexpr (MASK == 0) continue;
+            const lds_u8 *sb = lds + (ch % NSTAGE) * STAGE;
+            // (The compiler reads two k-steps' fragments, then issues their
+            // MFMAs.  Reading k-step ks + 1 before the MFMAs of ks, held in
+            // place by scheduling fences, measured no faster: the other wave
+            // of the SIMD covers the LDS latency.)
 #pragma unroll
-        for (int ks = 0; ks < G::KT / G::STEP_T; ++ks) {
-            v4i a[2], b[2], bn[2];
+            for (int ks = 0; ks < G::KT / G::STEP_T; ++ks) {
+                v4i a[2] = {}, b[2] = {}, bn[2] = {};
+                const int dt = ks * G::STEP_T * G::ROWB;
+                if constexpr (NA0) a[0] = frag<KIND>(sb + aoff[0] + dt);
+                if constexpr (NA1) a[1] = frag<KIND>(sb + aoff[1] + dt);
+                if constexpr (NB0) b[0] = frag<KIND>(sb + boff[0] + dt);
+                if constexpr (NB1) b[1] = frag<KIND>(sb + boff[1] + dt);
 #pragma unroll
-            for (int k = 0; k < 2; ++k) {
-                a[k] = frag<KIND>(sb + aoff[k] + ks * G::STEP_T * G::ROWB);
-                b[k] = frag<KIND>(sb + boff[k] + ks * G::STEP_T * G::ROWB);
+                for (int k = 0; k < 2; ++k)
+                    if ((k == 0 && NB0) || (k == 1 && NB1))
+#pragma unroll
+                        for (int e = 0; e < 4; ++e)
+                            bn[k][e] = (int)(G::I8 ? mfma::conj_neg_i8((uint32_t)b[k][e])
+                                                   : mfma::conj_swap_h((uint32_t)b[k][e]));
+                // B first: the accumulator's columns (one per lane) are then
+                // the (station, pol) rows of block I, its rows (registers)
+                // those of block J, which is the order of the output in memory
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+                    if (MASK & (1 << t)) are[t >> 1][t & 1] = mma<KIND>(b[t & 1], a[t >> 1], are[t >> 1][t & 1]);
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+                    if (MASK & (1 << t)) aim[t >> 1][t & 1] = mma<KIND>(bn[t & 1], a[t >> 1], aim[t >> 1][t & 1]);
             }
-#pragma unroll
-            for (int k = 0; k < 2; ++k)
-#pragma unroll
-                for (int e = 0; e < 4; ++e)
-                    bn[k][e] = (int)(G::I8 ? mfma::conj_neg_i8((uint32_t)b[k][e]) : mfma::conj_swap_h((uint32_t)b[k][e]));
-            // B first: the accumulator's columns (one per lane) are then the
-            // (station, pol) rows of block I, its rows (registers) those of
-            // block J, which is the order of the output in memory
-#pragma unroll
-            for (int rs = 0; rs < 2; ++rs)
-#pragma unroll
-                for (int cs = 0; cs < 2; ++cs) are[rs][cs] = mma<KIND>(b[cs], a[rs], are[rs][cs]);
-#pragma unroll
-            for (int rs = 0; rs < 2; ++rs)
-#pragma unroll
-                for (int cs = 0; cs < 2; ++cs) aim[rs][cs] = mma<KIND>(bn[cs], a[rs], aim[rs][cs]);
         }
+    };
+    // wave-uniform choice of the loop
+    const int mask = !any ? 0 : borrow ? 8 : lend ? 7 : (diag && wr == wc) ? 11 : 15;
+    switch (mask) {
+    case 15: chunks(std::integral_constant<int, 15>{}); break;
+    case 11: chunks(std::integral_constant<int, 11>{}); break;
+    case 7: chunks(std::integral_constant<int, 7>{}); break;
+    case 8: chunks(std::integral_constant<int, 8>{}); break;
+    default: chunks(std::integral_constant<int, 0>{}); break;
     }
     if (!any) return;
     if constexpr (G::I8) {
@@ -414,8 +457,8 @@ __device__ __forceinline__ void unit(const Job &job, int c, int bi, int bj, uint
     for (int t = 0; t < 4; ++t) {
         const int rs = t >> 1, cs = t & 1;
         if (run[rs][cs])
-            store_tile_direct<acc_t, OUT>(job, c, are[rs][cs], aim[rs][cs], I0 * 2 + wr * SB + rs * 32,
-                                          J0 * 2 + wc * SB + cs * 32, lane);
+            store_tile_direct<acc_t, OUT>(job, c, are[rs][cs], aim[rs][cs], I0 * 2 + rrow[rs], J0 * 2 + ccol[cs],
+                                          lane);
     }
 }
 
