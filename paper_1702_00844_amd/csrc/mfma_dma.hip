@@ -30,6 +30,13 @@
 //    on different banks: int8 granule g of row t is stored at g ^ 4 (t mod 4)
 //    (the four rows of a transpose group), 16-bit granule g at
 //    g ^ 8 ((t / 4) mod 2) (the two row sets of a wave's 4-byte reads).
+//  * The MFMAs take block J's fragment as their first operand, so that the
+//    accumulators hold V with one block-I (station, pol) row per lane: a lane
+//    then owns 16 contiguous bytes of the output, and tiles are stored
+//    straight from the registers (store_tile_direct), without an LDS image.
+//  * On a diagonal block pair the wave of the quadrant below the diagonal
+//    computes one tile of quadrant (0, 1), and the diagonal quadrants skip
+//    their tile below the diagonal, so that no wave has more than three.
 //
 // Station counts that are not whole 16-byte granules (n_stations % 4 != 0 for
 // int8, odd for 16-bit) are copied in 4-byte granules (G4 below).
@@ -58,12 +65,10 @@ constexpr int STAGE = 32768;        // bytes per stage (both blocks)
 constexpr int NSTAGE = 2;
 // Measured on 256 stations x 1024 channels x 1024 samples: two stages of
 // 32 KiB beat three of 24 KiB (0.72 against 0.80 ms for int8), two of 40 KiB
-// (0.72) and four of 16 KiB; the kernel is not bound by copy latency but by
-// its tile stores, which the two workgroups of a CU issue at the same time.
+// (0.72) and four of 16 KiB; the kernel is not bound by copy latency.
 static_assert(NSTAGE >= 2 && NSTAGE <= 4, "copies in flight are counted for up to two later chunks");
 static_assert((NSTAGE - 2) * (STAGE / 2 / 2 / 1024) < 32, "pending copies fit the vmcnt wait");
 constexpr int LDS_BYTES = NSTAGE * STAGE;
-static_assert(4 * mfma::IMG_BYTES <= LDS_BYTES, "tile images must fit the staging ring");
 
 template <int KIND>
 struct Geo {
