@@ -48,11 +48,37 @@ KERNEL_SOURCES = {
 }
 
 
+def code_text(src: str) -> str:
+    """C/C++ source without its comments, whitespace runs collapsed to one
+    space: what a change must touch to change the compiled kernel."""
+    out, i, n = [], 0, len(src)
+    while i < n:
+        ch = src[i]
+        if ch in "\"'":                       # string or character literal, kept whole
+            j = i + 1
+            while j < n and src[j] != ch:
+                j += 2 if src[j] == "\\" else 1
+            out.append(src[i:j + 1])
+            i = j + 1
+        elif src.startswith("//", i):
+            j = src.find("\n", i)
+            i = n if j < 0 else j
+        elif src.startswith("/*", i):
+            j = src.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+            out.append(" ")
+        else:
+            out.append(ch)
+            i += 1
+    return " ".join("".join(out).split())
+
+
 def source_sha(kind: str) -> str:
+    """Hash of a kernel's sources, comments and layout aside."""
     h = hashlib.sha256()
     for path in KERNEL_SOURCES[kind]:
-        with open(os.path.join(ROOT, path), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, path), encoding="utf-8") as f:
+            h.update(code_text(f.read()).encode())
     return h.hexdigest()[:16]
 
 

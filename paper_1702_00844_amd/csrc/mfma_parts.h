@@ -3,8 +3,9 @@
 // (global -> registers -> LDS, with the corner turn for 8- and 16-bit
 // samples), one chunk of MFMAs for a wave's quadrant, and the tile stores.
 // The kernels themselves are in mfma.hip (register staging, four waves per
-// workgroup) and mfma_dma.hip (copies straight into LDS), which also uses the
-// tile stores.
+// workgroup) and mfma_dma.hip (copies straight into LDS; it stores its tiles
+// straight from the accumulators and takes the sample kinds, accumulator and
+// output types and conjugation helpers from here).
 #pragma once
 #include "common.h"
 

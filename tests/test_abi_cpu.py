@@ -401,3 +401,16 @@ def test_xc_log_records_tune_cache_loads(tmp_path):
     log2 = tmp_path / "none.log"
     out = subprocess.run([_sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=120)
     assert out.returncode == 0 and not log2.exists() and "[xengine]" not in out.stderr
+
+
+def test_kernel_source_hash_ignores_comments_and_layout():
+    # bench.py reports counter-measured HBM traffic only while profiles/traffic.json
+    # was taken on the same kernel code; comments and layout are not code
+    import bench
+    src = 'int a; // "x" note\n/* block\n   comment */ const char *s = "a // b \\" /* c */";\n  x  =  1;'
+    assert bench.code_text(src) == 'int a; const char *s = "a // b \\" /* c */"; x = 1;'
+    assert bench.code_text("x = 1; // one") == bench.code_text("x  =  1;\n")
+    assert bench.code_text("x = 1;") != bench.code_text("x = 2;")
+    assert bench.code_text("c = '/';  // slash") == "c = '/';"
+    for kind in bench.KERNEL_SOURCES:
+        assert len(bench.source_sha(kind)) == 16
