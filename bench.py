@@ -391,6 +391,8 @@ def main():
     ap.add_argument("--stream-multi", type=int, default=5,
                     help="streams requested for the admission/multi-stream run at --stream-fold (0: skip)")
     ap.add_argument("--stream-multi-blocks", type=int, default=384)
+    ap.add_argument("--stream-two-k", type=int, default=16,
+                    help="k of the two-stream real-time run (spread ends, folds in order; 0: skip)")
     ap.add_argument("--no-oracle-timing", action="store_true", help="skip the oracle timing on every workload")
     ap.add_argument("--no-precision", action="store_true", help="skip the 16-bit error measurement")
     ap.add_argument("--no-fengine", action="store_true", help="skip the filter-bank measurement")
@@ -859,10 +861,11 @@ def stream_all(xe, inputs, torch, args):
     block), each over --stream-blocks blocks after a warm-up integration; the
     headline run is the smallest k whose block p99 meets the deadline.  Beside
     it: k = 8 with all channels folded every 8 blocks (the unstaggered
-    schedule), and --stream-multi streams requested at once (the server admits
-    what fits in 90 % of free device memory); the saturated multi-stream run
-    gives the device's sustained fold rate and so the number of streams it can
-    keep in real time."""
+    schedule); two streams at the real-time rate with k = --stream-two-k,
+    their integrations' ends spread over the groups' turns and their folds
+    run one at a time; and --stream-multi streams requested at once (the
+    server admits what fits in 90 % of free device memory), whose saturated
+    run gives the device's sustained fold rate."""
     out = {}
     ks = [int(v) for v in args.stream_ks.split(",") if v.strip()]
     runs = [stream_bench(xe, inputs, torch, 1, k, args.stream_blocks) for k in ks]
@@ -890,16 +893,23 @@ def stream_all(xe, inputs, torch, args):
     if args.stream_ref_blocks > 0:
         out["stream_all_channels"] = stream_bench(xe, inputs, torch, 1, args.stream_fold, args.stream_ref_blocks,
                                                   staggered=False)
+    if args.stream_two_k > 0:
+        two = stream_bench(xe, inputs, torch, 2, args.stream_two_k, args.stream_blocks, spread_ends=True,
+                           ordered=True)
+        two["all_blocks_on_time"] = two["streams_admitted"] == 2 and all(m == 0 for m in two["block_misses"])
+        out["stream_two"] = two
     if args.stream_multi > 0:
-        m = stream_bench(xe, inputs, torch, args.stream_multi, args.stream_fold, args.stream_multi_blocks)
+        m = stream_bench(xe, inputs, torch, args.stream_multi, args.stream_fold, args.stream_multi_blocks,
+                         spread_ends=True, ordered=True)
         total = sum(m["sustained_TFLOP/s"])
         m["device_sustained_TFLOP/s"] = round(total, 1)
-        m["sustainable_streams"] = int(total // m["realtime_TFLOP/s_needed_per_stream"])
+        m["streams_by_device_rate"] = int(total // m["realtime_TFLOP/s_needed_per_stream"])
         out["stream_multi"] = m
     return out
 
 
-def stream_bench(xe, inputs, torch, n_streams, k, n_blocks, S=512, C=4096, bt=256, bpi=192, staggered=True):
+def stream_bench(xe, inputs, torch, n_streams, k, n_blocks, S=512, C=4096, bt=256, bpi=192, staggered=True,
+                 spread_ends=False, ordered=False):
     """Streaming: 512 stations, 4096 channels, complex int8 blocks of 256
     samples arriving every P = 256 / 49152 s (192 blocks = one second per
     integration), every channel folded every k blocks into resident int32
@@ -909,12 +919,16 @@ def stream_bench(xe, inputs, torch, n_streams, k, n_blocks, S=512, C=4096, bt=25
     scheduled host time t0 + n P.  Block latency = completion of the last fold
     covering it - its arrival, against the deadline k P; fold latency =
     completion - arrival of the block that triggered it.  Streams that the
-    server refuses for lack of device memory are counted, not run."""
+    server refuses for lack of device memory are counted, not run.
+    spread_ends: each channel group folds its leftover of an integration at
+    its next turn; ordered: the streams' folds run one at a time in enqueue
+    order."""
     P = bt / 49152.0
     torch.cuda.empty_cache()    # the admission budget is a share of the free device memory
     srv = xe.Server()
+    srv.set_fold_order(ordered)
     desc = xe.Server.desc(S, C, bt, bpi, blocks_per_fold=k, ring_blocks=2 * k, in_type=xe.XC_IN_CI8,
-                          acc_type=xe.XC_OUT_CI32, block_period_s=P, staggered=staggered)
+                          acc_type=xe.XC_OUT_CI32, block_period_s=P, staggered=staggered, spread_ends=spread_ends)
     fp = xe.Server.footprint(desc)
     sids, admitted, refused = [], 0, 0
     for _ in range(n_streams):
@@ -969,7 +983,7 @@ def stream_bench(xe, inputs, torch, n_streams, k, n_blocks, S=512, C=4096, bt=25
     return {"workload": f"{S} stations, {C} channels, complex int8 blocks of {bt} samples every "
                         f"{P * 1e3:.3f} ms, {bpi} blocks per integration, every channel folded every {k} blocks "
                         + ("(staggered: one channel group per block)" if staggered else "(all channels at once)"),
-            "k": k, "staggered": staggered,
+            "k": k, "staggered": staggered, "spread_ends": spread_ends, "fold_order": ordered,
             "streams_requested": n_streams, "streams_admitted": admitted, "streams_refused": refused,
             "footprint_GB": round(fp / 1e9, 1), "deadline_ms": round(k * P * 1e3, 3),
             "block_p50_ms": [round(p["p50_ms"], 3) for p in per],

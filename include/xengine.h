@@ -425,7 +425,15 @@ typedef struct xc_stream_desc {
     int32_t staggered;              /* 0: every k blocks, one fold of all channels;
                                        1: the channels in k groups, one group folded
                                        per committed block (its outstanding blocks),
-                                       every group at the end of an integration     */
+                                       every group at the end of an integration;
+                                       2: as 1, but at the end of an integration each
+                                       group keeps its outstanding blocks until its
+                                       next turn (at most k - 1 blocks later) and folds
+                                       them then, into that integration's accumulator,
+                                       so that every block period gets one group's
+                                       fold; an integration is published once every
+                                       group has folded past its end, or by
+                                       xc_stream_flush                               */
     double block_period_s;          /* arrival period P; block deadline = k * P      */
 } xc_stream_desc;
 
@@ -456,6 +464,17 @@ typedef struct xc_server xc_server;
 xc_status xc_server_create(size_t hbm_budget_bytes, xc_server **out);
 /* Waits for every stream's work and frees everything. */
 void xc_server_destroy(xc_server *srv);
+
+/* Fold order across the server's streams (Section 1: the correlator must keep
+ * up with every stream it takes).  0 (the default): each stream's folds run on
+ * its own HIP stream, concurrently with the other streams'.  1: every fold
+ * enqueued from now on waits for the one the server enqueued before it
+ * (whatever its stream), so folds run one at a time in enqueue order: streams
+ * whose blocks arrive together then do not split the device for the length of
+ * each fold.  A stream's hold (xc_stream_hold) or a consumer's late release
+ * then delays the folds of the other streams enqueued after it as well.
+ * Errors: XC_ERR_INVALID_ARG (null server, value not 0 or 1). */
+xc_status xc_server_set_fold_order(xc_server *srv, int32_t one_at_a_time);
 
 /* Device bytes one stream needs: two resident accumulators (one integrating,
  * one published) plus the ring of sample blocks.  0 on bad args. */
@@ -535,6 +554,14 @@ xc_status xc_stream_stats(xc_server *srv, int32_t stream_id, xc_latency_stats *s
  * records (the next xc_stream_stats covers only blocks committed after this
  * call).  Integration state is unchanged. */
 xc_status xc_stream_reset_stats(xc_server *srv, int32_t stream_id);
+
+/* Staggered = 2: folds now what the channel groups have left of every
+ * integration whose blocks have all been committed, and publishes them (for a
+ * stream that stops, or pauses, at the end of an integration).  The blocks of
+ * the integration in progress are left to their groups' turns.  No effect for
+ * the other schedules, which fold everything at an integration's last block.
+ * Errors: XC_ERR_INVALID_ARG (no such stream), XC_ERR_HIP. */
+xc_status xc_stream_flush(xc_server *srv, int32_t stream_id);
 
 /* Waits for the stream's work (ending any hold) and frees its buffers. */
 xc_status xc_stream_close(xc_server *srv, int32_t stream_id);

@@ -485,14 +485,25 @@ class Server:
 
     @staticmethod
     def desc(n_stations, n_channels, block_times, blocks_per_integration, blocks_per_fold=1, ring_blocks=0,
-             in_type=XC_IN_CI8, acc_type=XC_OUT_CI32, block_period_s=0.0, staggered=True):
+             in_type=XC_IN_CI8, acc_type=XC_OUT_CI32, block_period_s=0.0, staggered=True, spread_ends=False):
         """Stream descriptor; staggered folds one of k channel groups per block
         (every channel still every k blocks), otherwise all channels every k
-        blocks."""
+        blocks.  spread_ends (staggered only): each group folds what it has
+        left of an integration at its next turn instead of all groups at the
+        integration's last block."""
         if ring_blocks == 0:
             ring_blocks = 2 * blocks_per_fold
+        mode = (2 if spread_ends else 1) if staggered else 0
         return _lib.XcStreamDesc(n_stations, 2, n_channels, block_times, blocks_per_integration, blocks_per_fold,
-                                 ring_blocks, in_type, acc_type, 1 if staggered else 0, block_period_s)
+                                 ring_blocks, in_type, acc_type, mode, block_period_s)
+
+    def set_fold_order(self, one_at_a_time: bool):
+        """True: the folds of all streams run one at a time, in enqueue order."""
+        _lib.check(lib().xc_server_set_fold_order(self._h, 1 if one_at_a_time else 0))
+
+    def flush(self, sid: int):
+        """Folds and publishes what is left of complete integrations (spread ends)."""
+        _lib.check(lib().xc_stream_flush(self._h, sid))
 
     @staticmethod
     def footprint(desc) -> int:

@@ -27,7 +27,21 @@
 //     ends within (k - 1) P + (one fold of C/k channels) of its arrival.  At
 //     the end of an integration every group folds what it has left (oldest
 //     pending block first), so that the integration is complete when it is
-//     published.
+//     published;
+//   - staggered, ends spread (staggered = 2): the same, except that at the
+//     end of an integration each group keeps what it has left until its next
+//     turn, k - 1 blocks at most, and then folds it (into the old
+//     integration's accumulator) together with its first blocks of the new
+//     one.  The device then gets one group's fold per block period throughout
+//     instead of up to k of them at the last block; each block still meets
+//     its deadline, and an integration is published once every group has
+//     folded past its end (k - 2 blocks into the next one), or on
+//     xc_stream_flush.
+// Folds of different streams run concurrently on their own HIP streams, or,
+// with xc_server_set_fold_order, one at a time in the order they are
+// enqueued (each waits for the server's previous fold): streams whose blocks
+// arrive together then no longer share the device through each fold, so each
+// fold takes its own time instead of both taking twice as long.
 // A block's latency runs from its arrival to the completion of the last fold
 // that covers it; its deadline is D = k P.  A fold's latency runs from the
 // arrival of the block that triggered it to its completion, against the
@@ -121,6 +135,7 @@ struct Stream {
     hipEvent_t ready_ev[2] = {nullptr, nullptr};    // recorded after an integration's last fold
     hipEvent_t release_ev[2] = {nullptr, nullptr};  // recorded on a consumer's stream by xc_stream_release
     hipEvent_t fill_ev = nullptr;                   // recorded on a producer's stream by xc_stream_commit_after
+    hipEvent_t fold_ev = nullptr;                   // recorded after each fold (fold order across streams)
     int32_t *hold_flag = nullptr;                   // host-coherent flag that ends a hold (xc_stream_hold)
     bool release_pending[2] = {false, false};
     int64_t published_seq = -1;
@@ -144,6 +159,8 @@ struct xc_server {
     size_t budget = 0;
     size_t used = 0;
     std::vector<Stream> streams;
+    bool ordered = false;   // folds of all streams one at a time, in enqueue order
+    int last_fold = -1;     // stream that enqueued the latest fold (ordered)
 };
 
 static xc_status validate_desc(const xc_stream_desc *d) {
@@ -156,7 +173,7 @@ static xc_status validate_desc(const xc_stream_desc *d) {
         return set_error(XC_ERR_INVALID_ARG, "blocks_per_integration must be a multiple of blocks_per_fold");
     if (d->ring_blocks < 2 * d->blocks_per_fold)
         return set_error(XC_ERR_INVALID_ARG, "ring_blocks must be >= 2 * blocks_per_fold");
-    if (d->staggered != 0 && d->staggered != 1) return set_error(XC_ERR_INVALID_ARG, "staggered must be 0 or 1");
+    if (d->staggered < 0 || d->staggered > 2) return set_error(XC_ERR_INVALID_ARG, "staggered must be 0, 1 or 2");
     if (!(d->block_period_s >= 0.0)) return set_error(XC_ERR_INVALID_ARG, "block_period_s must be >= 0");
     const int64_t T_int = (int64_t)d->block_times * d->blocks_per_integration;
     if (d->acc_type == XC_OUT_CI32 && T_int > XC_CI32_MAX_TIMES)
@@ -183,6 +200,7 @@ static void stream_free(Stream &s) {
         if (s.release_ev[k]) (void)hipEventDestroy(s.release_ev[k]);
     }
     if (s.fill_ev) (void)hipEventDestroy(s.fill_ev);
+    if (s.fold_ev) (void)hipEventDestroy(s.fold_ev);
     if (s.hold_flag) (void)hipHostFree(s.hold_flag);
     if (s.hs) (void)hipStreamDestroy(s.hs);
     s = Stream{};
@@ -196,8 +214,9 @@ static void group_channels(const Stream &s, int g, int &c0, int &c1) {
 }
 
 // Enqueues the fold of channel group g over blocks first .. last (absolute
-// numbers, all in one integration) and records it.
-static xc_status enqueue_fold(Stream &s, int g, int64_t first, int64_t last, int64_t trigger) {
+// numbers, all in one integration) after prev's latest fold (if not null),
+// and records it.
+static xc_status enqueue_fold(Stream &s, const Stream *prev, int g, int64_t first, int64_t last, int64_t trigger) {
     int c0, c1;
     group_channels(s, g, c0, c1);
     if (c1 <= c0) return XC_OK;
@@ -213,8 +232,16 @@ static xc_status enqueue_fold(Stream &s, int g, int64_t first, int64_t last, int
     job.bstride = s.block_elems;
     job.slot0 = slot0;
     job.nring = s.d.ring_blocks;
+    if (prev) {
+        hipError_t e = hipStreamWaitEvent(s.hs, prev->fold_ev, 0);
+        if (e != hipSuccess) return hip_error(e, "fold order");
+    }
     xc_status st = launch_plan(s.plan, (xc_in_type)s.d.in_type, (xc_out_type)s.d.acc_type, job, s.hs);
     if (st != XC_OK) return st;
+    {
+        hipError_t e = hipEventRecord(s.fold_ev, s.hs);
+        if (e != hipSuccess) return hip_error(e, "fold event");
+    }
     FoldDone *rec = new FoldDone;
     hipError_t e = hipLaunchHostFunc(s.hs, on_fold_done, rec);
     if (e != hipSuccess) {
@@ -312,6 +339,7 @@ xc_status xc_stream_open(xc_server *srv, const xc_stream_desc *desc, int32_t *st
         if (e == hipSuccess) e = hipEventCreateWithFlags(&s.release_ev[k], hipEventDisableTiming);
     }
     if (e == hipSuccess) e = hipEventCreateWithFlags(&s.fill_ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&s.fold_ev, hipEventDisableTiming);
     if (e == hipSuccess) e = hipHostMalloc((void **)&s.hold_flag, sizeof(int32_t), hipHostMallocCoherent);
     if (e == hipSuccess) __atomic_store_n(s.hold_flag, 1, __ATOMIC_RELEASE);
     if (e != hipSuccess) {
@@ -336,7 +364,8 @@ xc_status xc_stream_open(xc_server *srv, const xc_stream_desc *desc, int32_t *st
     *stream_id = id;
     log_line("stream %d opened: %d stations x %d channels, blocks of %d samples, k %d (%s), ring %d blocks, "
              "%.3f GB", id, desc->n_stations, desc->n_channels, desc->block_times, desc->blocks_per_fold,
-             desc->staggered ? "staggered" : "all channels", desc->ring_blocks, fp / 1e9);
+             desc->staggered == 2 ? "staggered, ends spread" : desc->staggered ? "staggered" : "all channels",
+             desc->ring_blocks, fp / 1e9);
     return XC_OK;
 }
 
@@ -364,7 +393,40 @@ xc_status xc_stream_acquire(xc_server *srv, int32_t id, void **block_dev_ptr) {
     return XC_OK;
 }
 
-static xc_status commit_locked(Stream *s, int32_t id, uint64_t arrival_ns, hipStream_t producer) {
+// Folds group g of stream id over blocks first .. last, one fold per
+// integration they fall in, in the server's fold order.
+static xc_status fold_range(xc_server *srv, Stream &s, int32_t id, int g, int64_t first, int64_t last,
+                            int64_t trigger) {
+    const int64_t bpi = s.d.blocks_per_integration;
+    while (first <= last) {
+        const int64_t end = std::min(last, (first / bpi + 1) * bpi - 1);
+        const Stream *prev = nullptr;
+        if (srv->ordered && srv->last_fold >= 0 && srv->last_fold != id && srv->streams[srv->last_fold].open)
+            prev = &srv->streams[srv->last_fold];
+        xc_status st = enqueue_fold(s, prev, g, first, end, trigger);
+        if (st != XC_OK) return st;
+        srv->last_fold = id;
+        first = end + 1;
+    }
+    return XC_OK;
+}
+
+// Spread ends: publishes every integration whose blocks have all been
+// committed and folded by every group.
+static xc_status publish_folded(Stream &s) {
+    const int64_t bpi = s.d.blocks_per_integration;
+    int64_t folded = s.committed;
+    for (int64_t g : s.group_next) folded = std::min(folded, g);
+    while ((s.published_seq + 2) * bpi <= folded) {
+        const int64_t j = s.published_seq + 1;
+        hipError_t e = hipEventRecord(s.ready_ev[j % 2], s.hs);
+        if (e != hipSuccess) return hip_error(e, "integration event");
+        s.published_seq = j;
+    }
+    return XC_OK;
+}
+
+static xc_status commit_locked(xc_server *srv, Stream *s, int32_t id, uint64_t arrival_ns, hipStream_t producer) {
     if (!s->acquired) return set_error(XC_ERR_STATE, "stream %d: commit without acquire", id);
     if (producer) {
         // the folds that read this slot run after the producer's work so far
@@ -379,6 +441,7 @@ static xc_status commit_locked(Stream *s, int32_t id, uint64_t arrival_ns, hipSt
     const int64_t bpi = s->d.blocks_per_integration;
     const int64_t integ = n / bpi, m = n % bpi;
     const int k = s->d.blocks_per_fold;
+    const bool spread = s->d.staggered == 2;
     if (m == 0) {
         // a new integration starts: its accumulator held integration integ - 2,
         // which a consumer may still be reading
@@ -387,14 +450,23 @@ static xc_status commit_locked(Stream *s, int32_t id, uint64_t arrival_ns, hipSt
             if (e != hipSuccess) return hip_error(e, "release event");
             s->release_pending[integ % 2] = false;
         }
-        for (auto &g : s->group_next) g = n;
+        if (!spread)
+            for (auto &g : s->group_next) g = n;
     }
     const bool last = m == bpi - 1;
     xc_status st = XC_OK;
     if (s->groups == 1) {
         if ((m + 1) % k == 0) {
-            st = enqueue_fold(*s, 0, s->group_next[0], n, n);
+            st = fold_range(srv, *s, id, 0, s->group_next[0], n, n);
             s->group_next[0] = n + 1;
+        }
+    } else if (spread) {
+        // group m mod k folds its outstanding blocks, the rest of the last
+        // integration first
+        const int g = (int)(m % k);
+        if (s->group_next[g] <= n) {
+            st = fold_range(srv, *s, id, g, s->group_next[g], n, n);
+            s->group_next[g] = n + 1;
         }
     } else {
         // group m mod k folds its outstanding blocks.  At the end of the
@@ -407,12 +479,13 @@ static xc_status commit_locked(Stream *s, int32_t id, uint64_t arrival_ns, hipSt
         std::stable_sort(order.begin(), order.end(),
                          [&](int a, int b) { return s->group_next[a] < s->group_next[b]; });
         for (int g : order) {
-            st = enqueue_fold(*s, g, s->group_next[g], n, n);
+            st = fold_range(srv, *s, id, g, s->group_next[g], n, n);
             if (st != XC_OK) break;
             s->group_next[g] = n + 1;
         }
     }
     if (st != XC_OK) return st;
+    if (spread) return publish_folded(*s);
     if (last) {
         hipError_t e = hipEventRecord(s->ready_ev[integ % 2], s->hs);
         if (e != hipSuccess) return hip_error(e, "integration event");
@@ -426,7 +499,7 @@ xc_status xc_stream_commit(xc_server *srv, int32_t id, uint64_t arrival_ns) {
     std::lock_guard<std::mutex> lk(srv->mu);
     Stream *s = get_stream(srv, id);
     if (!s) return set_error(XC_ERR_INVALID_ARG, "no open stream %d", id);
-    return commit_locked(s, id, arrival_ns, nullptr);
+    return commit_locked(srv, s, id, arrival_ns, nullptr);
 }
 
 xc_status xc_stream_commit_after(xc_server *srv, int32_t id, uint64_t arrival_ns, void *producer_stream) {
@@ -434,7 +507,7 @@ xc_status xc_stream_commit_after(xc_server *srv, int32_t id, uint64_t arrival_ns
     std::lock_guard<std::mutex> lk(srv->mu);
     Stream *s = get_stream(srv, id);
     if (!s) return set_error(XC_ERR_INVALID_ARG, "no open stream %d", id);
-    return commit_locked(s, id, arrival_ns, static_cast<hipStream_t>(producer_stream));
+    return commit_locked(srv, s, id, arrival_ns, static_cast<hipStream_t>(producer_stream));
 }
 
 xc_status xc_stream_integration(xc_server *srv, int32_t id, int64_t k, const void **vis, void **ready) {
@@ -603,11 +676,40 @@ xc_status xc_stream_reset_stats(xc_server *srv, int32_t id) {
     return XC_OK;
 }
 
+xc_status xc_stream_flush(xc_server *srv, int32_t id) {
+    if (!srv) return set_error(XC_ERR_INVALID_ARG, "null server");
+    std::lock_guard<std::mutex> lk(srv->mu);
+    Stream *s = get_stream(srv, id);
+    if (!s) return set_error(XC_ERR_INVALID_ARG, "no open stream %d", id);
+    if (s->d.staggered != 2) return XC_OK;     // nothing is left over past an integration's end
+    const int64_t end = s->committed / s->d.blocks_per_integration * s->d.blocks_per_integration;
+    std::vector<int> order;
+    for (int g = 0; g < s->groups; ++g)
+        if (s->group_next[g] < end) order.push_back(g);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return s->group_next[a] < s->group_next[b]; });
+    for (int g : order) {
+        xc_status st = fold_range(srv, *s, id, g, s->group_next[g], end - 1, s->committed - 1);
+        if (st != XC_OK) return st;
+        s->group_next[g] = end;
+    }
+    return publish_folded(*s);
+}
+
+xc_status xc_server_set_fold_order(xc_server *srv, int32_t one_at_a_time) {
+    if (!srv) return set_error(XC_ERR_INVALID_ARG, "null server");
+    if (one_at_a_time != 0 && one_at_a_time != 1) return set_error(XC_ERR_INVALID_ARG, "one_at_a_time must be 0 or 1");
+    std::lock_guard<std::mutex> lk(srv->mu);
+    srv->ordered = one_at_a_time != 0;
+    srv->last_fold = -1;
+    return XC_OK;
+}
+
 xc_status xc_stream_close(xc_server *srv, int32_t id) {
     if (!srv) return set_error(XC_ERR_INVALID_ARG, "null server");
     std::lock_guard<std::mutex> lk(srv->mu);
     Stream *s = get_stream(srv, id);
     if (!s) return set_error(XC_ERR_INVALID_ARG, "no open stream %d", id);
+    if (srv->last_fold == id) srv->last_fold = -1;
     srv->used -= s->footprint;
     log_line("stream %d closed after %lld blocks", id, (long long)s->committed);
     stream_free(*s);

@@ -364,7 +364,7 @@ def test_server_rejects_bad_stream_descriptions():
     sid = ctypes.c_int32()
     bad = [dict(blocks_per_fold=3, blocks_per_integration=8),          # not a multiple
            dict(ring_blocks=3, blocks_per_fold=2),                     # fewer than two folds of slots
-           dict(staggered=2), dict(n_pol=1), dict(block_times=0),
+           dict(staggered=3), dict(staggered=-1), dict(n_pol=1), dict(block_times=0),
            dict(acc_type=_lib.XC_OUT_CI32, block_times=512, blocks_per_integration=256)]   # int32 bound
     for kw in bad:
         a = dict(n_stations=8, n_channels=2, block_times=16, blocks_per_integration=4, blocks_per_fold=2,
@@ -375,6 +375,12 @@ def test_server_rejects_bad_stream_descriptions():
                               a["blocks_per_integration"], a["blocks_per_fold"], a["ring_blocks"], a["in_type"],
                               a["acc_type"], a["staggered"], a["block_period_s"])
         assert lib.xc_stream_open(srv, ctypes.byref(d), ctypes.byref(sid)) != 0, kw
+    # fold order: 0 or 1 only; no stream to flush (1 = XC_ERR_INVALID_ARG)
+    assert lib.xc_server_set_fold_order(None, 1) == 1
+    assert lib.xc_server_set_fold_order(srv, 2) == 1
+    assert lib.xc_server_set_fold_order(srv, 1) == 0 and lib.xc_server_set_fold_order(srv, 0) == 0
+    assert lib.xc_stream_flush(srv, 0) == 1
+    assert lib.xc_stream_flush(None, 0) == 1
     lib.xc_server_destroy(srv)
 
 

@@ -161,12 +161,15 @@ def _acquire(srv, sid):
 
 # block_times 24: the int8 kernel's 64-step chunks straddle the ring slots of a
 # fold; k = 3 with a ring of 7 slots makes folds wrap around the ring's end;
-# staggered folds give each channel group its own fold boundaries
+# staggered folds give each channel group its own fold boundaries ("spread":
+# staggered with the groups' leftovers folded at their next turn, flushed at
+# the end of every integration here)
 @pytest.mark.parametrize("kind,bt,k,ring,staggered,events", [
     ("ci8", 32, 2, 4, False, False), ("ci8", 24, 2, 4, True, False), ("ci8", 24, 3, 7, True, True),
     ("cf32", 32, 2, 4, True, True), ("cf32", 16, 3, 7, False, False), ("cf16", 32, 2, 5, True, False),
-    ("cbf16", 24, 2, 4, False, True)],
-    ids=["ci8_all", "ci8_stag", "ci8_stag_wrap_ev", "cf32_stag_ev", "cf32_all_wrap", "cf16_stag", "cbf16_all_ev"])
+    ("cbf16", 24, 2, 4, False, True), ("ci8", 24, 3, 7, "spread", True), ("cf32", 32, 2, 4, "spread", False)],
+    ids=["ci8_all", "ci8_stag", "ci8_stag_wrap_ev", "cf32_stag_ev", "cf32_all_wrap", "cf16_stag", "cbf16_all_ev",
+         "ci8_spread_wrap_ev", "cf32_spread"])
 def test_stream_integrations_match_oracle(kind, bt, k, ring, staggered, events):
     """Every integration read back through xc_stream_integration (its ready
     event waited on by a consumer stream) equals the oracle over its blocks;
@@ -178,7 +181,7 @@ def test_stream_integrations_match_oracle(kind, bt, k, ring, staggered, events):
     in_type = {"ci8": xe.XC_IN_CI8, "cf32": xe.XC_IN_CF32, "cf16": xe.XC_IN_CF16, "cbf16": xe.XC_IN_CBF16}[kind]
     acc = xe.XC_OUT_CI32 if kind == "ci8" else xe.XC_OUT_CF32
     d = xe.Server.desc(S, C, bt, bpi, blocks_per_fold=k, ring_blocks=ring, in_type=in_type, acc_type=acc,
-                       block_period_s=0.001, staggered=staggered)
+                       block_period_s=0.001, staggered=bool(staggered), spread_ends=staggered == "spread")
     sid = srv.open(d)
     producer, consumer = torch.cuda.Stream(), torch.cuda.Stream()
     blocks = []
@@ -204,6 +207,8 @@ def test_stream_integrations_match_oracle(kind, bt, k, ring, staggered, events):
             srv.commit(sid, time.monotonic_ns())
         if (b + 1) % bpi == 0:
             n = (b + 1) // bpi - 1
+            if staggered == "spread":
+                srv.flush(sid)
             shape = xe.vis_shape(C, S, acc)
             with torch.cuda.stream(consumer):
                 vptr = srv.wait_integration(sid, n, stream=consumer)     # the host does not wait
@@ -237,6 +242,86 @@ def test_stream_integrations_match_oracle(kind, bt, k, ring, staggered, events):
     srv.reset_stats(sid)
     assert srv.stats(sid)["blocks"] == 0
     srv.close_stream(sid)
+    srv.close()
+
+
+def _commit_blocks(srv, sid, blocks, C, bt, S):
+    for blk in blocks:
+        ptr = _acquire(srv, sid)
+        _fill_slot(ptr, blk, "ci8", C, bt, S)
+        torch.cuda.synchronize()
+        srv.commit(sid, time.monotonic_ns())
+
+
+def _read_integration(srv, sid, n, C, S):
+    vptr = srv.wait_integration(sid, n, stream=torch.cuda.current_stream())
+    got = xe.device_tensor(vptr, xe.vis_shape(C, S, xe.XC_OUT_CI32), torch.int32).clone()
+    torch.cuda.synchronize()
+    return gpu_vis_numpy(got)
+
+
+def test_stream_spread_ends_publish_after_the_groups_turns():
+    """Spread ends (k = 3): an integration's leftovers are folded at the
+    groups' next turns, so integration 0 is published with block bpi + 1 (the
+    last group with a leftover), not before; integration 1, whose stream stops
+    at its end, is published by xc_stream_flush.  Both equal the oracle, and
+    the folds are one per block plus one extra piece per leftover."""
+    S, C, bt, bpi, k = 20, 5, 24, 6, 3
+    srv = xe.Server()
+    sid = srv.open(xe.Server.desc(S, C, bt, bpi, blocks_per_fold=k, ring_blocks=7, block_period_s=0.001,
+                                  staggered=True, spread_ends=True))
+    blocks = [inputs.ci8_gaussian(C, bt, S, seed=900 + b, device=DEV) for b in range(2 * bpi)]
+    _commit_blocks(srv, sid, blocks[:bpi + 1], C, bt, S)
+    assert srv.latest(sid)[1] == -1          # groups 0 and 1 still hold blocks 4, 5 and 5
+    _commit_blocks(srv, sid, blocks[bpi + 1:bpi + 2], C, bt, S)
+    assert srv.latest(sid)[1] == 0
+    ref0 = oracle_vis(torch.cat(blocks[:bpi], dim=1))
+    assert np.array_equal(_read_integration(srv, sid, 0, C, S), ref0)
+    _commit_blocks(srv, sid, blocks[bpi + 2:], C, bt, S)
+    assert srv.latest(sid)[1] == 0
+    srv.flush(sid)
+    assert srv.latest(sid)[1] == 1
+    ref1 = oracle_vis(torch.cat(blocks[bpi:], dim=1))
+    assert np.array_equal(_read_integration(srv, sid, 1, C, S), ref1)
+    st = srv.stats(sid)
+    # 12 turns, blocks 6 and 7 fold two pieces each, the flush folds groups 0 and 1
+    assert st["blocks"] == 2 * bpi and st["pending"] == 0 and st["folds"] == 16
+    assert st["integrations"] == 2
+    srv.close_stream(sid)
+    srv.close()
+
+
+@pytest.mark.parametrize("spread", [False, True], ids=["staggered", "spread"])
+def test_stream_fold_order_across_streams(spread):
+    """With the server's fold order on, two streams committed in turn (and a
+    third opened and closed on the way) still produce exactly the oracle's
+    integrations; the order can be switched off and on between blocks."""
+    S, C, bt, bpi, k = 36, 6, 32, 4, 2
+    srv = xe.Server()
+    srv.set_fold_order(True)
+    d = xe.Server.desc(S, C, bt, bpi, blocks_per_fold=k, ring_blocks=2 * k, block_period_s=0.001,
+                       staggered=True, spread_ends=spread)
+    sids = [srv.open(d), srv.open(d)]
+    blocks = {sid: [inputs.ci8_gaussian(C, bt, S, seed=1300 + 97 * sid + b, device=DEV) for b in range(2 * bpi)]
+              for sid in sids}
+    for b in range(2 * bpi):
+        if b == bpi // 2:
+            extra = srv.open(d)
+            _commit_blocks(srv, extra, [blocks[sids[0]][0]], C, bt, S)
+            srv.close_stream(extra)
+        if b == bpi:
+            srv.set_fold_order(False)
+        if b == bpi + 1:
+            srv.set_fold_order(True)
+        for sid in sids:
+            _commit_blocks(srv, sid, [blocks[sid][b]], C, bt, S)
+    for sid in sids:
+        srv.flush(sid)
+        for n in range(2):
+            ref = oracle_vis(torch.cat(blocks[sid][n * bpi:(n + 1) * bpi], dim=1))
+            assert np.array_equal(_read_integration(srv, sid, n, C, S), ref), (sid, n)
+        st = srv.stats(sid)
+        assert st["blocks"] == 2 * bpi and st["pending"] == 0
     srv.close()
 
 
