@@ -112,6 +112,13 @@ int main(int argc, char **argv) {
     if (st == XC_OK) CHECK(xc_stream_close(srv, id) == XC_OK);   /* a GPU is present after all */
     else CHECK(st == XC_ERR_HIP || st == XC_ERR_OUT_OF_MEMORY);
     CHECK(xc_stream_close(srv, 99) == XC_ERR_INVALID_ARG);
+    bad_d = d;
+    bad_d.staggered = 3;
+    CHECK(xc_stream_open(srv, &bad_d, &id) == XC_ERR_INVALID_ARG);
+    CHECK(xc_server_set_fold_order(srv, 1) == XC_OK && xc_server_set_fold_order(srv, 0) == XC_OK);
+    CHECK(xc_server_set_fold_order(srv, 2) == XC_ERR_INVALID_ARG);
+    CHECK(xc_server_set_fold_order(NULL, 1) == XC_ERR_INVALID_ARG);
+    CHECK(xc_stream_flush(srv, 99) == XC_ERR_INVALID_ARG);
     xc_server_destroy(srv);
 
     if (failures) {
