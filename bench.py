@@ -833,6 +833,16 @@ def fengine_bench(xe, inputs, torch, dev, stream, steps=20):
         fb.run(z, taps, out=x, stream=stream)
         xe.correlate_into(x, o, stream=stream)
     ms_fx = time_launches(fx, steps, 3, stream)
+    # one kernel into the station-major layout, correlated from it
+    SM = xe.XC_LAYOUT_STATION_MAJOR
+    xs = torch.empty(fb.out_shape(SM), dtype=torch.complex64, device=dev)
+    ms_fs = time_launches(lambda: fb.run(z, taps, out=xs, stream=stream, layout=SM), steps, 3, stream)
+    ms_xs = time_launches(lambda: xe.correlate_into(xs, o, stream=stream, layout=SM), steps, 3, stream)
+
+    def fxs():
+        fb.run(z, taps, out=xs, stream=stream, layout=SM)
+        xe.correlate_into(xs, o, stream=stream, layout=SM)
+    ms_fxs = time_launches(fxs, steps, 3, stream)
     alg = (z.numel() + x.numel()) * 8
     moved = alg + 2 * x.numel() * 8
     flops_f = x.numel() * (4 * M + 5 * math.log2(N))
@@ -849,8 +859,18 @@ def fengine_bench(xe, inputs, torch, dev, stream, steps=20):
                       "traffic": traffic, "bytes_moved_incl_intermediate_GB/s": round(moved / (ms_f * 1e-3) / 1e9, 1)},
          "filter_bank_TFLOP/s": round(flops_f / (ms_f * 1e-3) / 1e12, 2),
          "correlator_ms": round(ms_x, 4), "f_then_x_ms": round(ms_fx, 4),
-         "f_then_x_correlator_TFLOP/s": round(flops_x / (ms_fx * 1e-3) / 1e12, 1)}
-    del z, x, o
+         "f_then_x_correlator_TFLOP/s": round(flops_x / (ms_fx * 1e-3) / 1e12, 1),
+         "station_major": {
+             "note": "one kernel writes x[N][S][T][2]; the correlator takes it as station-major input",
+             "filter_bank_ms": round(ms_fs, 4),
+             "filter_bank_Gsamples/s": round(z.numel() / (ms_fs * 1e-3) / 1e9, 1),
+             "roofline": {"bound": "hbm", "achieved": round(alg / (ms_fs * 1e-3) / 1e9, 1),
+                          "peak": PEAKS["hbm_GBs"], "unit": "GB/s",
+                          "frac": round(alg / (ms_fs * 1e-3) / 1e9 / PEAKS["hbm_GBs"], 4),
+                          "traffic": load_traffic("fengine_filter_fft_sm", "pfb")},
+             "correlator_ms": round(ms_xs, 4), "f_then_x_ms": round(ms_fxs, 4),
+             "f_then_x_correlator_TFLOP/s": round(flops_x / (ms_fxs * 1e-3) / 1e12, 1)}}
+    del z, x, xs, o
     torch.cuda.empty_cache()
     return r
 

@@ -672,6 +672,18 @@ xc_status xc_pfb_info(const xc_pfb *pfb, int32_t *n_frames, int64_t *device_byte
  */
 xc_status xc_pfb_run(xc_pfb *pfb, const void *z, const float *taps, const void *weights, void *x, void *stream);
 
+/*
+ * The same filter bank writing x complex64 [N][S][T][P] (channel, station,
+ * frame, polarisation: each station's frames contiguous per channel), the
+ * layout xc_correlate_station_major takes, in one kernel: no intermediate
+ * and no corner turn (the FX correlator's corner turn, Section 7, then
+ * happens in the correlator's copies into LDS).  N = 256 only (other N:
+ * XC_ERR_UNSUPPORTED); x must be 16-byte aligned.  Otherwise as xc_pfb_run,
+ * and bit-identical to its output up to the layout.
+ */
+xc_status xc_pfb_run_station_major(xc_pfb *pfb, const void *z, const float *taps, const void *weights, void *x,
+                                   void *stream);
+
 /* Frees a filter bank (its enqueued work must be complete). */
 void xc_pfb_destroy(xc_pfb *pfb);
 

@@ -318,29 +318,37 @@ class Pfb:
         _lib.check(lib().xc_pfb_info(h, ctypes.byref(t), ctypes.byref(b)))
         self.n_frames, self.device_bytes = t.value, b.value
 
-    def out_shape(self):
+    def out_shape(self, layout: int = XC_LAYOUT_TIME_MAJOR):
+        if layout == XC_LAYOUT_STATION_MAJOR:
+            return (self.N, self.S, self.n_frames, 2)
         return (self.N, self.n_frames, self.S, 2)
 
     def run(self, z: torch.Tensor, taps: torch.Tensor, weights: torch.Tensor | None = None,
-            out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+            out: torch.Tensor | None = None, stream=None, layout: int = XC_LAYOUT_TIME_MAJOR) -> torch.Tensor:
+        """layout = XC_LAYOUT_STATION_MAJOR writes x[N][S][T][2] in one kernel
+        (256 channels), for ``correlate(..., layout=XC_LAYOUT_STATION_MAJOR)``."""
         if z.dtype != torch.complex64 or tuple(z.shape) != (self.S, 2, self.n_in):
             raise ValueError(f"z must be complex64 of shape {(self.S, 2, self.n_in)}")
         if taps.dtype != torch.float32 or taps.numel() != self.M * self.N:
             raise ValueError(f"taps must be float32 with {self.M * self.N} values")
         if weights is not None and (weights.dtype != torch.complex64 or tuple(weights.shape) != (self.S, 2, self.N)):
             raise ValueError(f"weights must be complex64 of shape {(self.S, 2, self.N)}")
+        if layout not in (XC_LAYOUT_TIME_MAJOR, XC_LAYOUT_STATION_MAJOR):
+            raise ValueError(f"unknown layout {layout}")
+        shape = self.out_shape(layout)
         if out is None:
-            out = torch.empty(self.out_shape(), dtype=torch.complex64, device=z.device)
-        if out.dtype != torch.complex64 or tuple(out.shape) != self.out_shape():
-            raise ValueError(f"out must be complex64 of shape {self.out_shape()}")
+            out = torch.empty(shape, dtype=torch.complex64, device=z.device)
+        if out.dtype != torch.complex64 or tuple(out.shape) != shape:
+            raise ValueError(f"out must be complex64 of shape {shape}")
         tensors = [z, taps, out] + ([weights] if weights is not None else [])
         _require_device(*tensors)
         for t in tensors:
             if not t.is_contiguous():
                 raise ValueError("tensors must be contiguous")
-        _lib.check(lib().xc_pfb_run(self._h, ctypes.c_void_p(z.data_ptr()), ctypes.c_void_p(taps.data_ptr()),
-                                    ctypes.c_void_p(weights.data_ptr()) if weights is not None else None,
-                                    ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+        fn = lib().xc_pfb_run_station_major if layout == XC_LAYOUT_STATION_MAJOR else lib().xc_pfb_run
+        _lib.check(fn(self._h, ctypes.c_void_p(z.data_ptr()), ctypes.c_void_p(taps.data_ptr()),
+                      ctypes.c_void_p(weights.data_ptr()) if weights is not None else None,
+                      ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
         return out
 
     def close(self):

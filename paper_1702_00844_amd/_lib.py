@@ -116,6 +116,7 @@ SIGNATURES = {
     "xc_pfb_create": (c_i32, [c_i32, c_i32, c_i32, c_i32, c_i64, ctypes.POINTER(c_vp)]),
     "xc_pfb_info": (c_i32, [c_vp, ctypes.POINTER(c_i32), ctypes.POINTER(c_i64)]),
     "xc_pfb_run": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
+    "xc_pfb_run_station_major": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
     "xc_pfb_destroy": (None, [c_vp]),
     "xc_measure_peak": (c_i32, [c_i32, ctypes.POINTER(c_f64)]),
     "xc_status_string": (c_char_p, [c_i32]),

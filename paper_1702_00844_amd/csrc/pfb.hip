@@ -274,6 +274,113 @@ __global__ __launch_bounds__(THREADS) void filter_fft256(const float2 *__restric
     }
 }
 
+// Station-major output for 256 channels: one workgroup per (station, block of
+// 16 frames).  Its two halves filter and transform the station's two
+// polarisation streams exactly as filter_fft256 does; the spectra are then
+// turned in LDS into rows of channel k holding the block's frames and both
+// polarisations, so that each channel leaves as one 256-byte run of
+// x[k][s][t][p], the layout the correlator takes as station-major input:
+// no intermediate, no corner turn.
+__global__ __launch_bounds__(2 * THREADS) void filter_fft256_sm(const float2 *__restrict__ z,
+                                                              const float *__restrict__ taps,
+                                                              const float2 *__restrict__ weights,
+                                                              const float2 *__restrict__ twiddle,
+                                                              float2 *__restrict__ x, int S, int M, int n_in, int T,
+                                                              int nfb, int nwork) {
+    constexpr int N = 256, FB = 16, PAD = 17, FROW = 16 * PAD;
+    constexpr int OROW = 2 * FB + 1;    // one channel: FB frames x 2 pols, padded by one against bank conflicts
+    static_assert(N * OROW <= 2 * FB * FROW, "the channel rows fit the two filter buffers");
+    __shared__ __attribute__((aligned(16))) float2 buf[2 * FB * FROW];
+    __shared__ float2 tw[N / 2];
+    const int tid = threadIdx.x;
+    const int p = tid >> 8;             // polarisation of this half
+    const int n = tid & (N - 1);        // branch
+    // consecutive frame blocks of a station on one XCD (their inputs overlap by M - 1 frames)
+    const int w = xcd_remap(blockIdx.x, nwork);
+    if (w < 0) return;
+    const int s = w / nfb;
+    const int f0 = (w - s * nfb) * FB;
+    const int nf = T - f0 < FB ? T - f0 : FB;
+    const int stream = 2 * s + p;
+    for (int i = tid; i < N / 2; i += 2 * THREADS) tw[i] = twiddle[i];
+    float2 *pb = buf + p * (FB * FROW);
+
+    const float2 *zs = z + (size_t)stream * n_in;
+    constexpr int NZ = FB + MAX_TAPS - 1;
+    const int last = T + M - 2;
+    float h[MAX_TAPS];
+    float2 zin[NZ];
+#pragma unroll
+    for (int m = 0; m < MAX_TAPS; ++m) {
+        const float v = taps[(m < M ? m : M - 1) * N + n];
+        h[m] = m < M ? v : 0.f;
+    }
+#pragma unroll
+    for (int i = 0; i < NZ; ++i) zin[i] = zs[(size_t)(f0 + i < last ? f0 + i : last) * N + n];
+#pragma unroll
+    for (int f = 0; f < FB; ++f) {
+        float ur = 0.f, ui = 0.f;
+#pragma unroll
+        for (int m = 0; m < MAX_TAPS; ++m) {
+            ur += h[m] * zin[f + m].x;
+            ui += h[m] * zin[f + m].y;
+        }
+        if (f < nf) pb[f * FROW + n + (n >> 4)] = make_float2(ur, ui);
+    }
+    __syncthreads();
+
+    const int f = n >> 4, q = n & 15;
+    float2 a[16];
+    if (f < nf) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) a[i] = pb[f * FROW + PAD * i + q];        // u[16 i + q]
+        dft16(a);
+#pragma unroll
+        for (int k1 = 0; k1 < 16; ++k1) {
+            const int j = q * k1;                                              // W256^j, j <= 225
+            const float2 t = j < N / 2 ? tw[j] : make_float2(-tw[j - N / 2].x, -tw[j - N / 2].y);
+            pb[f * FROW + PAD * k1 + q] = cmul(a[k1], t);
+        }
+    }
+    __syncthreads();
+    if (f < nf) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) a[i] = pb[f * FROW + PAD * q + i];        // pass-1 output n2 = i, k1 = q
+        dft16(a);
+    }
+    __syncthreads();    // both halves are done with their buffers: the channel rows take their place
+    if (f < nf) {
+        const float2 *ws = weights ? weights + (size_t)stream * N : nullptr;
+#pragma unroll
+        for (int k2 = 0; k2 < 16; ++k2) {
+            const int k = q + 16 * k2;
+            buf[k * OROW + 2 * f + p] = ws ? cmul(a[k2], ws[k]) : a[k2];
+        }
+    }
+    __syncthreads();
+    // channel k, frame r: both polarisations, 16 bytes; a wave writes four channels' runs
+    float2 *xs = x + ((size_t)s * T + f0) * 2;
+    const size_t kstride = (size_t)S * T * 2;
+    for (int e = tid; e < N * FB; e += 2 * THREADS) {
+        const int k = e >> 4, r = e & 15;
+        if (r < nf) {
+            const float2 v0 = buf[k * OROW + 2 * r], v1 = buf[k * OROW + 2 * r + 1];
+            *reinterpret_cast<float4 *>(xs + k * kstride + 2 * r) = make_float4(v0.x, v0.y, v1.x, v1.y);
+        }
+    }
+}
+
+hipError_t launch_filter_fft256_sm(const void *z, const float *taps, const void *weights, const float2 *twiddle,
+                                   void *x, int S, int M, int n_in, int T, hipStream_t stream) {
+    const int nfb = (T + 15) / 16;
+    const int64_t nwork = (int64_t)nfb * S;
+    if (nwork > ((int64_t)1 << 31) - kNumXcd) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(filter_fft256_sm, dim3(xcd_grid((int)nwork)), dim3(2 * THREADS), 0, stream,
+                       static_cast<const float2 *>(z), taps, static_cast<const float2 *>(weights), twiddle,
+                       static_cast<float2 *>(x), S, M, n_in, T, nfb, (int)nwork);
+    return hipGetLastError();
+}
+
 template <int N>
 hipError_t launch_filter_fft(const void *z, const float *taps, const void *weights, const float2 *twiddle, void *y,
                              int streams, int M, int n_in, int T, hipStream_t stream) {
@@ -382,6 +489,21 @@ xc_status xc_pfb_run(xc_pfb *p, const void *z, const float *taps, const void *we
     e = launch_transpose_tiles(p->inter, x, 8, streams, p->N, (int64_t)p->T * p->N, (int64_t)p->T * streams,
                                p->N, streams, p->T, s);
     if (e != hipSuccess) return hip_error(e, "corner-turn launch");
+    return XC_OK;
+}
+
+xc_status xc_pfb_run_station_major(xc_pfb *p, const void *z, const float *taps, const void *weights, void *x,
+                                   void *stream) {
+    if (!p) return set_error(XC_ERR_INVALID_ARG, "null filter bank");
+    if (!z || !taps || !x) return set_error(XC_ERR_INVALID_ARG, "null samples, taps or output pointer");
+    if (((uintptr_t)z & 7u) || ((uintptr_t)x & 15u) || ((uintptr_t)weights & 7u) || ((uintptr_t)taps & 3u))
+        return set_error(XC_ERR_INVALID_ARG,
+                         "misaligned pointer (samples and weights: 8 bytes, output: 16 bytes, taps: 4 bytes)");
+    if (x == z) return set_error(XC_ERR_INVALID_ARG, "the filter bank is out of place (x == z)");
+    if (p->N != 256) return set_error(XC_ERR_UNSUPPORTED, "station-major output is built for 256 channels");
+    hipError_t e = pfb::launch_filter_fft256_sm(z, taps, weights, p->twiddle, x, p->S, p->M, p->n_in, p->T,
+                                                static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_error(e, "filter-bank launch");
     return XC_OK;
 }
 

@@ -48,6 +48,55 @@ def test_pfb_matches_oracle(N, M, S, extra, T, weighted):
     fb.close()
 
 
+@pytest.mark.parametrize("M", [1, 4, 16])
+@pytest.mark.parametrize("S,extra,T", [(1, 0, 1), (3, 77, 21), (2, 255, 40), (5, 3, 16)],
+                         ids=["S1_T1", "S3_T21", "S2_T40", "S5_T16"])
+@pytest.mark.parametrize("weighted", [False, True], ids=["plain", "weighted"])
+def test_pfb_station_major_matches_oracle(M, S, extra, T, weighted):
+    """The one-kernel station-major output x[N][S][T][2]: within the bar of the
+    fp64 oracle, and bit-identical to the time-major output turned around."""
+    N = 256
+    n_in = (T + M - 1) * N + extra
+    z = inputs.station_streams(S, n_in, seed=40 + M + S, device=DEV)
+    taps = torch.from_numpy(inputs.pfb_taps(N, M)).to(DEV)
+    w = None
+    if weighted:
+        g = torch.Generator(device="cpu").manual_seed(19)
+        w = torch.polar(torch.rand((S, 2, N), generator=g) + 0.5,
+                        torch.rand((S, 2, N), generator=g) * 6.283).to(torch.complex64).to(DEV)
+    fb = xe.Pfb(S, N, M, n_in)
+    xs = fb.run(z, taps, w, layout=xe.XC_LAYOUT_STATION_MAJOR)
+    xt = fb.run(z, taps, w)
+    torch.cuda.synchronize()
+    assert tuple(xs.shape) == (N, S, T, 2)
+    assert torch.equal(xs.permute(0, 2, 1, 3), xt)
+    ref = opfb.pfb_channelize(z.cpu().numpy(), taps.cpu().numpy(), N, None if w is None else w.cpu().numpy())
+    got = xs.permute(0, 2, 1, 3).cpu().numpy().astype(np.complex128)
+    assert _rel(got, ref) <= TOL, _rel(got, ref)
+    fb.close()
+
+
+def test_pfb_station_major_feeds_the_correlator():
+    """Station streams -> one-kernel station-major filter bank -> correlator on
+    station-major input, against the two oracles composed."""
+    N, M, S, T = 256, 4, 5, 33
+    n_in = (T + M - 1) * N
+    z = inputs.station_streams(S, n_in, seed=12, device=DEV)
+    taps = torch.from_numpy(inputs.pfb_taps(N, M)).to(DEV)
+    fb = xe.Pfb(S, N, M, n_in)
+    v = xe.correlate(fb.run(z, taps, layout=xe.XC_LAYOUT_STATION_MAJOR), layout=xe.XC_LAYOUT_STATION_MAJOR)
+    torch.cuda.synchronize()
+    ref = oracle.correlate_f64(opfb.pfb_channelize(z.cpu().numpy(), taps.cpu().numpy(), N))
+    assert rel_err(gpu_vis_numpy(v), ref) <= 2 * TOL
+    fb.close()
+    fb = xe.Pfb(2, 512, 2, 2 * 512)
+    with pytest.raises(xe.XengineError) as e:        # built for 256 channels
+        fb.run(inputs.station_streams(2, 2 * 512, device=DEV), torch.from_numpy(inputs.pfb_taps(512, 2)).to(DEV),
+               layout=xe.XC_LAYOUT_STATION_MAJOR)
+    assert e.value.status_name == "XC_ERR_UNSUPPORTED"
+    fb.close()
+
+
 def test_pfb_tone_closed_form():
     """Taps with equal branch sums c: a tone at bin k0 lands in channel k0 with
     amplitude c N, every other channel at rounding level."""
