@@ -555,7 +555,7 @@ def compare_paths(xe, inputs, torch, dev, stream, steps=10):
              ("f32_mfma", "cf32", {"kernel": xe.XC_KERNEL_MFMA}, "fp32_mfma_TF", "f32_mfma16",
               "p256_cf32_mfma_mfma16_b64", "mfma16"),
              ("f32_mfma_4products", "cf32", {"kernel": xe.XC_KERNEL_MFMA, "product": xe.XC_PRODUCT_FOUR},
-              "fp32_mfma_TF", "f32_mfma16", None, "mfma16"),
+              "fp32_mfma_TF", "f32_mfma16", "p256_cf32_mfma4_mfma16_b64", "mfma16"),
              ("f32_valu", "cf32", {"kernel": xe.XC_KERNEL_VALU}, "fp32_valu_TF", "f32_fma", "p256_cf32_valu_valu_b32",
               "valu")]
     probes = {}
