@@ -182,9 +182,14 @@ int64_t xc_correlate_split_bytes(int32_t n_stations, int32_t n_pol, int32_t n_ch
 
 /*
  * Kernel configuration.  Zero fields mean "default for this shape".
- *   kernel        xc_kernel
+ *   kernel        xc_kernel.  AUTO: for complex float32 on at most 16 stations
+ *                 (and no other field set) VALU with block 16, otherwise MFMA.
  *   block         stations per block of the triangle's block grid (Section 4.5
- *                 splits large triangles into blocks).  VALU: 32.  MFMA: 32 or 64
+ *                 splits large triangles into blocks).  VALU: 32 (default), or
+ *                 16 for arrays of at most 16 stations: one workgroup per
+ *                 channel correlates all its baselines (the chunk of 128 time
+ *                 steps and up to 32 time groups are fixed; time_chunk 0 or
+ *                 128, time_split 0 or 1, no register tiles).  MFMA: 32 or 64
  *                 (AUTO: 32 for complex-float32 on at most 48 stations, else 64).
  *   time_chunk    time steps staged in LDS per pipeline stage (fixed by the
  *                 other fields except for VALU: 16 or 32, default 32;
@@ -271,7 +276,8 @@ xc_status xc_correlate_split_static(const xc_config *cfg, const void *samples, x
  * xc_correlate_config on the time-major block.  Kernels: complex float32 on
  * the 64-station matrix-core kernel (kernel AUTO or XC_KERNEL_MFMA, block 0
  * or 64; cfg may set its time split and product form) or on the vector-ALU
- * kernel (XC_KERNEL_VALU); int8 and 16-bit samples on the 64-station
+ * kernels (XC_KERNEL_VALU; AUTO on at most 16 stations takes the one-channel
+ * kernel, block 16, as xc_correlate does); int8 and 16-bit samples on the 64-station
  * direct-to-LDS matrix-core kernel, in 4-byte copies (one station's word per
  * lane, gathered from 64 station series per copy).  Errors as for
  * xc_correlate_config, and XC_ERR_UNSUPPORTED for the 32-station or
@@ -390,7 +396,8 @@ xc_status xc_autotune(const void *samples, xc_in_type in_type, int32_t n_station
 int64_t xc_tune_candidates(xc_in_type in_type, xc_config *out, int64_t capacity);
 
 /* The tuning bucket of a shape (host only): key = {in_type, out_type,
- * ceil(S / 32), 1 if S fills whole copy granules of the direct-to-LDS kernel
+ * ceil(S / 32) (0 for at most 16 stations, the one-channel kernel's
+ * range), 1 if S fills whole copy granules of the direct-to-LDS kernel
  * (4 int8 or 2 16-bit stations), ceil(log2 T), min(ceil(log2(C x
  * 64-station block pairs)), 12)}.  Shapes with equal keys share a tuned
  * configuration. */

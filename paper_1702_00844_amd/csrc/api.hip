@@ -97,8 +97,10 @@ TuneKey tune_bucket(int in_type, int out_type, int S, int C, int T) {
     const int gran = in_type == XC_IN_CI8 ? 4 : (in_type == XC_IN_CF32 ? 1 : 2);
     const int64_t nb = (S + 63) / 64;
     const int64_t units = (int64_t)C * (nb * (nb + 1) / 2);
-    return TuneKey{in_type, out_type, (S + 31) / 32, S % gran == 0 ? 1 : 0, ceil_log2(T),
-                   std::min(ceil_log2(units), 12)};
+    // station classes: 32-station blocks, and arrays of at most 16 stations
+    // apart (class 0), which have a kernel of their own
+    const int sclass = S <= 16 ? 0 : (S + 31) / 32;
+    return TuneKey{in_type, out_type, sclass, S % gran == 0 ? 1 : 0, ceil_log2(T), std::min(ceil_log2(units), 12)};
 }
 
 void tune_put(const TuneKey &k, const xc_config &cfg) {
@@ -149,6 +151,13 @@ xc_status resolve(const xc_config *cfg_in, xc_in_type in_type, xc_out_type out_t
         if (tune_get(tune_bucket((int)in_type, (int)out_type, S, C, T), &tuned)) cfg = tuned;
     }
     int kernel = cfg.kernel;
+    // complex float32 on at most 16 stations: the one-channel kernel (8
+    // stations x 16 channels x 256 samples: 6.2 us per launch against 21-25 us
+    // for the block-pair kernels, whose chunk loop waits on its loads; 16
+    // stations x 256 channels x 768 samples: 27 against 49-69 us)
+    const bool small_auto = kernel == XC_KERNEL_AUTO && in_type == XC_IN_CF32 && S <= 16 && !cfg.block &&
+                            !cfg.time_chunk && !cfg.time_split && !cfg.tile_w && !cfg.tile_h;
+    if (small_auto) kernel = XC_KERNEL_VALU;
     if (kernel == XC_KERNEL_AUTO) kernel = XC_KERNEL_MFMA;
     if (kernel != XC_KERNEL_VALU && kernel != XC_KERNEL_MFMA)
         return set_error(XC_ERR_INVALID_ARG, "invalid kernel %d", cfg.kernel);
@@ -163,23 +172,37 @@ xc_status resolve(const xc_config *cfg_in, xc_in_type in_type, xc_out_type out_t
     if (kernel == XC_KERNEL_VALU) {
         if (in_type != XC_IN_CF32)
             return set_error(XC_ERR_UNSUPPORTED, "the vector-ALU kernel takes complex-float32 samples only");
-        p.block = cfg.block ? cfg.block : 32;
-        p.time_chunk = cfg.time_chunk ? cfg.time_chunk : 32;
-        p.time_split = cfg.time_split ? cfg.time_split : 4;
+        p.block = cfg.block ? cfg.block : (small_auto ? 16 : 32);
         p.staging = cfg.staging ? cfg.staging : XC_STAGING_REGISTERS;
-        // default 4 x 2 tiles, chunks of 32 time steps, four time groups: the
-        // fastest measured configuration on 64 stations (74.7 TFLOP/s against
-        // 73.1 for 2 x 2 tiles and 53.0 for 4 x 4) and within 1 % of the
-        // fastest on 256 stations (85.1 against 85.4)
-        p.tile_w = cfg.tile_w ? cfg.tile_w : 4;
-        p.tile_h = cfg.tile_h ? cfg.tile_h : 2;
-        if (p.block != 32) return set_error(XC_ERR_INVALID_ARG, "VALU block must be 32 (got %d)", p.block);
-        if (!valu_available(p.tile_w, p.tile_h, p.time_chunk, p.time_split))
-            return set_error(XC_ERR_INVALID_ARG,
-                             "VALU (tile %d x %d, time_chunk %d, time_split %d) not available", p.tile_w, p.tile_h,
-                             p.time_chunk, p.time_split);
         if (p.staging != XC_STAGING_REGISTERS)
-            return set_error(XC_ERR_INVALID_ARG, "the vector-ALU kernel stages through registers only");
+            return set_error(XC_ERR_INVALID_ARG, "the vector-ALU kernels stage through registers only");
+        if (p.block == 16) {
+            // one workgroup per channel, all baselines; its chunk (128 time
+            // steps) and time groups (up to 32) are fixed
+            if (S > 16) return set_error(XC_ERR_INVALID_ARG, "VALU block 16 takes at most 16 stations (got %d)", S);
+            if (cfg.tile_w || cfg.tile_h)
+                return set_error(XC_ERR_INVALID_ARG, "VALU block 16 has no register tiles (tile_w, tile_h must be 0)");
+            if (cfg.time_chunk && cfg.time_chunk != 128)
+                return set_error(XC_ERR_INVALID_ARG, "VALU block 16 stages chunks of 128 time steps");
+            if (cfg.time_split > 1)
+                return set_error(XC_ERR_INVALID_ARG, "VALU block 16 chooses its own time groups (time_split 0 or 1)");
+            p.time_chunk = 128;
+            p.time_split = 1;
+        } else {
+            p.time_chunk = cfg.time_chunk ? cfg.time_chunk : 32;
+            p.time_split = cfg.time_split ? cfg.time_split : 4;
+            // default 4 x 2 tiles, chunks of 32 time steps, four time groups: the
+            // fastest measured configuration on 64 stations (74.7 TFLOP/s against
+            // 73.1 for 2 x 2 tiles and 53.0 for 4 x 4) and within 1 % of the
+            // fastest on 256 stations (85.1 against 85.4)
+            p.tile_w = cfg.tile_w ? cfg.tile_w : 4;
+            p.tile_h = cfg.tile_h ? cfg.tile_h : 2;
+            if (p.block != 32) return set_error(XC_ERR_INVALID_ARG, "VALU block must be 32 or 16 (got %d)", p.block);
+            if (!valu_available(p.tile_w, p.tile_h, p.time_chunk, p.time_split))
+                return set_error(XC_ERR_INVALID_ARG,
+                                 "VALU (tile %d x %d, time_chunk %d, time_split %d) not available", p.tile_w,
+                                 p.tile_h, p.time_chunk, p.time_split);
+        }
     } else {
         // complex-float32 on few stations: 64-station blocks would leave most
         // of their tiles empty (measured: 8, 24 and 40 stations run 15-20 %
@@ -509,9 +532,16 @@ xc_status xc_correlate_station_major(const xc_config *cfg, const void *samples, 
     // the kernels whose sample loads take either layout: the 64-station
     // matrix-core kernels that copy straight into LDS (complex float32 16 x 16
     // tiles; int8 and 16-bit samples in 4-byte copies) and the vector-ALU
-    // kernel (complex float32)
+    // kernels (complex float32, including the one-channel kernel)
     xc_config c = cfg ? *cfg : xc_config{};
-    if (c.kernel == XC_KERNEL_AUTO) c.kernel = XC_KERNEL_MFMA;
+    if (c.kernel == XC_KERNEL_AUTO) {
+        // as for time-major input: the one-channel kernel for complex float32
+        // on at most 16 stations, otherwise the 64-station matrix-core kernel
+        const bool small = in_type == XC_IN_CF32 && n_stations <= 16 && !c.block && !c.time_chunk &&
+                           !c.time_split && !c.tile_w && !c.tile_h;
+        c.kernel = small ? XC_KERNEL_VALU : XC_KERNEL_MFMA;
+        if (small) c.block = 16;
+    }
     if (c.kernel == XC_KERNEL_MFMA && c.block != 0 && c.block != 64)
         return set_error(XC_ERR_UNSUPPORTED, "station-major input: the matrix-core kernel on 64-station blocks only");
     if (c.kernel == XC_KERNEL_MFMA) c.block = 64;

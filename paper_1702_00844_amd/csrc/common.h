@@ -129,7 +129,7 @@ inline int xcd_grid(int nwork) {
 // Resolved configuration of one launch.
 struct Plan {
     int kernel;      // XC_KERNEL_VALU or XC_KERNEL_MFMA
-    int block;       // stations per block
+    int block;       // stations per block (vector ALU: 32, or 16 for the one-channel small-array kernel)
     int time_chunk;  // time steps per LDS stage
     int time_split;  // waves sharing one output block over time
     int staging;     // XC_STAGING_REGISTERS or XC_STAGING_LDS
@@ -146,6 +146,9 @@ bool valu_available(int tile_w, int tile_h, int time_chunk, int time_split);
 
 // Launchers (return hipSuccess or the launch error).
 hipError_t launch_valu(const Plan &plan, const Job &job, hipStream_t stream);
+// Arrays of at most 16 stations (complex float32): one workgroup per channel.
+hipError_t launch_small(const Job &job, hipStream_t stream);
+hipError_t launch_small_batch(const Job *jobs, const Unit *units, const int *bounds, int grid, hipStream_t stream);
 hipError_t launch_mfma(const Plan &plan, xc_in_type in_type, xc_out_type out_type,
                        const Job &job, hipStream_t stream);
 

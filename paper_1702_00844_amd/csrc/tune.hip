@@ -41,6 +41,9 @@ std::vector<xc_config> candidates(xc_in_type in_type) {
         v.push_back(xc_config{XC_KERNEL_MFMA, 64, 0, 1, XC_STAGING_REGISTERS, 0, 0, 0});
         return v;
     }
+    // arrays of at most 16 stations: one workgroup per channel (skipped for
+    // larger arrays, where it does not resolve)
+    v.push_back(xc_config{XC_KERNEL_VALU, 16, 0, 0, 0, 0, 0, 0});
     // one or two time groups, four or three real products
     for (int ts = 1; ts <= 2; ++ts)
         for (int pr = XC_PRODUCT_FOUR; pr <= XC_PRODUCT_THREE; ++pr)

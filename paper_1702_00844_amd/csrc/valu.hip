@@ -478,11 +478,13 @@ struct BatchLaunch {
 }  // namespace
 
 hipError_t launch_valu(const Plan &plan, const Job &job, hipStream_t stream) {
+    if (plan.block == 16) return launch_small(job, stream);
     return valu::dispatch(plan, FlatLaunch{job, stream});
 }
 
 hipError_t launch_valu_batch(const Plan &plan, const Job *jobs, const Unit *units, const int *bounds, int grid,
                              hipStream_t stream) {
+    if (plan.block == 16) return launch_small_batch(jobs, units, bounds, grid, stream);
     return valu::dispatch(plan, BatchLaunch{jobs, units, bounds, grid, stream});
 }
 

@@ -333,21 +333,44 @@ def test_tune_candidates_pruned_by_table1():
     (one of each mirror pair) whose Table 1 register count, plus staging and
     address registers, fits 256: 8 x 4, 4 x 8 and 8 x 8 are pruned."""
     cands = xe.tune_candidates(_lib.XC_IN_CF32)
-    tiles = {(c["tile_w"], c["tile_h"]) for c in cands if c["kernel"] == _lib.XC_KERNEL_VALU}
+    tiles = {(c["tile_w"], c["tile_h"]) for c in cands if c["kernel"] == _lib.XC_KERNEL_VALU and c["block"] == 32}
     assert tiles == {(4, 4), (8, 2), (4, 2), (2, 2)}
     for w, h in [(8, 4), (8, 8)]:
         assert xe.tile_cost(w, h)[2] > 256 - 24
-    for c in cands:        # every candidate resolves for a shape
-        r = xe.resolve_config((_lib.XC_IN_CF32, 4, 64, 40, 2), config=c)
+    # and the one-channel kernel for arrays of at most 16 stations
+    assert sum(1 for c in cands if c["kernel"] == _lib.XC_KERNEL_VALU and c["block"] == 16) == 1
+    for c in cands:        # every candidate resolves for a small array
+        r = xe.resolve_config((_lib.XC_IN_CF32, 4, 64, 12, 2), config=c)
         assert r["kernel"] == c["kernel"]
     i8 = xe.tune_candidates(_lib.XC_IN_CI8)
     assert all(c["kernel"] == _lib.XC_KERNEL_MFMA for c in i8) and len(i8) == 3
+
+
+def test_small_array_kernel_resolution():
+    # complex float32 on at most 16 stations: the one-channel kernel (vector ALU, block 16) by default
+    r = xe.resolve_config((_lib.XC_IN_CF32, 16, 256, 8, 2))
+    assert (r["kernel"], r["block"], r["time_chunk"], r["time_split"]) == (_lib.XC_KERNEL_VALU, 16, 128, 1)
+    assert xe.resolve_config((_lib.XC_IN_CF32, 16, 256, 16, 2))["block"] == 16
+    assert xe.resolve_config((_lib.XC_IN_CF32, 16, 256, 17, 2))["kernel"] == _lib.XC_KERNEL_MFMA
+    assert xe.resolve_config((_lib.XC_IN_CI8, 16, 256, 8, 2), _lib.XC_OUT_CI32)["kernel"] == _lib.XC_KERNEL_MFMA
+    # an explicit kernel choice keeps its own defaults
+    assert xe.resolve_config((_lib.XC_IN_CF32, 16, 256, 8, 2), config={"kernel": _lib.XC_KERNEL_VALU})["block"] == 32
+    assert xe.resolve_config((_lib.XC_IN_CF32, 16, 256, 8, 2), config={"kernel": _lib.XC_KERNEL_MFMA})["block"] == 32
+    for bad in [dict(kernel=_lib.XC_KERNEL_VALU, block=16, tile_w=2, tile_h=2),
+                dict(kernel=_lib.XC_KERNEL_VALU, block=16, time_chunk=32),
+                dict(kernel=_lib.XC_KERNEL_VALU, block=16, time_split=2)]:
+        with pytest.raises(xe.XengineError):
+            xe.resolve_config((_lib.XC_IN_CF32, 16, 256, 8, 2), config=bad)
+    with pytest.raises(xe.XengineError):      # at most 16 stations
+        xe.resolve_config((_lib.XC_IN_CF32, 16, 256, 20, 2), config={"kernel": _lib.XC_KERNEL_VALU, "block": 16})
 
 
 def test_tune_buckets():
     b = lambda S, C, T, it=_lib.XC_IN_CI8: xe.tune_bucket(it, _lib.XC_OUT_CI32 if it == 1 else 0, S, C, T)
     assert b(100, 500, 768) == b(120, 600, 700)          # same 32-station blocks, T and unit classes
     assert b(100, 500, 768) != b(130, 500, 768)          # another station-block count
+    f = lambda S: b(S, 64, 768, _lib.XC_IN_CF32)
+    assert f(8) == f(16) != f(17) == f(32)                 # at most 16 stations: the one-channel kernel's bucket
     assert b(100, 500, 768) != b(101, 500, 768)          # 101 stations are not whole int8 copy granules
     assert b(100, 500, 768) != b(100, 500, 2000)         # another integration-length class
     assert b(100, 8, 768) != b(100, 500, 768)            # few units against a full device

@@ -81,6 +81,47 @@ def test_batch_matches_oracle(kind, config, shapes, use_graph):
     plan.close()
 
 
+def test_batch_mixes_the_small_array_kernel():
+    """Complex float32 with the default configuration: sub-arrays of at most
+    16 stations take the one-channel kernel, the others the matrix cores, in
+    one plan (one launch per configuration), replayed from a graph."""
+    shapes = [(8, 5, 100), (16, 3, 300), (40, 2, 64), (1, 7, 129), (70, 1, 33)]
+    xs = _make("cf32", shapes, seed=70)
+    outs = [torch.full(xe.vis_shape(s[1], s[0], xe.XC_OUT_CF32), 7, dtype=torch.complex64, device=DEV)
+            for s in shapes]
+    plan = xe.BatchPlan(xs, outs, use_graph=True)
+    for rep in range(2):
+        for o in outs:
+            o.fill_(3)
+        torch.cuda.synchronize()
+        plan.run()
+        torch.cuda.synchronize()
+        _check("cf32", xs, outs)
+    plan.close()
+
+
+def test_stream_of_a_small_array():
+    """A 12-station complex-float32 stream (folded by the one-channel kernel
+    through the ring's time-blocked addressing) equals the oracle."""
+    S, C, bt, bpi, k = 12, 3, 40, 4, 2
+    srv = xe.Server()
+    sid = srv.open(xe.Server.desc(S, C, bt, bpi, blocks_per_fold=k, ring_blocks=5, in_type=xe.XC_IN_CF32,
+                                  acc_type=xe.XC_OUT_CF32, block_period_s=0.001, staggered=True))
+    blocks = [inputs.cn_gaussian(C, bt, S, seed=300 + b, device=DEV) for b in range(2 * bpi)]
+    for blk in blocks:
+        ptr = _acquire(srv, sid)
+        _fill_slot(ptr, blk, "cf32", C, bt, S)
+        torch.cuda.synchronize()
+        srv.commit(sid, time.monotonic_ns())
+    for n in range(2):
+        vptr = srv.wait_integration(sid, n, stream=torch.cuda.current_stream())
+        got = xe.device_tensor(vptr, xe.vis_shape(C, S, xe.XC_OUT_CF32), torch.complex64).clone()
+        torch.cuda.synchronize()
+        ref = oracle_vis(torch.cat(blocks[n * bpi:(n + 1) * bpi], dim=1))
+        assert rel_err(gpu_vis_numpy(got), ref) <= 1e-5, n
+    srv.close()
+
+
 def test_batch_accumulate():
     xs = _make("ci8", SHAPES, seed=90)
     base = [torch.randint(-1000, 1000, xe.vis_shape(s[1], s[0], xe.XC_OUT_CI32), dtype=torch.int32, device=DEV)

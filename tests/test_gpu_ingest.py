@@ -138,7 +138,10 @@ def test_station_major_kernel_matches_time_major(shape, config):
     C, S, T = shape
     x = _samples("cf32", C, T, S, seed=900 + S + T)
     cfg = dict(config or {})
-    if cfg.get("kernel") != xe.XC_KERNEL_VALU:
+    if not cfg:
+        # AUTO: the one-channel kernel on at most 16 stations, else the 64-station matrix-core kernel
+        cfg = {"kernel": xe.XC_KERNEL_VALU, "block": 16} if S <= 16 else {"kernel": xe.XC_KERNEL_MFMA, "block": 64}
+    elif cfg.get("kernel") != xe.XC_KERNEL_VALU:
         cfg = {"kernel": xe.XC_KERNEL_MFMA, "block": 64, **cfg}
     ref = xe.correlate(x, config=cfg)
     got = xe.correlate(_station_major(x), config=config, layout=SM)

@@ -60,6 +60,40 @@ def test_cf32_parity(shape, cfg):
     assert_hermitian_autos(got, S)
 
 
+# the one-channel kernel for arrays of at most 16 stations (the default for
+# complex float32 there): station counts 1..16, integrations across its
+# 128-step chunks (1, 2, 77, 128, 129, 300, 1000 steps), 1..17 channels
+SMALL = dict(kernel=xe.XC_KERNEL_VALU, block=16)
+SMALL_SHAPES = [(1, 1, 1), (1, 4, 300), (2, 3, 129), (5, 17, 128), (8, 16, 256), (13, 3, 77), (16, 5, 1000),
+                (16, 1, 2)]
+
+
+@pytest.mark.parametrize("shape", SMALL_SHAPES, ids=lambda s: "S%d_C%d_T%d" % s)
+@pytest.mark.parametrize("cfg", [None, SMALL], ids=["auto", "explicit"])
+def test_small_array_kernel(shape, cfg):
+    """Within 1e-5 of the oracle, Hermitian autocorrelations, accumulation
+    adding exactly the same sums again; station-major input gives the same
+    bits; the integration split within 1e-5."""
+    S, C, T = shape
+    if cfg is not None:     # (AUTO may also take a configuration tuned for the shape's bucket)
+        assert xe.resolve_config((xe.XC_IN_CF32, C, T, S, 2), config=cfg)["block"] == 16
+    x = _cf32(S, C, T, seed=7 * S + T)
+    v = xe.correlate(x, config=cfg)
+    v2 = v.clone()
+    xe.correlate(x, out=v2, accumulate=True, config=cfg)
+    vs = xe.correlate(x.permute(0, 2, 1, 3).contiguous(), config=cfg, layout=xe.XC_LAYOUT_STATION_MAJOR)
+    vt = xe.correlate(x, config=SMALL)
+    vp = xe.correlate(x, config=cfg, split=3)
+    torch.cuda.synchronize()
+    ref = oracle_vis(x)
+    got = gpu_vis_numpy(v)
+    assert rel_err(got, ref) <= FP32_TOL, rel_err(got, ref)
+    assert_hermitian_autos(got, S)
+    assert torch.equal(v2, v + v)
+    assert torch.equal(vs, vt)
+    assert rel_err(gpu_vis_numpy(vp), ref) <= FP32_TOL
+
+
 # int8 kernels: the default (staged straight into LDS when S % 4 == 0), the
 # register-staged one on 64-station blocks, and 32-station blocks; extra shapes
 # with S % 4 == 0 give the direct-to-LDS kernel diagonal and off-diagonal
