@@ -45,6 +45,15 @@ constexpr int BROW = RB * 8;        // bytes of one block's time step (1 KiB)
 // with one (two workgroups per CU)
 template <int TS>
 constexpr int stage() { return TS == 2 ? 65536 : 32768; }
+// a diagonal unit's triangle of baselines as an image of the output: at most
+// 2080 baselines x 4 polarisation products
+constexpr int IMG = 2080 * 4;
+// LDS of a workgroup: the two stages, and with two time groups also one
+// triangle image per group (2 KiB more than the stages)
+template <int TS>
+constexpr int lds_bytes() {
+    return TS == 2 && 2 * IMG * 8 > 2 * stage<TS>() ? 2 * IMG * 8 : 2 * stage<TS>();
+}
 // bytes per staged time step: block I only on the diagonal, I then J elsewhere
 template <bool DIAG>
 constexpr int pitch() { return DIAG ? BROW : 2 * BROW; }
@@ -136,14 +145,13 @@ __device__ __forceinline__ void store_tile(const Job &job, int c, const v4f &re,
 // Diagonal block pair, two time groups: the unit's triangle of baselines
 // (local j < nj, i <= j, at local index j (j + 1) / 2 + i, 32 bytes each,
 // at most 2080 x 32 = 66 560 bytes) is assembled in LDS as an image of the
-// output: time group 0 writes its sums, then time group 1 adds its own (so
-// each element is group 0's sum plus group 1's, as in the register
-// reduction), and the workgroup copies the image out in 16-byte granules,
-// a wave writing 1 KiB runs of consecutive baselines.  Autocorrelations are
-// written as the other stores do: XX, YY real, YX = conj(XY).
-template <bool ADD>
-__device__ __forceinline__ void image_tile(float2 *__restrict__ img, const v4f &re, const v4f &im, int trow,
-                                           int tcol, int nj, int lane) {
+// output, one image per time group, written by both groups at once; the
+// workgroup then copies out their sum (each element group 0's sum plus
+// group 1's, as in the register reduction) in 16-byte granules, a wave
+// writing 1 KiB runs of consecutive baselines.  Autocorrelations are written
+// as the other stores do: XX, YY real, YX = conj(XY).
+__device__ __forceinline__ void image_tile(float2 *__restrict__ img, const v4f &re, const v4f &im, int trow, int tcol,
+                                           int nj, int lane) {
     const int col = tcol * 16 + (lane & 15);
     const int jl = col >> 1;
     const int q = col & 1;
@@ -161,22 +169,8 @@ __device__ __forceinline__ void image_tile(float2 *__restrict__ img, const v4f &
             if (p == 1 && q == 0) continue;     // written as conj(XY) by the q = 1 lane
             if (p == q) vi = 0.f;
         }
-        const int e = (jb + il) * 4 + p * 2 + q;
-        if (ADD) {
-            const float2 o = img[e];
-            img[e] = make_float2(o.x + vr, o.y + vi);
-        } else {
-            img[e] = make_float2(vr, vi);
-        }
-        if (il == jl && p == 0 && q == 1) {
-            const int e2 = (jb + il) * 4 + 2;
-            if (ADD) {
-                const float2 o = img[e2];
-                img[e2] = make_float2(o.x + vr, o.y - vi);
-            } else {
-                img[e2] = make_float2(vr, -vi);
-            }
-        }
+        img[(jb + il) * 4 + p * 2 + q] = make_float2(vr, vi);
+        if (il == jl && p == 0 && q == 1) img[(jb + il) * 4 + 2] = make_float2(vr, -vi);
     }
 }
 
@@ -347,23 +341,17 @@ __device__ __forceinline__ void wave_unit(const Job &job, int c, int bi, int bj,
     __syncthreads();
 
     if constexpr (DIAG && TS == 2) {
-        static_assert(2080 * 32 <= 2 * STAGE, "the triangle image must fit the staging area");
-        float2 *img = reinterpret_cast<float2 *>(lds);
+        static_assert(2 * IMG * 8 <= lds_bytes<TS>(), "the two triangle images fit the workgroup's LDS");
+        float2 *img = reinterpret_cast<float2 *>(lds) + grp * IMG;
         const int nj = S - J0 < SB ? S - J0 : SB;
+        if (any) {
 #pragma unroll
-        for (int ph = 0; ph < 2; ++ph) {
-            if (grp == ph && any) {
-#pragma unroll
-                for (int s = 0; s < NT; ++s) {
-                    if (ph == 0)
-                        image_tile<false>(img, are[s], aim[s], SC::arow(SC::a_of(s)), SC::bcol(SC::b_of(s)), nj, lane);
-                    else
-                        image_tile<true>(img, are[s], aim[s], SC::arow(SC::a_of(s)), SC::bcol(SC::b_of(s)), nj, lane);
-                }
-            }
-            __syncthreads();
+            for (int s = 0; s < NT; ++s)
+                image_tile(img, are[s], aim[s], SC::arow(SC::a_of(s)), SC::bcol(SC::b_of(s)), nj, lane);
         }
+        __syncthreads();
         const float4 *img4 = reinterpret_cast<const float4 *>(lds);
+        const float4 *img4b = img4 + IMG / 2;      // group 1's image
         float4 *__restrict__ V4 = reinterpret_cast<float4 *>(static_cast<float2 *>(job.vis) +
                                                              (size_t)c * ((size_t)S * (S + 1) / 2) * 4);
         const int ng = nj * (nj + 1);     // 16-byte granules: two per baseline
@@ -390,6 +378,8 @@ __device__ __forceinline__ void wave_unit(const Job &job, int c, int bi, int bj,
                 const int g = g0 + n * 256 * TS;
                 if (g >= ng) break;
                 float4 v = img4[g];
+                const float4 u = img4b[g];
+                v = make_float4(v.x + u.x, v.y + u.y, v.z + u.z, v.w + u.w);
                 if (job.accumulate) v = make_float4(v.x + o[n].x, v.y + o[n].y, v.z + o[n].z, v.w + o[n].w);
                 *dst[n] = v;
             }
@@ -458,10 +448,11 @@ __device__ __forceinline__ void unit(const Job &job, int c, int bi, int bj, uint
     }
 }
 
-// LDS: two staging buffers (64 or 128 KiB), reused for the time-group reduction.
+// LDS: two staging buffers (64 or 128 KiB), reused for the time-group
+// reduction (two time groups: 130 KiB, for the groups' two triangle images).
 template <int TS, bool G3>
 __global__ __launch_bounds__(256 * TS, 2 / TS) void kernel(Job job, int nwork) {
-    __shared__ __attribute__((aligned(16))) uint8_t lds[2 * stage<TS>()];
+    __shared__ __attribute__((aligned(16))) uint8_t lds[lds_bytes<TS>()];
     const int w = xcd_remap(blockIdx.x, nwork);
     if (w < 0) return;
     int c, bi, bj;
@@ -473,7 +464,7 @@ template <int TS, bool G3>
 __global__ __launch_bounds__(256 * TS, 2 / TS) void kernel_batch(const Job *__restrict__ jobs,
                                                                  const Unit *__restrict__ units,
                                                                  const int *__restrict__ bounds) {
-    __shared__ __attribute__((aligned(16))) uint8_t lds[2 * stage<TS>()];
+    __shared__ __attribute__((aligned(16))) uint8_t lds[lds_bytes<TS>()];
     const int u = batch_unit(bounds, blockIdx.x);
     if (u < 0) return;
     const Unit un = units[u];
