@@ -913,17 +913,22 @@ def stream_all(xe, inputs, torch, args):
     if args.stream_ref_blocks > 0:
         out["stream_all_channels"] = stream_bench(xe, inputs, torch, 1, args.stream_fold, args.stream_ref_blocks,
                                                   staggered=False)
+    on_time = 0          # streams kept in real time with every block on time, in the runs above
+    if runs and any(r["block_misses"][0] == 0 for r in runs):
+        on_time = 1
     if args.stream_two_k > 0:
         two = stream_bench(xe, inputs, torch, 2, args.stream_two_k, args.stream_blocks, spread_ends=True,
                            ordered=True)
         two["all_blocks_on_time"] = two["streams_admitted"] == 2 and all(m == 0 for m in two["block_misses"])
         out["stream_two"] = two
+        if two["all_blocks_on_time"]:
+            on_time = 2
+    out["streams_all_blocks_on_time"] = on_time
     if args.stream_multi > 0:
         m = stream_bench(xe, inputs, torch, args.stream_multi, args.stream_fold, args.stream_multi_blocks,
                          spread_ends=True, ordered=True)
-        total = sum(m["sustained_TFLOP/s"])
-        m["device_sustained_TFLOP/s"] = round(total, 1)
-        m["streams_by_device_rate"] = int(total // m["realtime_TFLOP/s_needed_per_stream"])
+        # saturated (the admitted streams fall behind): the device's fold rate at this k
+        m["device_sustained_TFLOP/s"] = round(sum(m["sustained_TFLOP/s"]), 1)
         out["stream_multi"] = m
     return out
 
