@@ -484,3 +484,51 @@ def test_correlate_captured_in_a_graph():
         g.replay()
         torch.cuda.synchronize()
         assert torch.equal(out, ref)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_stream_schedules_randomised(seed):
+    """Two int8 streams of different shapes on one server, blocks committed in
+    turn, each with a schedule drawn from {all channels, staggered, staggered
+    with spread ends} and the server's fold order on or off: every integration,
+    read as soon as it is published (spread ends: also after a flush at the
+    end), equals the oracle bit for bit."""
+    rng = np.random.default_rng(100 + seed)
+    srv = xe.Server()
+    srv.set_fold_order(bool(rng.integers(2)))
+    streams = []
+    for _ in range(2):
+        S, C = int(rng.integers(3, 41)), int(rng.integers(1, 7))
+        k = int(rng.integers(1, 5))
+        bpi = k * int(rng.integers(1, 4))
+        bt = int(rng.choice([8, 16, 24, 40]))
+        mode = int(rng.integers(3))
+        d = xe.Server.desc(S, C, bt, bpi, blocks_per_fold=k, ring_blocks=2 * k + int(rng.integers(0, 4)),
+                           block_period_s=0.001, staggered=mode > 0, spread_ends=mode == 2)
+        streams.append(dict(sid=srv.open(d), S=S, C=C, bt=bt, bpi=bpi, blocks=[], read=-1))
+    n_int = 3
+    for b in range(n_int * max(s["bpi"] for s in streams)):
+        for st in streams:
+            if len(st["blocks"]) == n_int * st["bpi"]:
+                continue
+            blk = inputs.ci8_gaussian(st["C"], st["bt"], st["S"], seed=int(rng.integers(1 << 30)), device=DEV)
+            st["blocks"].append(blk)
+            _commit_blocks(srv, st["sid"], [blk], st["C"], st["bt"], st["S"])
+            _read_published(srv, st)
+    for st in streams:
+        srv.flush(st["sid"])
+        _read_published(srv, st)
+        assert st["read"] == n_int - 1
+        stats = srv.stats(st["sid"])
+        assert stats["pending"] == 0 and stats["integrations"] == n_int
+    srv.close()
+
+
+def _read_published(srv, st):
+    """Reads and checks every integration of stream st published since the last call."""
+    latest = srv.latest(st["sid"])[1]
+    for n in range(st["read"] + 1, latest + 1):
+        window = torch.cat(st["blocks"][n * st["bpi"]:(n + 1) * st["bpi"]], dim=1)
+        got = _read_integration(srv, st["sid"], n, st["C"], st["S"])
+        assert np.array_equal(got, oracle_vis(window)), (st["S"], st["C"], n)
+        st["read"] = n
