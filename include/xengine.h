@@ -684,9 +684,9 @@ xc_status xc_pfb_run(xc_pfb *pfb, const void *z, const float *taps, const void *
  * frame, polarisation: each station's frames contiguous per channel), the
  * layout xc_correlate_station_major takes, in one kernel: no intermediate
  * and no corner turn (the FX correlator's corner turn, Section 7, then
- * happens in the correlator's copies into LDS).  N = 256 only (other N:
- * XC_ERR_UNSUPPORTED); x must be 16-byte aligned.  Otherwise as xc_pfb_run,
- * and bit-identical to its output up to the layout.
+ * happens in the correlator's copies into LDS).  x must be 16-byte aligned.
+ * Otherwise as xc_pfb_run, and bit-identical to its output up to the
+ * layout.
  */
 xc_status xc_pfb_run_station_major(xc_pfb *pfb, const void *z, const float *taps, const void *weights, void *x,
                                    void *stream);

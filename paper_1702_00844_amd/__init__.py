@@ -325,8 +325,8 @@ class Pfb:
 
     def run(self, z: torch.Tensor, taps: torch.Tensor, weights: torch.Tensor | None = None,
             out: torch.Tensor | None = None, stream=None, layout: int = XC_LAYOUT_TIME_MAJOR) -> torch.Tensor:
-        """layout = XC_LAYOUT_STATION_MAJOR writes x[N][S][T][2] in one kernel
-        (256 channels), for ``correlate(..., layout=XC_LAYOUT_STATION_MAJOR)``."""
+        """layout = XC_LAYOUT_STATION_MAJOR writes x[N][S][T][2] in one kernel,
+        for ``correlate(..., layout=XC_LAYOUT_STATION_MAJOR)``."""
         if z.dtype != torch.complex64 or tuple(z.shape) != (self.S, 2, self.n_in):
             raise ValueError(f"z must be complex64 of shape {(self.S, 2, self.n_in)}")
         if taps.dtype != torch.float32 or taps.numel() != self.M * self.N:

@@ -47,21 +47,15 @@ struct Geo {
     static constexpr int LOG2N = N == 256 ? 8 : 9;
 };
 
+// Filter and transform frames f0 .. f0 + nf - 1 of one stream zs: thread tid
+// (of THREADS) owns branches tid + b THREADS.  The spectra end in
+// buf[return value]; every call of a workgroup passes the same number of
+// barriers (the two halves of the station-major kernel call it side by side).
 template <int N>
-__global__ __launch_bounds__(THREADS) void filter_fft(const float2 *__restrict__ z, const float *__restrict__ taps,
-                                                      const float2 *__restrict__ weights,
-                                                      const float2 *__restrict__ twiddle, float2 *__restrict__ y,
-                                                      int M, int n_in, int T) {
+__device__ __forceinline__ int filter_transform(const float2 *__restrict__ zs, const float *__restrict__ taps, int M,
+                                                int T, int f0, int nf, const float2 *tw,
+                                                float2 (*buf)[Geo<N>::FB * N], int tid) {
     typedef Geo<N> G;
-    __shared__ __attribute__((aligned(16))) float2 buf[2][G::FB * N];
-    __shared__ float2 tw[N / 2];
-    const int tid = threadIdx.x;
-    const int stream = blockIdx.y;
-    const int f0 = blockIdx.x * G::FB;
-    const int nf = T - f0 < G::FB ? T - f0 : G::FB;          // frames of this block
-    for (int i = tid; i < N / 2; i += THREADS) tw[i] = twiddle[i];
-
-    const float2 *zs = z + (size_t)stream * n_in;
     // every input sample of the block's frames (frames f0 .. f0 + nf + M - 2 of
     // the stream) is loaded at once, so that the block waits for memory once;
     // the loads are unconditional (frame indices clamped to the last frame of
@@ -122,6 +116,23 @@ __global__ __launch_bounds__(THREADS) void filter_fft(const float2 *__restrict__
         __syncthreads();
         src ^= 1;
     }
+    return src;
+}
+
+template <int N>
+__global__ __launch_bounds__(THREADS) void filter_fft(const float2 *__restrict__ z, const float *__restrict__ taps,
+                                                      const float2 *__restrict__ weights,
+                                                      const float2 *__restrict__ twiddle, float2 *__restrict__ y,
+                                                      int M, int n_in, int T) {
+    typedef Geo<N> G;
+    __shared__ __attribute__((aligned(16))) float2 buf[2][G::FB * N];
+    __shared__ float2 tw[N / 2];
+    const int tid = threadIdx.x;
+    const int stream = blockIdx.y;
+    const int f0 = blockIdx.x * G::FB;
+    const int nf = T - f0 < G::FB ? T - f0 : G::FB;          // frames of this block
+    for (int i = tid; i < N / 2; i += THREADS) tw[i] = twiddle[i];
+    const int src = filter_transform<N>(z + (size_t)stream * n_in, taps, M, T, f0, nf, tw, buf, tid);
 
     // weights and the channel rows of the block's frames
     const float2 *ws = weights ? weights + (size_t)stream * N : nullptr;
@@ -133,6 +144,73 @@ __global__ __launch_bounds__(THREADS) void filter_fft(const float2 *__restrict__
             v = make_float2(v.x * w.x - v.y * w.y, v.x * w.y + v.y * w.x);
         }
         ys[q] = v;
+    }
+}
+
+// Station-major output for the Stockham kernel's channel counts (512): one
+// workgroup of 2 THREADS per (station, block of FB frames), its two halves
+// filtering and transforming the station's two polarisation streams side by
+// side; the spectra are then turned in LDS into rows of channel k (the
+// block's frames x both polarisations) and leave as runs of x[k][s][t][p],
+// as in filter_fft256_sm.
+template <int N>
+__global__ __launch_bounds__(2 * THREADS) void filter_fft_sm(const float2 *__restrict__ z,
+                                                             const float *__restrict__ taps,
+                                                             const float2 *__restrict__ weights,
+                                                             const float2 *__restrict__ twiddle,
+                                                             float2 *__restrict__ x, int S, int M, int n_in, int T,
+                                                             int nfb, int nwork) {
+    typedef Geo<N> G;
+    constexpr int OROW = 2 * G::FB + 1;    // one channel: FB frames x 2 pols, padded by one against bank conflicts
+    constexpr int NV = G::FB * N / THREADS;   // spectrum values per thread
+    static_assert(N * OROW <= 2 * 2 * G::FB * N, "the channel rows fit the filter buffers");
+    __shared__ __attribute__((aligned(16))) float2 buf[2][2][G::FB * N];
+    __shared__ float2 tw[N / 2];
+    const int tid = threadIdx.x;
+    const int p = tid / THREADS;           // polarisation of this half
+    const int t = tid - p * THREADS;
+    const int w = xcd_remap(blockIdx.x, nwork);
+    if (w < 0) return;
+    const int s = w / nfb;
+    const int f0 = (w - s * nfb) * G::FB;
+    const int nf = T - f0 < G::FB ? T - f0 : G::FB;
+    const int stream = 2 * s + p;
+    for (int i = tid; i < N / 2; i += 2 * THREADS) tw[i] = twiddle[i];
+    __syncthreads();
+    const int src = filter_transform<N>(z + (size_t)stream * n_in, taps, M, T, f0, nf, tw, buf[p], t);
+    // this half's spectra (weighted) into registers, then the channel rows in their place
+    const float2 *ws = weights ? weights + (size_t)stream * N : nullptr;
+    float2 v[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        const int q = t + i * THREADS;      // frame q / N, channel q % N
+        float2 a = make_float2(0.f, 0.f);
+        if (q < nf * N) {
+            a = buf[p][src][q];
+            if (ws) {
+                const float2 c = ws[q & (N - 1)];
+                a = make_float2(a.x * c.x - a.y * c.y, a.x * c.y + a.y * c.x);
+            }
+        }
+        v[i] = a;
+    }
+    __syncthreads();
+    float2 *img = &buf[0][0][0];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        const int q = t + i * THREADS;
+        if (q < nf * N) img[(q & (N - 1)) * OROW + 2 * (q / N) + p] = v[i];
+    }
+    __syncthreads();
+    // channel k, frame r: both polarisations, 16 bytes
+    float2 *xs = x + ((size_t)s * T + f0) * 2;
+    const size_t kstride = (size_t)S * T * 2;
+    for (int e = tid; e < N * G::FB; e += 2 * THREADS) {
+        const int k = e / G::FB, r = e - k * G::FB;
+        if (r < nf) {
+            const float2 v0 = img[k * OROW + 2 * r], v1 = img[k * OROW + 2 * r + 1];
+            *reinterpret_cast<float4 *>(xs + k * kstride + 2 * r) = make_float4(v0.x, v0.y, v1.x, v1.y);
+        }
     }
 }
 
@@ -370,6 +448,18 @@ __global__ __launch_bounds__(2 * THREADS) void filter_fft256_sm(const float2 *__
     }
 }
 
+template <int N>
+hipError_t launch_filter_fft_sm(const void *z, const float *taps, const void *weights, const float2 *twiddle, void *x,
+                                int S, int M, int n_in, int T, hipStream_t stream) {
+    const int nfb = (T + Geo<N>::FB - 1) / Geo<N>::FB;
+    const int64_t nwork = (int64_t)nfb * S;
+    if (nwork > ((int64_t)1 << 31) - kNumXcd) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(filter_fft_sm<N>, dim3(xcd_grid((int)nwork)), dim3(2 * THREADS), 0, stream,
+                       static_cast<const float2 *>(z), taps, static_cast<const float2 *>(weights), twiddle,
+                       static_cast<float2 *>(x), S, M, n_in, T, nfb, (int)nwork);
+    return hipGetLastError();
+}
+
 hipError_t launch_filter_fft256_sm(const void *z, const float *taps, const void *weights, const float2 *twiddle,
                                    void *x, int S, int M, int n_in, int T, hipStream_t stream) {
     const int nfb = (T + 15) / 16;
@@ -500,9 +590,10 @@ xc_status xc_pfb_run_station_major(xc_pfb *p, const void *z, const float *taps, 
         return set_error(XC_ERR_INVALID_ARG,
                          "misaligned pointer (samples and weights: 8 bytes, output: 16 bytes, taps: 4 bytes)");
     if (x == z) return set_error(XC_ERR_INVALID_ARG, "the filter bank is out of place (x == z)");
-    if (p->N != 256) return set_error(XC_ERR_UNSUPPORTED, "station-major output is built for 256 channels");
-    hipError_t e = pfb::launch_filter_fft256_sm(z, taps, weights, p->twiddle, x, p->S, p->M, p->n_in, p->T,
-                                                static_cast<hipStream_t>(stream));
+    hipError_t e = p->N == 256 ? pfb::launch_filter_fft256_sm(z, taps, weights, p->twiddle, x, p->S, p->M, p->n_in,
+                                                              p->T, static_cast<hipStream_t>(stream))
+                               : pfb::launch_filter_fft_sm<512>(z, taps, weights, p->twiddle, x, p->S, p->M,
+                                                                p->n_in, p->T, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_error(e, "filter-bank launch");
     return XC_OK;
 }
