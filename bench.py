@@ -877,8 +877,9 @@ def fengine_bench(xe, inputs, torch, dev, stream, steps=20):
 
 def stream_all(xe, inputs, torch, args):
     """The streaming measurements.  One stream at the real-time rate with
-    staggered folds for every fold length k of --stream-ks (deadline k P per
-    block), each over --stream-blocks blocks after a warm-up integration; the
+    staggered folds (integration ends spread over the groups' turns) for every
+    fold length k of --stream-ks (deadline k P per block), each over
+    --stream-blocks blocks after a warm-up integration; the
     headline run is the smallest k whose block p99 meets the deadline.  Beside
     it: k = 8 with all channels folded every 8 blocks (the unstaggered
     schedule); two streams at the real-time rate with k = --stream-two-k,
@@ -888,7 +889,7 @@ def stream_all(xe, inputs, torch, args):
     run gives the device's sustained fold rate."""
     out = {}
     ks = [int(v) for v in args.stream_ks.split(",") if v.strip()]
-    runs = [stream_bench(xe, inputs, torch, 1, k, args.stream_blocks) for k in ks]
+    runs = [stream_bench(xe, inputs, torch, 1, k, args.stream_blocks, spread_ends=True) for k in ks]
     if runs:
         meeting = [r for r in runs if r["block_p99_ms"][0] <= r["deadline_ms"]]
         head = dict(min(meeting, key=lambda r: r["k"]) if meeting else max(runs, key=lambda r: r["k"]))
