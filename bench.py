@@ -19,6 +19,7 @@ vector-ALU form on the same values).
 from __future__ import annotations
 
 import argparse
+import gc
 import hashlib
 import json
 import math
@@ -1000,7 +1001,14 @@ def stream_bench(xe, inputs, torch, n_streams, k, n_blocks, S=512, C=4096, bt=25
     feed(bpi - 2 * k)
     for sid in sids:
         srv.reset_stats(sid)
-    stalls = feed(n_blocks)
+    # the producer loop runs without the Python garbage collector, whose pauses
+    # would delay commits past their scheduled arrival and count as latency
+    gc.collect()
+    gc.disable()
+    try:
+        stalls = feed(n_blocks)
+    finally:
+        gc.enable()
     per = [srv.stats(sid) for sid in sids]
     for sid in sids:
         srv.close_stream(sid)
