@@ -9,9 +9,13 @@
 //     x[k][t][s][p] = w[s][p][k] y_{s,p}[t][k]         (w optional)
 //
 // and its output x is the correlator's channel-major, time-major input: the
-// FX correlator's corner turn (Section 7) is the last step.
+// FX correlator's corner turn (Section 7) is the last step.  The station-major
+// form x[k][s][t][p] (the correlator's other input layout) is written by one
+// kernel per channel count (filter_fft256_sm, filter_fft_sm): a workgroup
+// takes both polarisations of a station, and the spectra are turned in LDS
+// into per-channel runs of the block's frames, so there is no intermediate.
 //
-// Two HBM-bound kernels:
+// Time-major output, two HBM-bound kernels:
 //  * filter_fft: one workgroup per (station-polarisation stream, block of
 //    frames); thread n owns polyphase branch n (and n + 256): its M taps and
 //    the samples of the block's frames (plus the M - 1 frames after them)
