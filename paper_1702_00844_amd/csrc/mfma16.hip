@@ -18,8 +18,10 @@
 //    waves carry equal work.  For 64 stations this computes 9216 complex
 //    products per time step for 8320 wanted (90 %).
 //  * TS = 2 splits every staged chunk of time steps between two groups of four
-//    waves (two waves per SIMD); the second group's partial sums are added
-//    into the first's through LDS before the single store.
+//    waves (two waves per SIMD); off the diagonal the second group's partial
+//    sums are added into the first's through LDS before the single store, on
+//    it each group writes a triangle image of its own and the copy-out adds
+//    the two.
 //  * Samples go from HBM straight into LDS (global_load_lds, see lds_dma.h),
 //    in their time-major layout: one 1 KiB row per block and time step (block
 //    I only on the diagonal, I then J elsewhere).  Two stages of 64 KiB (two
