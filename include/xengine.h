@@ -577,6 +577,25 @@ xc_status xc_stream_close(xc_server *srv, int32_t stream_id);
 /* q-quantile (0..1) of n values by the nearest-rank method; NaN if n == 0. */
 double xc_quantile(const double *values, int64_t n, double q);
 
+/* The fold schedule of a stream (the real-time stream of Section 1,
+ * integrated in sub-intervals whose partial sums are added, as Section 4.5
+ * does), computed on the host without touching a device: the folds the server
+ * enqueues when blocks 0 .. n_blocks - 1 are committed and, with flush = 1,
+ * xc_stream_flush is called after them.  Row r of folds (6 int64 per row; the
+ * first max_folds rows are written, caller-owned) is {trigger block (whose
+ * commit enqueues the fold; n_blocks - 1 for the flush), channel group, first
+ * channel, end channel (exclusive; equal to the first when the group has no
+ * channels), first block, last block}, in enqueue order, and every fold lies
+ * within one integration.  published_after[j] (max_integrations entries,
+ * caller-owned) is the block whose commit publishes integration j, n_blocks
+ * if the flush does, -1 if neither.  *n_folds is the number of folds, also
+ * beyond max_folds.  Errors: the descriptor checks of xc_stream_open,
+ * XC_ERR_INVALID_ARG (null output pointers, negative counts, flush not 0 or
+ * 1). */
+xc_status xc_stream_schedule(const xc_stream_desc *desc, int64_t n_blocks, int32_t flush, int64_t *folds,
+                             int64_t max_folds, int64_t *n_folds, int64_t *published_after,
+                             int64_t max_integrations);
+
 /* ------------------------------------------------------------------------ */
 /* Host ingest: samples in host memory (Section 3.6's host-to-device bound,    */
 /* Section 4.4's asynchronous copies and memory-layout transpose).            */

@@ -517,6 +517,24 @@ class Server:
     def footprint(desc) -> int:
         return int(lib().xc_stream_footprint(ctypes.byref(desc)))
 
+    @staticmethod
+    def schedule(desc, n_blocks: int, flush: bool = False):
+        """The folds the server enqueues for n_blocks commits (and a flush),
+        computed on the host: (folds, published_after), folds as rows
+        (trigger block, group, first channel, end channel, first block,
+        last block), published_after[j] the block whose commit publishes
+        integration j (n_blocks: the flush; -1: not published)."""
+        n = ctypes.c_int64()
+        n_int = n_blocks // desc.blocks_per_integration + 1
+        pub = (ctypes.c_int64 * n_int)()
+        _lib.check(lib().xc_stream_schedule(ctypes.byref(desc), n_blocks, 1 if flush else 0, None, 0,
+                                            ctypes.byref(n), pub, n_int))
+        rows = (ctypes.c_int64 * (6 * max(n.value, 1)))()
+        _lib.check(lib().xc_stream_schedule(ctypes.byref(desc), n_blocks, 1 if flush else 0, rows, n.value,
+                                            ctypes.byref(n), pub, n_int))
+        folds = [tuple(rows[6 * r:6 * r + 6]) for r in range(n.value)]
+        return folds, list(pub)
+
     def open(self, desc) -> int:
         sid = ctypes.c_int32()
         _lib.check(lib().xc_stream_open(self._h, ctypes.byref(desc), ctypes.byref(sid)))

@@ -108,6 +108,8 @@ SIGNATURES = {
     "xc_server_set_fold_order": (c_i32, [c_vp, c_i32]),
     "xc_stream_reset_stats": (c_i32, [c_vp, c_i32]),
     "xc_quantile": (c_f64, [ctypes.POINTER(c_f64), c_i64, c_f64]),
+    "xc_stream_schedule": (c_i32, [ctypes.POINTER(XcStreamDesc), c_i64, c_i32, ctypes.POINTER(c_i64), c_i64,
+                                   ctypes.POINTER(c_i64), ctypes.POINTER(c_i64), c_i64]),
     "xc_transpose_to_time_major": (c_i32, [c_vp, c_vp, c_i32, c_i32, c_i32, c_i32, c_i32, c_vp]),
     "xc_ingest_create": (c_i32, [c_i32, c_i32, c_i32, c_i32, c_i32, c_i32, c_i32, ctypes.POINTER(c_vp)]),
     "xc_ingest_info": (c_i32, [c_vp, ctypes.POINTER(c_i32), ctypes.POINTER(c_i64)]),

@@ -206,11 +206,93 @@ static void stream_free(Stream &s) {
     s = Stream{};
 }
 
-// Channels [c0, c1) of channel group g of G.
+// Channels [c0, c1) of channel group g of groups, over C channels.
+static void group_range(int C, int groups, int g, int &c0, int &c1) {
+    c0 = (int)((int64_t)C * g / groups);
+    c1 = (int)((int64_t)C * (g + 1) / groups);
+}
+
 static void group_channels(const Stream &s, int g, int &c0, int &c1) {
-    const int C = s.d.n_channels;
-    c0 = (int)((int64_t)C * g / s.groups);
-    c1 = (int)((int64_t)C * (g + 1) / s.groups);
+    group_range(s.d.n_channels, s.groups, g, c0, c1);
+}
+
+// ---- The fold schedule (host logic only, no device calls) ----
+
+struct PlannedFold {
+    int g;                 // channel group
+    int64_t first, last;   // blocks, all in one integration
+};
+
+// Appends the folds of group g over blocks first .. last, one per integration
+// they fall in.
+static void plan_range(int g, int64_t first, int64_t last, int64_t bpi, std::vector<PlannedFold> &out) {
+    while (first <= last) {
+        const int64_t end = std::min(last, (first / bpi + 1) * bpi - 1);
+        out.push_back(PlannedFold{g, first, end});
+        first = end + 1;
+    }
+}
+
+// Appends, in enqueue order, the folds that the commit of block n starts;
+// next[g] (each group's first block not yet folded) is advanced.
+static void plan_commit(const xc_stream_desc &d, int groups, int64_t n, std::vector<int64_t> &next,
+                        std::vector<PlannedFold> &out) {
+    const int64_t bpi = d.blocks_per_integration, m = n % bpi;
+    const int k = d.blocks_per_fold;
+    const bool spread = d.staggered == 2;
+    if (m == 0 && !spread)
+        for (auto &g : next) g = n;
+    auto take = [&](int g) {
+        plan_range(g, next[g], n, bpi, out);
+        next[g] = n + 1;
+    };
+    if (groups == 1) {
+        if ((m + 1) % k == 0) take(0);
+    } else if (spread) {
+        // group m mod k folds its outstanding blocks, the rest of the last
+        // integration first
+        const int g = (int)(m % k);
+        if (next[g] <= n) take(g);
+    } else {
+        // group m mod k folds its outstanding blocks.  At the end of the
+        // integration every group does, in the order of their oldest pending
+        // block (the regular group's k blocks first, then the others' shorter
+        // remainders), so that each block's last fold comes as early as it can.
+        const bool last = m == bpi - 1;
+        std::vector<int> order;
+        for (int g = 0; g < groups; ++g)
+            if ((last || g == (int)(m % k)) && next[g] <= n) order.push_back(g);
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return next[a] < next[b]; });
+        for (int g : order) take(g);
+    }
+}
+
+// Spread ends: the folds that complete every integration whose blocks have
+// all been committed, oldest pending block first.
+static void plan_flush(const xc_stream_desc &d, int groups, int64_t committed, std::vector<int64_t> &next,
+                       std::vector<PlannedFold> &out) {
+    if (d.staggered != 2) return;     // nothing is left over past an integration's end
+    const int64_t bpi = d.blocks_per_integration;
+    const int64_t end = committed / bpi * bpi;
+    std::vector<int> order;
+    for (int g = 0; g < groups; ++g)
+        if (next[g] < end) order.push_back(g);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return next[a] < next[b]; });
+    for (int g : order) {
+        plan_range(g, next[g], end - 1, bpi, out);
+        next[g] = end;
+    }
+}
+
+// Last integration published once `committed` blocks are in and the groups
+// have folded up to next: with spread ends, every integration that all groups
+// have folded past; otherwise each integration at its last block.
+static int64_t plan_published(const xc_stream_desc &d, int64_t committed, const std::vector<int64_t> &next) {
+    const int64_t bpi = d.blocks_per_integration;
+    int64_t folded = committed;
+    if (d.staggered == 2)
+        for (int64_t g : next) folded = std::min(folded, g);
+    return folded / bpi - 1;
 }
 
 // Enqueues the fold of channel group g over blocks first .. last (absolute
@@ -264,6 +346,58 @@ size_t xc_stream_footprint(const xc_stream_desc *d) {
     const size_t acc = (size_t)d->n_channels * B * 4 * 8;
     const size_t block = (size_t)d->n_channels * d->block_times * d->n_stations * 2 * in_elem_bytes(d->in_type);
     return 2 * acc + (size_t)d->ring_blocks * block;
+}
+
+xc_status xc_stream_schedule(const xc_stream_desc *desc, int64_t n_blocks, int32_t flush, int64_t *folds,
+                             int64_t max_folds, int64_t *n_folds, int64_t *published_after,
+                             int64_t max_integrations) {
+    if (!n_folds || (max_folds > 0 && !folds) || (max_integrations > 0 && !published_after))
+        return set_error(XC_ERR_INVALID_ARG, "null output pointer");
+    if (n_blocks < 0 || max_folds < 0 || max_integrations < 0)
+        return set_error(XC_ERR_INVALID_ARG, "negative count");
+    if (flush != 0 && flush != 1) return set_error(XC_ERR_INVALID_ARG, "flush must be 0 or 1");
+    xc_status st = validate_desc(desc);
+    if (st != XC_OK) return st;
+    const xc_stream_desc &d = *desc;
+    const int groups = d.staggered ? d.blocks_per_fold : 1;
+    std::vector<int64_t> next((size_t)groups, 0);
+    std::vector<PlannedFold> plan;
+    for (int64_t j = 0; j < max_integrations; ++j) published_after[j] = -1;
+    int64_t count = 0, published = -1;
+    auto emit = [&](int64_t trigger) {
+        for (const auto &f : plan) {
+            if (count < max_folds) {
+                int c0, c1;
+                group_range(d.n_channels, groups, f.g, c0, c1);
+                int64_t *r = folds + 6 * count;
+                r[0] = trigger;
+                r[1] = f.g;
+                r[2] = c0;
+                r[3] = c1;
+                r[4] = f.first;
+                r[5] = f.last;
+            }
+            ++count;
+        }
+        plan.clear();
+    };
+    auto publish = [&](int64_t committed, int64_t when) {
+        const int64_t last = plan_published(d, committed, next);
+        for (int64_t j = published + 1; j <= last && j < max_integrations; ++j) published_after[j] = when;
+        published = std::max(published, last);
+    };
+    for (int64_t n = 0; n < n_blocks; ++n) {
+        plan_commit(d, groups, n, next, plan);
+        emit(n);
+        publish(n + 1, n);
+    }
+    if (flush) {
+        plan_flush(d, groups, n_blocks, next, plan);
+        emit(n_blocks - 1);
+        publish(n_blocks, n_blocks);
+    }
+    *n_folds = count;
+    return XC_OK;
 }
 
 double xc_quantile(const double *values, int64_t n, double q) {
@@ -393,31 +527,33 @@ xc_status xc_stream_acquire(xc_server *srv, int32_t id, void **block_dev_ptr) {
     return XC_OK;
 }
 
-// Folds group g of stream id over blocks first .. last, one fold per
-// integration they fall in, in the server's fold order.
-static xc_status fold_range(xc_server *srv, Stream &s, int32_t id, int g, int64_t first, int64_t last,
-                            int64_t trigger) {
-    const int64_t bpi = s.d.blocks_per_integration;
-    while (first <= last) {
-        const int64_t end = std::min(last, (first / bpi + 1) * bpi - 1);
-        const Stream *prev = nullptr;
-        if (srv->ordered && srv->last_fold >= 0 && srv->last_fold != id && srv->streams[srv->last_fold].open)
-            prev = &srv->streams[srv->last_fold];
-        xc_status st = enqueue_fold(s, prev, g, first, end, trigger);
+// Enqueues a planned fold of stream id, after the server's previous fold when
+// folds run in order.
+static xc_status enqueue_planned(xc_server *srv, Stream &s, int32_t id, const PlannedFold &f, int64_t trigger) {
+    const Stream *prev = nullptr;
+    if (srv->ordered && srv->last_fold >= 0 && srv->last_fold != id && srv->streams[srv->last_fold].open)
+        prev = &srv->streams[srv->last_fold];
+    xc_status st = enqueue_fold(s, prev, f.g, f.first, f.last, trigger);
+    if (st == XC_OK) srv->last_fold = id;
+    return st;
+}
+
+// Enqueues the planned folds in order; each group's progress is kept as far
+// as its folds were enqueued, the planned progress once all were.
+static xc_status enqueue_plan(xc_server *srv, Stream &s, int32_t id, const std::vector<PlannedFold> &plan,
+                              const std::vector<int64_t> &next, int64_t trigger) {
+    for (const auto &f : plan) {
+        xc_status st = enqueue_planned(srv, s, id, f, trigger);
         if (st != XC_OK) return st;
-        srv->last_fold = id;
-        first = end + 1;
+        s.group_next[f.g] = f.last + 1;
     }
+    s.group_next = next;
     return XC_OK;
 }
 
-// Spread ends: publishes every integration whose blocks have all been
-// committed and folded by every group.
-static xc_status publish_folded(Stream &s) {
-    const int64_t bpi = s.d.blocks_per_integration;
-    int64_t folded = s.committed;
-    for (int64_t g : s.group_next) folded = std::min(folded, g);
-    while ((s.published_seq + 2) * bpi <= folded) {
+// Records the ready event of every integration up to `last` not yet published.
+static xc_status publish_up_to(Stream &s, int64_t last) {
+    while (s.published_seq < last) {
         const int64_t j = s.published_seq + 1;
         hipError_t e = hipEventRecord(s.ready_ev[j % 2], s.hs);
         if (e != hipSuccess) return hip_error(e, "integration event");
@@ -440,58 +576,19 @@ static xc_status commit_locked(xc_server *srv, Stream *s, int32_t id, uint64_t a
     s->block_fold.push_back(nullptr);
     const int64_t bpi = s->d.blocks_per_integration;
     const int64_t integ = n / bpi, m = n % bpi;
-    const int k = s->d.blocks_per_fold;
-    const bool spread = s->d.staggered == 2;
-    if (m == 0) {
+    if (m == 0 && s->release_pending[integ % 2]) {
         // a new integration starts: its accumulator held integration integ - 2,
         // which a consumer may still be reading
-        if (s->release_pending[integ % 2]) {
-            hipError_t e = hipStreamWaitEvent(s->hs, s->release_ev[integ % 2], 0);
-            if (e != hipSuccess) return hip_error(e, "release event");
-            s->release_pending[integ % 2] = false;
-        }
-        if (!spread)
-            for (auto &g : s->group_next) g = n;
+        hipError_t e = hipStreamWaitEvent(s->hs, s->release_ev[integ % 2], 0);
+        if (e != hipSuccess) return hip_error(e, "release event");
+        s->release_pending[integ % 2] = false;
     }
-    const bool last = m == bpi - 1;
-    xc_status st = XC_OK;
-    if (s->groups == 1) {
-        if ((m + 1) % k == 0) {
-            st = fold_range(srv, *s, id, 0, s->group_next[0], n, n);
-            s->group_next[0] = n + 1;
-        }
-    } else if (spread) {
-        // group m mod k folds its outstanding blocks, the rest of the last
-        // integration first
-        const int g = (int)(m % k);
-        if (s->group_next[g] <= n) {
-            st = fold_range(srv, *s, id, g, s->group_next[g], n, n);
-            s->group_next[g] = n + 1;
-        }
-    } else {
-        // group m mod k folds its outstanding blocks.  At the end of the
-        // integration every group does, in the order of their oldest pending
-        // block (the regular group's k blocks first, then the others' shorter
-        // remainders), so that each block's last fold comes as early as it can.
-        std::vector<int> order;
-        for (int g = 0; g < s->groups; ++g)
-            if ((last || g == (int)(m % k)) && s->group_next[g] <= n) order.push_back(g);
-        std::stable_sort(order.begin(), order.end(),
-                         [&](int a, int b) { return s->group_next[a] < s->group_next[b]; });
-        for (int g : order) {
-            st = fold_range(srv, *s, id, g, s->group_next[g], n, n);
-            if (st != XC_OK) break;
-            s->group_next[g] = n + 1;
-        }
-    }
+    std::vector<int64_t> next = s->group_next;
+    std::vector<PlannedFold> plan;
+    plan_commit(s->d, s->groups, n, next, plan);
+    xc_status st = enqueue_plan(srv, *s, id, plan, next, n);
     if (st != XC_OK) return st;
-    if (spread) return publish_folded(*s);
-    if (last) {
-        hipError_t e = hipEventRecord(s->ready_ev[integ % 2], s->hs);
-        if (e != hipSuccess) return hip_error(e, "integration event");
-        s->published_seq = integ;
-    }
-    return XC_OK;
+    return publish_up_to(*s, plan_published(s->d, s->committed, s->group_next));
 }
 
 xc_status xc_stream_commit(xc_server *srv, int32_t id, uint64_t arrival_ns) {
@@ -681,18 +778,12 @@ xc_status xc_stream_flush(xc_server *srv, int32_t id) {
     std::lock_guard<std::mutex> lk(srv->mu);
     Stream *s = get_stream(srv, id);
     if (!s) return set_error(XC_ERR_INVALID_ARG, "no open stream %d", id);
-    if (s->d.staggered != 2) return XC_OK;     // nothing is left over past an integration's end
-    const int64_t end = s->committed / s->d.blocks_per_integration * s->d.blocks_per_integration;
-    std::vector<int> order;
-    for (int g = 0; g < s->groups; ++g)
-        if (s->group_next[g] < end) order.push_back(g);
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return s->group_next[a] < s->group_next[b]; });
-    for (int g : order) {
-        xc_status st = fold_range(srv, *s, id, g, s->group_next[g], end - 1, s->committed - 1);
-        if (st != XC_OK) return st;
-        s->group_next[g] = end;
-    }
-    return publish_folded(*s);
+    std::vector<int64_t> next = s->group_next;
+    std::vector<PlannedFold> plan;
+    plan_flush(s->d, s->groups, s->committed, next, plan);
+    xc_status st = enqueue_plan(srv, *s, id, plan, next, s->committed - 1);
+    if (st != XC_OK) return st;
+    return publish_up_to(*s, plan_published(s->d, s->committed, s->group_next));
 }
 
 xc_status xc_server_set_fold_order(xc_server *srv, int32_t one_at_a_time) {
