@@ -121,6 +121,20 @@ int main(int argc, char **argv) {
     CHECK(xc_stream_flush(srv, 99) == XC_ERR_INVALID_ARG);
     xc_server_destroy(srv);
 
+    /* the fold schedule on the host: counting, a full and a truncated listing */
+    xc_stream_desc sd = d;
+    sd.staggered = 2;
+    int64_t nf = -1, pub[4];
+    CHECK(xc_stream_schedule(&sd, 11, 1, NULL, 0, &nf, pub, 4) == XC_OK && nf > 0);
+    int64_t *rows = (int64_t *)malloc((size_t)nf * 6 * sizeof(int64_t));
+    int64_t nf2 = -1;
+    CHECK(rows != NULL && xc_stream_schedule(&sd, 11, 1, rows, nf, &nf2, pub, 4) == XC_OK && nf2 == nf);
+    CHECK(rows[4] == 0 && pub[0] >= 3 && pub[1] >= 7 && pub[2] == -1 && pub[3] == -1);
+    CHECK(xc_stream_schedule(&sd, 11, 1, rows, 1, &nf2, pub, 1) == XC_OK && nf2 == nf);
+    CHECK(xc_stream_schedule(&sd, 11, 3, rows, 1, &nf2, pub, 1) == XC_ERR_INVALID_ARG);
+    CHECK(xc_stream_schedule(&sd, 11, 0, rows, 1, NULL, pub, 1) == XC_ERR_INVALID_ARG);
+    free(rows);
+
     if (failures) {
         fprintf(stderr, "%d check(s) failed\n", failures);
         return 1;

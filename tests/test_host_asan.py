@@ -6,7 +6,8 @@ driver in tests/host_asan/, and run with leak checking (leaks inside the HIP
 runtime itself suppressed).  The driver exercises the host logic: index and
 size helpers, quantiles, batch work lists, configuration resolution, tuning
 candidates and cache parsing (valid, malformed and over-long lines), argument
-rejection, stream admission and a stream whose device allocation fails.
+rejection, stream admission, a stream whose device allocation fails, and the
+streaming fold schedule (counted, listed in full and truncated).
 """
 import os
 import subprocess
