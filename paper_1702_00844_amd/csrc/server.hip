@@ -37,6 +37,9 @@
 //     its deadline, and an integration is published once every group has
 //     folded past its end (k - 2 blocks into the next one), or on
 //     xc_stream_flush.
+// The schedules are host logic of their own (plan_commit, plan_flush,
+// plan_published): the server enqueues the folds they plan, and
+// xc_stream_schedule returns the same plan without a device.
 // Folds of different streams run concurrently on their own HIP streams, or,
 // with xc_server_set_fold_order, one at a time in the order they are
 // enqueued (each waits for the server's previous fold): streams whose blocks
