@@ -492,7 +492,8 @@ def test_stream_schedules_randomised(seed):
     turn, each with a schedule drawn from {all channels, staggered, staggered
     with spread ends} and the server's fold order on or off: every integration,
     read as soon as it is published (spread ends: also after a flush at the
-    end), equals the oracle bit for bit."""
+    end), equals the oracle bit for bit; the server publishes at the blocks
+    and runs the folds that the host schedule (xc_stream_schedule) lists."""
     rng = np.random.default_rng(100 + seed)
     srv = xe.Server()
     srv.set_fold_order(bool(rng.integers(2)))
@@ -505,8 +506,10 @@ def test_stream_schedules_randomised(seed):
         mode = int(rng.integers(3))
         d = xe.Server.desc(S, C, bt, bpi, blocks_per_fold=k, ring_blocks=2 * k + int(rng.integers(0, 4)),
                            block_period_s=0.001, staggered=mode > 0, spread_ends=mode == 2)
-        streams.append(dict(sid=srv.open(d), S=S, C=C, bt=bt, bpi=bpi, blocks=[], read=-1))
+        streams.append(dict(sid=srv.open(d), S=S, C=C, bt=bt, bpi=bpi, blocks=[], read=-1, desc=d))
     n_int = 3
+    for st in streams:
+        st["plan"] = xe.Server.schedule(st["desc"], n_int * st["bpi"], flush=True)
     for b in range(n_int * max(s["bpi"] for s in streams)):
         for st in streams:
             if len(st["blocks"]) == n_int * st["bpi"]:
@@ -514,6 +517,9 @@ def test_stream_schedules_randomised(seed):
             blk = inputs.ci8_gaussian(st["C"], st["bt"], st["S"], seed=int(rng.integers(1 << 30)), device=DEV)
             st["blocks"].append(blk)
             _commit_blocks(srv, st["sid"], [blk], st["C"], st["bt"], st["S"])
+            nb = len(st["blocks"]) - 1
+            expect = max([j for j, w in enumerate(st["plan"][1]) if 0 <= w <= nb], default=-1)
+            assert srv.latest(st["sid"])[1] == expect, (nb, expect)
             _read_published(srv, st)
     for st in streams:
         srv.flush(st["sid"])
@@ -521,6 +527,9 @@ def test_stream_schedules_randomised(seed):
         assert st["read"] == n_int - 1
         stats = srv.stats(st["sid"])
         assert stats["pending"] == 0 and stats["integrations"] == n_int
+        folds, pub = st["plan"]
+        assert stats["folds"] == sum(1 for f in folds if f[3] > f[2])    # groups without channels launch nothing
+        assert sum(1 for w in pub if w >= 0) == n_int
     srv.close()
 
 
