@@ -150,6 +150,32 @@ __device__ __forceinline__ ACC mma(const v4i &a, const v4i &b, const ACC &c) {
                                                        0, 0);
 }
 
+// Element offset, within one channel's visibilities, of the 16 bytes of
+// baseline (i, j) and pol p (both q).  Baselines past the last station or
+// below the diagonal are clamped to a valid one, so that accumulate mode can
+// fetch a tile's old values without branches (the clamped values are not
+// stored).
+__device__ __forceinline__ uint32_t piece(int S, int i, int j, int p) {
+    const int jc = j < S ? j : S - 1;
+    const int ic = i <= jc ? i : jc;
+    return (uint32_t)(((size_t)jc * (jc + 1) / 2 + ic) * 4 + p * 2);
+}
+
+// Lane L's k-th piece of the tile at (row0, col0) (the order of
+// store_tile_direct), for accumulate mode: f(k, element offset).
+template <typename F>
+__device__ __forceinline__ void tile_pieces(int S, int row0, int col0, int lane, F f) {
+    const int m = lane & 31;
+    const int i = (row0 >> 1) + (m >> 1);
+    const int p = m & 1;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const int r = (k >> 1) * 4 + (k & 1) * 2;
+        const int n = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        f(k, piece(S, i, (col0 >> 1) + (n >> 1), p));
+    }
+}
+
 // Store (or add, in accumulate mode) one 32 x 32 tile straight from the
 // accumulators, whose column (one per lane) is the (station, pol) row
 // row0 + lane % 32 of block I and whose register r holds row
@@ -160,46 +186,28 @@ __device__ __forceinline__ ACC mma(const v4i &a, const v4i &b, const ACC &c) {
 // 16 baselines, 512 contiguous bytes: eight 16-byte stores per lane and tile,
 // no LDS.  Autocorrelations (i = j) are made Hermitian on the way: XX and YY
 // get imaginary part 0 and the p = 1 lane writes YX = conj(XY), XY coming
-// from its p = 0 neighbour.  Accumulate mode loads the tile's old values
-// first (addresses of the lanes that store nothing clamped to a valid
-// baseline), so that the loads are in flight together.
-template <typename ACC, typename OUT>
-__device__ __forceinline__ void store_tile_direct(const Job &job, int c, const ACC &re, const ACC &im, int row0,
-                                                  int col0, int lane) {
-    const int S = job.S;
-    OUT *__restrict__ V = static_cast<OUT *>(job.vis) + (size_t)c * ((size_t)S * (S + 1) / 2) * 4;
+// from its p = 0 neighbour.  In accumulate mode old(k) gives the old value of
+// the lane's k-th 16 bytes, loaded beforehand (tile_pieces gives their
+// offsets), so that a tile's eight loads are in flight together.
+template <typename ACC, typename OUT, bool ACCUMULATE, typename OLD>
+__device__ __forceinline__ void store_tile_direct(OUT *__restrict__ V, int S, const ACC &re, const ACC &im, int row0,
+                                                  int col0, int lane, OLD old) {
     const int m = lane & 31;
     const int i = (row0 >> 1) + (m >> 1);
     const int p = m & 1;
     const bool on_diag = row0 == col0;       // the tile holds autocorrelations (wave-uniform)
-    int jj[8];
-    bool ok[8];
-    size_t e[8];                              // element index of the lane's 16 bytes (q = 0)
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
         const int r = (k >> 1) * 4 + (k & 1) * 2;
         const int n = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-        jj[k] = (col0 >> 1) + (n >> 1);
-        ok[k] = jj[k] < S && i <= jj[k];
-        const int jc = jj[k] < S ? jj[k] : S - 1;
-        const int ic = i <= jc ? i : jc;
-        e[k] = ((size_t)jc * (jc + 1) / 2 + ic) * 4 + p * 2;
-    }
-    uint4 old[8];
-    if (job.accumulate) {
-#pragma unroll
-        for (int k = 0; k < 8; ++k) old[k] = *reinterpret_cast<const uint4 *>(V + e[k]);
-    }
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        const int r = (k >> 1) * 4 + (k & 1) * 2;
+        const int jj = (col0 >> 1) + (n >> 1);
         OUT v0 = Out<OUT>::make(re[r], im[r]);            // q = 0
         OUT v1 = Out<OUT>::make(re[r + 1], im[r + 1]);    // q = 1
         if (on_diag) {
             // the p = 0 neighbour's XY (its q = 1 value), for YX = conj(XY)
             const uint32_t xr = (uint32_t)__builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v1.x), 0xb1, 0xf, 0xf, false);
             const uint32_t xi = (uint32_t)__builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v1.y), 0xb1, 0xf, 0xf, false);
-            if (i == jj[k]) {
+            if (i == jj) {
                 if (p == 0) {
                     v0.y = 0;                                  // Im XX
                 } else {
@@ -211,8 +219,8 @@ __device__ __forceinline__ void store_tile_direct(const Job &job, int c, const A
         }
         uint4 w = make_uint4(__builtin_bit_cast(uint32_t, v0.x), __builtin_bit_cast(uint32_t, v0.y),
                              __builtin_bit_cast(uint32_t, v1.x), __builtin_bit_cast(uint32_t, v1.y));
-        if (job.accumulate) w = Vec<OUT>::add(w, old[k]);
-        if (ok[k]) *reinterpret_cast<uint4 *>(V + e[k]) = w;
+        if constexpr (ACCUMULATE) w = Vec<OUT>::add(w, old(k));
+        if (jj < S && i <= jj) *reinterpret_cast<uint4 *>(V + piece(S, i, jj, p)) = w;
     }
 }
 
@@ -458,12 +466,29 @@ __device__ __forceinline__ void unit(const Job &job, int c, int bi, int bj, uint
 #pragma unroll
             for (int cs = 0; cs < 2; ++cs) aim[rs][cs] = -aim[rs][cs];
     }
+    OUT *__restrict__ V = static_cast<OUT *>(job.vis) + (size_t)c * ((size_t)S * (S + 1) / 2) * 4;
+    if (!job.accumulate) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int rs = t >> 1, cs = t & 1;
+            if (run[rs][cs])
+                store_tile_direct<acc_t, OUT, false>(V, S, are[rs][cs], aim[rs][cs], I0 * 2 + rrow[rs],
+                                                     J0 * 2 + ccol[cs], lane, [](int) { return uint4{}; });
+        }
+        return;
+    }
+    // Accumulate mode, one tile at a time: the tile's old values are loaded
+    // together, then added and stored.  (Fetching all tiles' old values at
+    // once, two of them into the free stages, measured no faster.)
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
         const int rs = t >> 1, cs = t & 1;
-        if (run[rs][cs])
-            store_tile_direct<acc_t, OUT>(job, c, are[rs][cs], aim[rs][cs], I0 * 2 + rrow[rs], J0 * 2 + ccol[cs],
-                                          lane);
+        if (!run[rs][cs]) continue;
+        const int row0 = I0 * 2 + rrow[rs], col0 = J0 * 2 + ccol[cs];
+        uint4 old[8];
+        tile_pieces(S, row0, col0, lane, [&](int k, uint32_t e) { old[k] = *reinterpret_cast<const uint4 *>(V + e); });
+        store_tile_direct<acc_t, OUT, true>(V, S, are[rs][cs], aim[rs][cs], row0, col0, lane,
+                                            [&](int k) { return old[k]; });
     }
 }
 
