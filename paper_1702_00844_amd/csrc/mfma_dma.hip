@@ -186,12 +186,14 @@ __device__ __forceinline__ void tile_pieces(int S, int row0, int col0, int lane,
 // 16 baselines, 512 contiguous bytes: eight 16-byte stores per lane and tile,
 // no LDS.  Autocorrelations (i = j) are made Hermitian on the way: XX and YY
 // get imaginary part 0 and the p = 1 lane writes YX = conj(XY), XY coming
-// from its p = 0 neighbour.  In accumulate mode old(k) gives the old value of
-// the lane's k-th 16 bytes, loaded beforehand (tile_pieces gives their
-// offsets), so that a tile's eight loads are in flight together.
-template <typename ACC, typename OUT, bool ACCUMULATE, typename OLD>
+// from its p = 0 neighbour.  off(k, i, j, p) gives the element offset of the
+// lane's k-th 16 bytes (baseline (i, j), pol p); in accumulate mode old(k)
+// gives their old value, loaded beforehand at the offsets tile_pieces lists
+// (and kept for the stores), so that a tile's eight loads are in flight
+// together.
+template <typename ACC, typename OUT, bool ACCUMULATE, typename OLD, typename OFF>
 __device__ __forceinline__ void store_tile_direct(OUT *__restrict__ V, int S, const ACC &re, const ACC &im, int row0,
-                                                  int col0, int lane, OLD old) {
+                                                  int col0, int lane, OLD old, OFF off) {
     const int m = lane & 31;
     const int i = (row0 >> 1) + (m >> 1);
     const int p = m & 1;
@@ -220,7 +222,7 @@ __device__ __forceinline__ void store_tile_direct(OUT *__restrict__ V, int S, co
         uint4 w = make_uint4(__builtin_bit_cast(uint32_t, v0.x), __builtin_bit_cast(uint32_t, v0.y),
                              __builtin_bit_cast(uint32_t, v1.x), __builtin_bit_cast(uint32_t, v1.y));
         if constexpr (ACCUMULATE) w = Vec<OUT>::add(w, old(k));
-        if (jj < S && i <= jj) *reinterpret_cast<uint4 *>(V + piece(S, i, jj, p)) = w;
+        if (jj < S && i <= jj) *reinterpret_cast<uint4 *>(V + off(k, i, jj, p)) = w;
     }
 }
 
@@ -472,8 +474,9 @@ __device__ __forceinline__ void unit(const Job &job, int c, int bi, int bj, uint
         for (int t = 0; t < 4; ++t) {
             const int rs = t >> 1, cs = t & 1;
             if (run[rs][cs])
-                store_tile_direct<acc_t, OUT, false>(V, S, are[rs][cs], aim[rs][cs], I0 * 2 + rrow[rs],
-                                                     J0 * 2 + ccol[cs], lane, [](int) { return uint4{}; });
+                store_tile_direct<acc_t, OUT, false>(
+                    V, S, are[rs][cs], aim[rs][cs], I0 * 2 + rrow[rs], J0 * 2 + ccol[cs], lane,
+                    [](int) { return uint4{}; }, [&](int, int i, int j, int p) { return piece(S, i, j, p); });
         }
         return;
     }
@@ -486,9 +489,13 @@ __device__ __forceinline__ void unit(const Job &job, int c, int bi, int bj, uint
         if (!run[rs][cs]) continue;
         const int row0 = I0 * 2 + rrow[rs], col0 = J0 * 2 + ccol[cs];
         uint4 old[8];
-        tile_pieces(S, row0, col0, lane, [&](int k, uint32_t e) { old[k] = *reinterpret_cast<const uint4 *>(V + e); });
+        uint32_t e[8];
+        tile_pieces(S, row0, col0, lane, [&](int k, uint32_t ek) {
+            e[k] = ek;
+            old[k] = *reinterpret_cast<const uint4 *>(V + ek);
+        });
         store_tile_direct<acc_t, OUT, true>(V, S, are[rs][cs], aim[rs][cs], row0, col0, lane,
-                                            [&](int k) { return old[k]; });
+                                            [&](int k) { return old[k]; }, [&](int k, int, int, int) { return e[k]; });
     }
 }
 
