@@ -241,6 +241,38 @@ def test_accumulate_int_exact(S):
     assert np.array_equal(gpu_vis_numpy(v), oracle_vis(torch.cat([x1, x2], dim=1)))
 
 
+@pytest.mark.parametrize("S", [71, 132])
+@pytest.mark.parametrize("kind", ["ci8_ci32", "ci8_cf32", "f16", "bf16"])
+def test_direct_store_accumulate_exact(kind, S):
+    """Accumulate mode of the int8 and 16-bit kernel that copies straight into
+    LDS and stores tiles from its accumulators (two calls into one output),
+    on integer-valued samples so that every sum is exact in the output type
+    (at most 320 x 2 x 127^2 < 2^24): bit for bit the oracle's result over the
+    concatenated integration.  S = 71 is one full and one partial 64-station
+    block (copied in 4-byte words for both sample types); S = 132 is two full
+    blocks and a four-station edge block (16-byte copies), with off-diagonal
+    pairs."""
+    C, T = 2, 160
+    x1 = inputs.ci8_gaussian(C, T, S, seed=41, device=DEV)
+    x2 = inputs.ci8_gaussian(C, T, S, seed=42, device=DEV)
+    cfg = dict(kernel=xe.XC_KERNEL_MFMA, block=64, staging=xe.XC_STAGING_LDS)
+    if kind in ("f16", "bf16"):
+        dt = torch.float16 if kind == "f16" else torch.bfloat16
+        a, b, out_type = x1.to(dt), x2.to(dt), None          # |v| <= 127: exact in both
+    else:
+        a, b = x1, x2
+        out_type = xe.XC_OUT_CI32 if kind == "ci8_ci32" else xe.XC_OUT_CF32
+    v = xe.correlate(a, config=cfg, out_type=out_type)
+    xe.correlate(b, out=v, accumulate=True, config=cfg)
+    torch.cuda.synchronize()
+    ref = oracle_vis(torch.cat([x1, x2], dim=1))
+    got = gpu_vis_numpy(v)
+    if kind == "ci8_ci32":
+        assert np.array_equal(got, ref)
+    else:
+        assert np.array_equal(got, ref[..., 0] + 1j * ref[..., 1])
+
+
 @pytest.mark.parametrize("S", [9, 12])
 def test_int32_worst_case(S):
     """All samples (127, -127): V = 2 * 127^2 * T exactly, at a ragged T."""
